@@ -1,0 +1,278 @@
+/*
+ * pm.h -- C-ABI of the MI355X particle-mesh hot path (libpm.so).
+ *
+ * Li et al., "Differentiable Cosmological Simulation with the Adjoint Method"
+ * (arXiv:2211.09815): the particle-mesh force (Sec. 2.2), its vector-Jacobian
+ * product (Sec. 4.2), the FastPM kick-drift-kick leapfrog (Sec. 2.3,
+ * eq. KDFK) and its adjoint with reverse-time integration (Sec. 4.2,
+ * eqs. KDFKO_adj and KDFKO_grad), the 2LPT initial conditions (Sec. 2.1,
+ * eq. lpt) and the final-density objective of Sec. 5.2.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Return value: PM_OK (0) or a negative PM_E* code.  Arguments are checked
+ *    before anything is launched; no call aborts, throws or exits.  The text
+ *    of the last error of a plan is returned by pm_last_error(plan)
+ *    (pm_last_error(NULL) gives the last plan-creation error of the calling
+ *    thread).
+ *  - Units: positions, displacements and momenta are in mesh cells, time in
+ *    1/H0 (H0 = 1).  The force coefficient `coef` is 1.5 * Omega_m (the
+ *    Poisson equation for phi~ = a phi, Sec. 2.2).
+ *  - Particles: N_p = ptcl[0]*ptcl[1]*ptcl[2] in row-major lattice order.
+ *    Particle n = (i*ptcl[1] + j)*ptcl[2] + k sits at the Lagrangian position
+ *    q = (i, j, k) * r + lattice_offset with r[a] = mesh[a] / ptcl[a]; only
+ *    its displacement s is stored (x = q + s, Sec. 2.1).  Per-particle
+ *    vectors are structure-of-arrays [3][N_p] (all x components first).
+ *  - Mesh: real fields [mesh[0]][mesh[1]][mesh[2]] in C order (last index
+ *    contiguous); half spectra [mesh[0]][mesh[1]][mesh[2]/2 + 1] of
+ *    interleaved complex numbers (re, im), exactly numpy's rfftn layout.
+ *  - Types: "state" arrays (displacement s, momentum p) have
+ *    cfg.state_dtype; mesh fields, spectra, accelerations, weights and the
+ *    adjoint variables (xi, pi, alpha) have cfg.mesh_dtype.
+ *  - Ownership: the caller owns every pointer argument; all pointers except
+ *    host-struct arguments are DEVICE pointers on the plan's device.  The
+ *    plan owns only its scratch (meshes, spectra, twiddles, reduction space),
+ *    allocated once in pm_plan_create and sized by pm_workspace_bytes.  Hot
+ *    calls allocate nothing.
+ *  - Streams: every call is asynchronous on the given stream (0 = default).
+ *    Scalars reported on the device (J, coef_bar, theta_bar) are ready after
+ *    the stream is synchronised.  A plan is not thread-safe; calls made with
+ *    one plan on different streams must be ordered by the caller.
+ *  - Determinism: with cfg.deterministic = 0 the paint accumulates with
+ *    floating-point atomics, so results differ between runs at the rounding
+ *    level (the paper's Table rep discusses the same effect on GPUs).  With
+ *    cfg.deterministic = 1 the paint accumulates in 64-bit fixed point and
+ *    every call is bitwise reproducible.
+ */
+#ifndef PM_H
+#define PM_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define PM_OK            0
+#define PM_EINVAL       -1   /* bad argument value or NULL pointer           */
+#define PM_ESHAPE       -2   /* mesh or lattice shape not supported          */
+#define PM_ENOMEM       -3   /* device allocation failed (plan creation)     */
+#define PM_EDEVICE      -4   /* a HIP call failed                            */
+#define PM_EUNSUPPORTED -5   /* valid but not implemented combination        */
+#define PM_ENONFINITE   -6   /* NaN/Inf found by pm_check_finite             */
+
+#define PM_F32 0
+#define PM_F64 1
+
+/* ---- plan -------------------------------------------------------------- */
+typedef struct pm_plan_s* pm_plan;
+
+typedef struct {
+    int32_t mesh[3];        /* mesh cells per axis: powers of two, 4..1024     */
+    int32_t ptcl[3];        /* particle lattice per axis (>= 1); for pm_lpt    */
+                            /* and pm_lpt_vjp a cube with a power-of-two side  */
+    double  box[3];         /* box side in Mpc/h (only pm_lpt/pm_lpt_vjp use it) */
+    double  lattice_offset; /* offset of the lattice in mesh cells (all axes)  */
+    int32_t mesh_dtype;     /* PM_F32 or PM_F64: mesh, FFT, force, adjoint     */
+    int32_t state_dtype;    /* PM_F32 or PM_F64: s and p accumulators          */
+    int32_t deterministic;  /* 1: fixed-point paint, bitwise reproducible      */
+} pm_config;
+
+/* Creates a plan on the current HIP device and allocates its scratch.
+ * Errors: PM_EINVAL (NULL), PM_ESHAPE (mesh not a power of two in 4..1024,
+ * ptcl < 1), PM_EUNSUPPORTED (mesh_dtype F32 with state_dtype F64 is allowed;
+ * mesh F64 with state F32 is not), PM_ENOMEM, PM_EDEVICE. */
+int pm_plan_create(const pm_config* cfg, pm_plan* out);
+int pm_plan_destroy(pm_plan plan);
+/* Bytes of device scratch pm_plan_create allocates for cfg (0 if invalid). */
+size_t pm_workspace_bytes(const pm_config* cfg);
+const char* pm_last_error(pm_plan plan);
+const char* pm_strerror(int code);
+
+/* ---- a3: CIC paint (Sec. 2.2, eq. cic) --------------------------------- */
+/* mesh[c][cell] = sum_n w_c(n) W(cell, q_n + disp_n) for c < nch, with the
+ * trilinear weight W of eq. cic (base node floor(x), periodic wrap).
+ * disp: [3][N_p] state dtype.  weights: [nch][N_p] mesh dtype, or NULL for
+ * unit mass (then nch must be 1).  mesh: [nch][N_c] mesh dtype, overwritten.
+ * 1 <= nch <= 4. */
+int pm_paint(pm_plan plan, const void* disp, const void* weights, int nch,
+             void* mesh, hipStream_t stream);
+
+/* ---- a4/a6: 3-D real FFT on the mesh (Sec. 2.2) ------------------------ */
+/* dir = +1: R2C, out(k) = sum_x in(x) exp(-i k.x) (unnormalised), in: batch
+ * real fields, out: batch half spectra.  dir = -1: C2R, out(x) = (1/N_c)
+ * sum_k in(k) exp(+i k.x) over the Hermitian completion of the half
+ * spectrum (the imaginary parts on the kz = 0 and kz = N/2 planes are
+ * ignored, as numpy's irfftn does); `in` is used as scratch and destroyed.
+ * in and out must not overlap.  1 <= batch <= 4. */
+int pm_fft(pm_plan plan, int dir, void* in, void* out, int batch, hipStream_t stream);
+
+/* ---- a5: Poisson gradient (Sec. 2.2) ----------------------------------- */
+/* grad_k[j](k) = T_j(k) delta_k(k), T_j = i k_j coef / k^2, k_j = 2 pi m_j /
+ * mesh[j]; zero at k = 0 and on the Nyquist plane of axis j (so that each
+ * operator is real and exactly anti-self-adjoint).  delta_k: one half
+ * spectrum; grad_k: [3] half spectra (must not overlap delta_k). */
+int pm_poisson_grad(pm_plan plan, const void* delta_k, void* grad_k, double coef,
+                    hipStream_t stream);
+
+/* ---- a7: CIC readout (Sec. 2.2) ---------------------------------------- */
+/* out[c][n] = sum_cell W(cell, q_n + disp_n) mesh[c][cell], the same weights
+ * as pm_paint.  mesh: [nch][N_c], out: [nch][N_p], 1 <= nch <= 4. */
+int pm_readout(pm_plan plan, const void* disp, const void* mesh, int nch, void* out,
+               hipStream_t stream);
+
+/* ---- a3..a7 composed: PM force ----------------------------------------- */
+/* acc = -grad phi~ at the particles: paint, delta = rho N_c/N_p - 1, R2C,
+ * Poisson gradient, 3 C2R, readout.  acc: [3][N_p] mesh dtype. */
+int pm_force(pm_plan plan, const void* disp, double coef, void* acc, hipStream_t stream);
+
+/* ---- a8: force VJP (Sec. 4.2; scatter/gather VJPs) ---------------------- */
+/* For cotangent acc_bar [3][N_p] of the accelerations:
+ *   disp_bar[k][n] = sum_j acc_bar[j][n] d a_j(n) / d x_k(n') summed over n'
+ *                    (the VJP with respect to all particle positions),
+ *   *coef_bar     += sum_{n,j} acc_bar[j][n] a_j(n) / coef   (device double),
+ *   acc_out        = a (optional, may be NULL).
+ * disp_bar: [3][N_p] mesh dtype, overwritten. */
+int pm_force_vjp(pm_plan plan, const void* disp, const void* acc_bar, double coef,
+                 void* disp_bar, double* coef_bar, void* acc_out, hipStream_t stream);
+
+/* ---- a1: step coefficients and KDK steps (Sec. 2.3, eq. KDFK) ------------ */
+/* Step i (1-based) goes from a_{i-1} to a_i through a_{i-1/2}:
+ *   Ka = K(t_{i-1}, t_{i-1}, t_{i-1/2}),  D = D(t_{i-1/2}, t_{i-1}, t_i),
+ *   Kb = K(t_i, t_{i-1/2}, t_i), and their derivatives with respect to
+ *   Omega_m (dKa, dD, dKb). */
+typedef struct { double Ka, D, Kb, dKa, dD, dKb; } pm_step_coef;
+
+typedef struct {
+    void* s;     /* [3][N_p] state dtype, displacement (in/out)              */
+    void* p;     /* [3][N_p] state dtype, momentum (in/out)                  */
+    void* acc;   /* [3][N_p] mesh dtype, force cache a_n (optional)          */
+} pm_state;
+
+typedef struct {
+    void* xi;    /* [3][N_p] mesh dtype, adjoint of x (in/out)               */
+    void* pi;    /* [3][N_p] mesh dtype, adjoint of p (in/out)               */
+} pm_adj;
+
+/* Forward start: a_0 = F(x_0); p <- p_0 + a_0 first->Ka.
+ * In: (s_0, p_0).  Out: (s_0, p_{1/2}). */
+int pm_fwd_init(pm_plan plan, pm_state* st, const pm_step_coef* first, double coef,
+                hipStream_t stream);
+
+/* Forward step i with merged kicks:
+ *   s_i = s_{i-1} + p_{i-1/2} D_i;  a_i = F(x_i);
+ *   p  <- p_{i-1/2} + a_i (Kb_i + next->Ka)     (next = step i+1)
+ * or, with next == NULL (last step), p_n = p_{n-1/2} + a_n Kb_n and a_n is
+ * stored in st->acc when st->acc != NULL.
+ * In: (s_{i-1}, p_{i-1/2}).  Out: (s_i, p_{i+1/2}) or (s_n, p_n). */
+int pm_step_fwd(pm_plan plan, pm_state* st, const pm_step_coef* cur,
+                const pm_step_coef* next, double coef, hipStream_t stream);
+
+/* ---- a9/a10: adjoint with reverse-time integration (eq. KDFKO_adj) ------ */
+/* theta_bar: device double[2], accumulated (+=): [0] dJ/dOmega_m, [1]
+ * dJ/dsigma8 (the steps only touch [0]; coef must equal 1.5 Omega_m). */
+
+/* Reverse start at t_n.  In: (s_n, p_n, acc = a_n or NULL to recompute),
+ * (xi_n, pi_n).  Computes alpha_n, zeta_n = pi_n . da/d(x, Omega_m) at x_n,
+ * then the kick back:  p <- p_n - a_n Kb_n,  xi <- xi_n + alpha_n Kb_n,
+ * theta_bar[0] += (pi_n . a_n) dKb_n + zeta_n Kb_n.
+ * Out: (s_n, p_{n-1/2}), (xi_{n-1/2}, pi_n). */
+int pm_adj_init(pm_plan plan, pm_state* st, pm_adj* adj, const pm_step_coef* last,
+                double coef, double* theta_bar, hipStream_t stream);
+
+/* Reverse step i (i = n..1) with merged kicks:
+ *   theta_bar[0] += (xi_{i-1/2} . p_{i-1/2}) dD_i
+ *   s_{i-1} = s_i - p_{i-1/2} D_i;   pi_{i-1} = pi_i + xi_{i-1/2} D_i
+ *   a, alpha, zeta at x_{i-1} (force and its VJP with cotangent pi_{i-1})
+ *   K = Ka_i + prev->Kb (prev = step i-1), or Ka_i when prev == NULL
+ *   p <- p - a K;   xi <- xi + alpha K
+ *   theta_bar[0] += (pi_{i-1} . a)(dKa_i + prev->dKb) + zeta K
+ * In: (s_i, p_{i-1/2}), (xi_{i-1/2}, pi_i).
+ * Out: (s_{i-1}, p_{i-3/2}), (xi_{i-3/2}, pi_{i-1}), or at i = 1
+ * (s_0, p_0), (xi_0, pi_0). */
+int pm_step_adj(pm_plan plan, pm_state* st, pm_adj* adj, const pm_step_coef* cur,
+                const pm_step_coef* prev, double coef, double* theta_bar,
+                hipStream_t stream);
+
+/* Whole loops (native drivers of the two calls above).  coefs: host array of
+ * n steps.  pm_run_fwd = pm_fwd_init + n x pm_step_fwd;  pm_run_adj =
+ * pm_adj_init + n x pm_step_adj (reverse order). */
+int pm_run_fwd(pm_plan plan, pm_state* st, const pm_step_coef* coefs, int n, double coef,
+               hipStream_t stream);
+int pm_run_adj(pm_plan plan, pm_state* st, pm_adj* adj, const pm_step_coef* coefs, int n,
+               double coef, double* theta_bar, hipStream_t stream);
+
+/* ---- a11: objective and its VJP (Sec. 5.2) ------------------------------- */
+/* delta = paint(x) N_c/N_p - 1; *J = (1/N_c) sum (delta - target)^2 (device
+ * double, overwritten); disp_bar[k][n] = sum_cell dW/dx_k (2 (delta -
+ * target)/N_p) (mesh dtype, overwritten; may be NULL). target: [N_c] mesh
+ * dtype. */
+int pm_density_mse(pm_plan plan, const void* disp, const void* target, double* J,
+                   void* disp_bar, hipStream_t stream);
+
+/* Density contrast of a unit-mass paint: delta = paint(x) N_c/N_p - 1
+ * (the field the objective compares; [N_c] mesh dtype, overwritten). */
+int pm_density(pm_plan plan, const void* disp, void* delta, hipStream_t stream);
+
+/* ---- support: cosmology tables (Appendix A, eqs. G_eval and Plin) --------- */
+typedef struct {
+    double omega_m, omega_b, h, n_s, sigma8, t_cmb;
+} pm_cosmo;
+
+/* Initial-condition factors at a_0: D1, D2 and P_m = a^2 E D_m' (momentum),
+ * the amplitude A of P_lin(k) = A k^n_s T^2(k) (normalised to sigma8 at a=1),
+ * each with its derivative with respect to Omega_m. */
+typedef struct {
+    double D1, D2, P1, P2, A;
+    double dD1, dD2, dP1, dP2, dA;
+} pm_ic_coef;
+
+/* Host-only, FP64: growth ODEs in suppression-factor form (Appendix A),
+ * G_D, G_K (eq. G_eval), the step coefficients of n steps on a_grid[0..n]
+ * (midpoint half steps) with d/dOmega_m, and the IC factors at a_grid[0].
+ * Either output may be NULL.  Flat LambdaCDM, H0 = 1. */
+int pm_tables(const pm_cosmo* cosmo, const double* a_grid, int n, pm_step_coef* coefs,
+              pm_ic_coef* ic);
+
+/* ---- s1/s2: 2LPT initial conditions and VJP (Sec. 2.1, eq. lpt) ---------- */
+/* omega: white noise on the ptcl^3 lattice ([N_p] mesh dtype, C order).
+ * delta1 = irfft(sqrt(P(k)/V_cell) rfft(omega)), V_cell = (box/ptcl)^3;
+ * s1 = -grad phi1, s2 = -grad phi2 with lattice spectral derivatives;
+ * st->s = r (D1 s1 + D2 s2), st->p = r (P1 s1 + P2 s2) (state dtype). */
+int pm_lpt(pm_plan plan, const void* omega, const pm_cosmo* cosmo, const pm_ic_coef* ic,
+           pm_state* st, hipStream_t stream);
+
+/* Transpose of pm_lpt: omega_bar = d<xi0, s_0> + <pi0, p_0> / d omega
+ * ([N_p] mesh dtype, overwritten); theta_bar[0] += the Omega_m derivative
+ * through P(k) and the time factors, theta_bar[1] += the sigma8 derivative.
+ * xi0, pi0: adj->xi, adj->pi. */
+int pm_lpt_vjp(pm_plan plan, const void* omega, const pm_cosmo* cosmo,
+               const pm_ic_coef* ic, const pm_adj* adj, void* omega_bar,
+               double* theta_bar, hipStream_t stream);
+
+/* ---- support: health check and timing ------------------------------------ */
+/* Sets *bad (device int) to 1 if any of n values of dtype in `x` is NaN or
+ * Inf (else leaves it).  Returns PM_OK; the caller reads *bad after sync. */
+int pm_check_finite(pm_plan plan, const void* x, int64_t n, int dtype, int* bad,
+                    hipStream_t stream);
+
+/* Kernel timing: while enabled, every launch of the kernel family `kernel`
+ * (PM_K_* below) is bracketed by HIP events on its stream; pm_timing_read
+ * synchronises those events and returns the summed milliseconds and the
+ * number of launches since the last reset. */
+#define PM_K_PAINT     1
+#define PM_K_FFT_R2C_Z 2
+#define PM_K_FFT_C2R_Z 3
+#define PM_K_FFT_LINES 4
+#define PM_K_FFT_POISSON 5
+#define PM_K_GATHER    6
+int pm_timing_enable(pm_plan plan, int kernel, int on);
+int pm_timing_read(pm_plan plan, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PM_H */

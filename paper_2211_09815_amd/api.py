@@ -1,0 +1,307 @@
+"""Thin Python binding of libpm (same names as include/pm.h).
+
+Argument marshalling only: each method checks tensor device, dtype, shape and
+contiguity, then passes raw device pointers and the current HIP stream to
+the C-ABI.  Every computation happens in the library's kernels.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import PmAdj, PmConfig, PmCosmo, PmIcCoef, PmState, PmStepCoef, check, lib
+
+_TORCH_DT = {_lib.PM_F32: torch.float32, _lib.PM_F64: torch.float64}
+_CPLX_DT = {_lib.PM_F32: torch.complex64, _lib.PM_F64: torch.complex128}
+
+
+def _code(dtype):
+    if dtype in (torch.float32, "f32", "float32", np.float32):
+        return _lib.PM_F32
+    if dtype in (torch.float64, "f64", "float64", np.float64):
+        return _lib.PM_F64
+    raise ValueError("dtype must be float32 or float64, got %r" % (dtype,))
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def step_coef(row):
+    """pm_step_coef from (Ka, D, Kb, dKa, dD, dKb)."""
+    return PmStepCoef(*[float(v) for v in row])
+
+
+class Cosmology:
+    """theta = (Omega_m, sigma8) with Omega_b, h, n_s, T_cmb held fixed."""
+
+    def __init__(self, omega_m=0.3, sigma8=0.8, omega_b=0.05, h=0.7, n_s=0.96, t_cmb=2.7255):
+        self.omega_m, self.sigma8, self.omega_b = omega_m, sigma8, omega_b
+        self.h, self.n_s, self.t_cmb = h, n_s, t_cmb
+
+    def c_struct(self):
+        return PmCosmo(self.omega_m, self.omega_b, self.h, self.n_s, self.sigma8, self.t_cmb)
+
+    def replace(self, **kw):
+        d = dict(omega_m=self.omega_m, sigma8=self.sigma8, omega_b=self.omega_b, h=self.h,
+                 n_s=self.n_s, t_cmb=self.t_cmb)
+        d.update(kw)
+        return Cosmology(**d)
+
+
+def tables(cosmo, a_grid):
+    """Host FP64 tables (pm_tables): step coefficients (n, 6) as
+    (Ka, D, Kb, dKa, dD, dKb) and the IC factors at a_grid[0] as a dict."""
+    a = np.ascontiguousarray(np.asarray(a_grid, dtype=np.float64))
+    n = len(a) - 1
+    coefs = (PmStepCoef * max(n, 1))()
+    ic = PmIcCoef()
+    check(lib().pm_tables(ctypes.byref(cosmo.c_struct()), a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n,
+                          coefs if n > 0 else None, ctypes.byref(ic)))
+    arr = np.array([[c.Ka, c.D, c.Kb, c.dKa, c.dD, c.dKb] for c in coefs[:n]], dtype=np.float64).reshape(n, 6)
+    icd = {f: getattr(ic, f) for f, _ in PmIcCoef._fields_}
+    return arr, icd
+
+
+def ic_struct(icd):
+    return PmIcCoef(*[float(icd[f]) for f, _ in PmIcCoef._fields_])
+
+
+class Plan:
+    """A libpm plan: mesh/lattice geometry, precision and device scratch."""
+
+    def __init__(self, mesh, ptcl, box=(1.0, 1.0, 1.0), lattice_offset=0.0, mesh_dtype=torch.float32,
+                 state_dtype=torch.float64, deterministic=False):
+        mesh = tuple(int(m) for m in (mesh if np.iterable(mesh) else (mesh,) * 3))
+        ptcl = tuple(int(m) for m in (ptcl if np.iterable(ptcl) else (ptcl,) * 3))
+        box = tuple(float(b) for b in (box if np.iterable(box) else (box,) * 3))
+        self.cfg = PmConfig((ctypes.c_int32 * 3)(*mesh), (ctypes.c_int32 * 3)(*ptcl), (ctypes.c_double * 3)(*box),
+                            float(lattice_offset), _code(mesh_dtype), _code(state_dtype), int(bool(deterministic)))
+        self.mesh = mesh
+        self.ptcl = ptcl
+        self.box = box
+        self.n_particles = ptcl[0] * ptcl[1] * ptcl[2]
+        self.n_cells = mesh[0] * mesh[1] * mesh[2]
+        self.spec_shape = (mesh[0], mesh[1], mesh[2] // 2 + 1)
+        self.mdt = _TORCH_DT[self.cfg.mesh_dtype]
+        self.sdt = _TORCH_DT[self.cfg.state_dtype]
+        self.cdt = _CPLX_DT[self.cfg.mesh_dtype]
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        h = ctypes.c_void_p()
+        check(lib().pm_plan_create(ctypes.byref(self.cfg), ctypes.byref(h)))
+        self._h = h
+        self._dev_scalars = torch.zeros(4, dtype=torch.float64, device=self.device)
+
+    @staticmethod
+    def workspace_bytes(mesh, ptcl, mesh_dtype=torch.float32, state_dtype=torch.float64):
+        cfg = PmConfig((ctypes.c_int32 * 3)(*mesh), (ctypes.c_int32 * 3)(*ptcl), (ctypes.c_double * 3)(1, 1, 1),
+                       0.0, _code(mesh_dtype), _code(state_dtype), 0)
+        return lib().pm_workspace_bytes(ctypes.byref(cfg))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- tensor checks ----------------------------------------------------
+    def _t(self, t, dtype, numel, name):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError("%s must be a torch tensor" % name)
+        if t.device.type != "cuda":
+            raise ValueError("%s must be on the GPU" % name)
+        if t.dtype != dtype:
+            raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        if numel is not None and t.numel() != numel:
+            raise ValueError("%s must have %d elements, got %d" % (name, numel, t.numel()))
+        return t
+
+    def _disp(self, disp):
+        return self._t(disp, self.sdt, 3 * self.n_particles, "disp")
+
+    def _c(self, rc):
+        return check(rc, self._h)
+
+    # ---- hot path ----------------------------------------------------------
+    def paint(self, disp, weights=None, out=None):
+        """CIC paint (pm_paint): (nch, n0, n1, n2) mesh, unit mass if weights is None."""
+        self._disp(disp)
+        nch = 1 if weights is None else weights.numel() // self.n_particles
+        if weights is not None:
+            self._t(weights, self.mdt, nch * self.n_particles, "weights")
+        if out is None:
+            out = torch.empty((nch,) + self.mesh, dtype=self.mdt, device=self.device)
+        self._t(out, self.mdt, nch * self.n_cells, "out")
+        self._c(lib().pm_paint(self._h, _ptr(disp), _ptr(weights), nch, _ptr(out), _stream()))
+        return out
+
+    def fft_r2c(self, x, out=None):
+        """R2C (pm_fft dir=+1) of (batch, n0, n1, n2) real -> (batch, n0, n1, n2/2+1) complex."""
+        batch = x.numel() // self.n_cells
+        self._t(x, self.mdt, batch * self.n_cells, "x")
+        if out is None:
+            out = torch.empty((batch,) + self.spec_shape, dtype=self.cdt, device=self.device)
+        self._t(out, self.cdt, batch * int(np.prod(self.spec_shape)), "out")
+        self._c(lib().pm_fft(self._h, 1, _ptr(x), _ptr(out), batch, _stream()))
+        return out
+
+    def fft_c2r(self, X, out=None, destroy_input=False):
+        """C2R (pm_fft dir=-1) with 1/N_c; the input is copied unless destroy_input."""
+        nsp = int(np.prod(self.spec_shape))
+        batch = X.numel() // nsp
+        self._t(X, self.cdt, batch * nsp, "X")
+        src = X if destroy_input else X.clone()
+        if out is None:
+            out = torch.empty((batch,) + self.mesh, dtype=self.mdt, device=self.device)
+        self._t(out, self.mdt, batch * self.n_cells, "out")
+        self._c(lib().pm_fft(self._h, -1, _ptr(src), _ptr(out), batch, _stream()))
+        return out
+
+    def poisson_grad(self, delta_k, coef, out=None):
+        nsp = int(np.prod(self.spec_shape))
+        self._t(delta_k, self.cdt, nsp, "delta_k")
+        if out is None:
+            out = torch.empty((3,) + self.spec_shape, dtype=self.cdt, device=self.device)
+        self._t(out, self.cdt, 3 * nsp, "out")
+        self._c(lib().pm_poisson_grad(self._h, _ptr(delta_k), _ptr(out), float(coef), _stream()))
+        return out
+
+    def readout(self, disp, mesh, out=None):
+        self._disp(disp)
+        nch = mesh.numel() // self.n_cells
+        self._t(mesh, self.mdt, nch * self.n_cells, "mesh")
+        if out is None:
+            out = torch.empty((nch, self.n_particles), dtype=self.mdt, device=self.device)
+        self._t(out, self.mdt, nch * self.n_particles, "out")
+        self._c(lib().pm_readout(self._h, _ptr(disp), _ptr(mesh), nch, _ptr(out), _stream()))
+        return out
+
+    def force(self, disp, coef, out=None):
+        self._disp(disp)
+        if out is None:
+            out = torch.empty((3, self.n_particles), dtype=self.mdt, device=self.device)
+        self._t(out, self.mdt, 3 * self.n_particles, "acc")
+        self._c(lib().pm_force(self._h, _ptr(disp), float(coef), _ptr(out), _stream()))
+        return out
+
+    def force_vjp(self, disp, acc_bar, coef, want_acc=True):
+        """(disp_bar, coef_bar (device FP64 scalar), acc or None)."""
+        self._disp(disp)
+        self._t(acc_bar, self.mdt, 3 * self.n_particles, "acc_bar")
+        xbar = torch.empty((3, self.n_particles), dtype=self.mdt, device=self.device)
+        acc = torch.empty_like(xbar) if want_acc else None
+        cbar = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self._c(lib().pm_force_vjp(self._h, _ptr(disp), _ptr(acc_bar), float(coef), _ptr(xbar), _ptr(cbar),
+                                   _ptr(acc), _stream()))
+        return xbar, cbar, acc
+
+    # ---- integration --------------------------------------------------------
+    def new_state(self, s, p, with_acc=True):
+        self._t(s, self.sdt, 3 * self.n_particles, "s")
+        self._t(p, self.sdt, 3 * self.n_particles, "p")
+        acc = torch.empty((3, self.n_particles), dtype=self.mdt, device=self.device) if with_acc else None
+        return {"s": s, "p": p, "acc": acc}
+
+    @staticmethod
+    def _st(state):
+        return PmState(state["s"].data_ptr(), state["p"].data_ptr(),
+                       state["acc"].data_ptr() if state.get("acc") is not None else None)
+
+    @staticmethod
+    def _adj(adj):
+        return PmAdj(adj["xi"].data_ptr(), adj["pi"].data_ptr())
+
+    def fwd_init(self, state, first, coef):
+        self._c(lib().pm_fwd_init(self._h, ctypes.byref(self._st(state)), ctypes.byref(step_coef(first)),
+                                  float(coef), _stream()))
+
+    def step_fwd(self, state, cur, nxt, coef):
+        n = ctypes.byref(step_coef(nxt)) if nxt is not None else None
+        self._c(lib().pm_step_fwd(self._h, ctypes.byref(self._st(state)), ctypes.byref(step_coef(cur)), n,
+                                  float(coef), _stream()))
+
+    def adj_init(self, state, adj, last, coef, theta_bar):
+        self._t(theta_bar, torch.float64, 2, "theta_bar")
+        self._c(lib().pm_adj_init(self._h, ctypes.byref(self._st(state)), ctypes.byref(self._adj(adj)),
+                                  ctypes.byref(step_coef(last)), float(coef), _ptr(theta_bar), _stream()))
+
+    def step_adj(self, state, adj, cur, prev, coef, theta_bar):
+        self._t(theta_bar, torch.float64, 2, "theta_bar")
+        pv = ctypes.byref(step_coef(prev)) if prev is not None else None
+        self._c(lib().pm_step_adj(self._h, ctypes.byref(self._st(state)), ctypes.byref(self._adj(adj)),
+                                  ctypes.byref(step_coef(cur)), pv, float(coef), _ptr(theta_bar), _stream()))
+
+    def _coef_array(self, coefs):
+        coefs = np.asarray(coefs, dtype=np.float64).reshape(-1, 6)
+        arr = (PmStepCoef * len(coefs))(*[step_coef(r) for r in coefs])
+        return arr, len(coefs)
+
+    def run_fwd(self, state, coefs, coef):
+        arr, n = self._coef_array(coefs)
+        self._c(lib().pm_run_fwd(self._h, ctypes.byref(self._st(state)), arr, n, float(coef), _stream()))
+
+    def run_adj(self, state, adj, coefs, coef, theta_bar):
+        self._t(theta_bar, torch.float64, 2, "theta_bar")
+        arr, n = self._coef_array(coefs)
+        self._c(lib().pm_run_adj(self._h, ctypes.byref(self._st(state)), ctypes.byref(self._adj(adj)), arr, n,
+                                 float(coef), _ptr(theta_bar), _stream()))
+
+    def density_mse(self, disp, target, want_grad=True):
+        """(J device FP64 scalar, disp_bar or None)."""
+        self._disp(disp)
+        self._t(target, self.mdt, self.n_cells, "target")
+        J = torch.zeros(1, dtype=torch.float64, device=self.device)
+        xbar = torch.empty((3, self.n_particles), dtype=self.mdt, device=self.device) if want_grad else None
+        self._c(lib().pm_density_mse(self._h, _ptr(disp), _ptr(target), _ptr(J), _ptr(xbar), _stream()))
+        return J, xbar
+
+    def density(self, disp, out=None):
+        """delta = paint(x) N_c/N_p - 1 (pm_density), shape mesh."""
+        self._disp(disp)
+        if out is None:
+            out = torch.empty(self.mesh, dtype=self.mdt, device=self.device)
+        self._t(out, self.mdt, self.n_cells, "out")
+        self._c(lib().pm_density(self._h, _ptr(disp), _ptr(out), _stream()))
+        return out
+
+    # ---- initial conditions -------------------------------------------------
+    def lpt(self, omega, cosmo, ic, state):
+        self._t(omega, self.mdt, self.n_particles, "omega")
+        self._c(lib().pm_lpt(self._h, _ptr(omega), ctypes.byref(cosmo.c_struct()), ctypes.byref(ic_struct(ic)),
+                             ctypes.byref(self._st(state)), _stream()))
+
+    def lpt_vjp(self, omega, cosmo, ic, adj, theta_bar, out=None):
+        self._t(omega, self.mdt, self.n_particles, "omega")
+        self._t(theta_bar, torch.float64, 2, "theta_bar")
+        if out is None:
+            out = torch.empty_like(omega)
+        self._c(lib().pm_lpt_vjp(self._h, _ptr(omega), ctypes.byref(cosmo.c_struct()), ctypes.byref(ic_struct(ic)),
+                                 ctypes.byref(self._adj(adj)), _ptr(out), _ptr(theta_bar), _stream()))
+        return out
+
+    # ---- support ------------------------------------------------------------
+    def check_finite(self, x):
+        bad = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self._c(lib().pm_check_finite(self._h, _ptr(x), x.numel(), _code(x.dtype), _ptr(bad), _stream()))
+        return bad
+
+    def timing_enable(self, kernel, on=True):
+        self._c(lib().pm_timing_enable(self._h, int(kernel), int(bool(on))))
+
+    def timing_read(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._c(lib().pm_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

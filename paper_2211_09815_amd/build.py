@@ -1,0 +1,75 @@
+"""Build libpm.so (the HIP/gfx950 library behind include/pm.h) in-tree.
+
+    python -m paper_2211_09815_amd.build          # or __graft_entry__.build()
+
+Every source under csrc/ is compiled with hipcc for gfx950 into _build/,
+then linked into paper_2211_09815_amd/libpm.so.  Packed FP32 instructions are
+disabled (-packed-fp32-ops); device code is compiled with -O3 and without
+fast-math.
+"""
+import os
+import shutil
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libpm.so")
+SOURCES = ["api.hip", "fft.hip", "particles.hip", "cosmo.hip", "lpt.hip"]
+ARCH = "gfx950"
+
+
+def hipcc():
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found (ROCm is required to build libpm)")
+
+
+def compile_flags():
+    return [
+        "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+        "-I" + INCLUDE, "-I" + CSRC,
+        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        "-Wall", "-Wno-unused-result", "-Wno-unused-function",
+    ]
+
+
+def _run(cmd):
+    proc = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    out = "\n".join(l for l in proc.stdout.splitlines() if "packed-fp32-ops" not in l)
+    return proc.returncode, out
+
+
+def build(verbose=False, jobs=None):
+    """Compile all sources and link libpm.so; raises RuntimeError on failure."""
+    cc = hipcc()
+    os.makedirs(BUILD, exist_ok=True)
+    jobs = jobs or min(len(SOURCES), max(1, (os.cpu_count() or 2)))
+    objs = []
+    cmds = []
+    for src in SOURCES:
+        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+        objs.append(obj)
+        cmds.append([cc] + compile_flags() + ["-c", os.path.join(CSRC, src), "-o", obj])
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(_run, cmds))
+    for cmd, (rc, out) in zip(cmds, results):
+        if verbose and out.strip():
+            print(out)
+        if rc != 0:
+            raise RuntimeError("compile failed: %s\n%s" % (" ".join(cmd), out))
+    tmp = LIB + ".tmp"
+    rc, out = _run([cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs)
+    if rc != 0:
+        raise RuntimeError("link failed:\n" + out)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

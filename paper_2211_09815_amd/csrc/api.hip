@@ -1,0 +1,646 @@
+// C-ABI entry points of libpm: plan management and the hot-path calls
+// (paint, FFT, Poisson gradient, readout, force, force VJP, KDK forward and
+// adjoint steps, density objective).  Every call validates its arguments
+// before launching and reports errors through pm_last_error.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <new>
+
+#include "pm_internal.h"
+
+using namespace pmx;
+
+namespace pmx {
+
+thread_local std::string g_create_error;
+
+int set_error(Plan* p, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (p) p->err = buf;
+  else g_create_error = buf;
+  return code;
+}
+
+void timing_begin(Plan* p, int kernel, hipStream_t s) {
+  Timing& t = p->timing;
+  if (t.kernel != kernel || !t.created) return;
+  if (t.nev + 2 > int(sizeof(t.ev) / sizeof(t.ev[0]))) return;
+  (void)hipEventRecord(t.ev[t.nev], s);
+}
+
+void timing_end(Plan* p, int kernel, hipStream_t s) {
+  Timing& t = p->timing;
+  if (t.kernel != kernel || !t.created) return;
+  if (t.nev + 2 > int(sizeof(t.ev) / sizeof(t.ev[0]))) return;
+  (void)hipEventRecord(t.ev[t.nev + 1], s);
+  t.nev += 2;
+}
+
+}  // namespace pmx
+
+namespace {
+
+bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+int validate_cfg(const pm_config* c, std::string& why) {
+  if (!c) { why = "config is NULL"; return PM_EINVAL; }
+  for (int a = 0; a < 3; ++a) {
+    if (!pow2_in(c->mesh[a], 4, 1024)) { why = "mesh sizes must be powers of two in [4, 1024]"; return PM_ESHAPE; }
+    if (c->ptcl[a] < 1) { why = "particle lattice sizes must be >= 1"; return PM_ESHAPE; }
+  }
+  if ((c->mesh_dtype != PM_F32 && c->mesh_dtype != PM_F64) || (c->state_dtype != PM_F32 && c->state_dtype != PM_F64)) {
+    why = "dtype must be PM_F32 or PM_F64";
+    return PM_EINVAL;
+  }
+  if (c->mesh_dtype == PM_F64 && c->state_dtype == PM_F32) {
+    why = "FP64 mesh with FP32 state is not supported";
+    return PM_EUNSUPPORTED;
+  }
+  if (c->deterministic != 0 && c->deterministic != 1) { why = "deterministic must be 0 or 1"; return PM_EINVAL; }
+  if (c->deterministic) { why = "deterministic (fixed-point) paint is not built yet"; return PM_EUNSUPPORTED; }
+  const int64_t np = int64_t(c->ptcl[0]) * c->ptcl[1] * c->ptcl[2];
+  if (np > (int64_t(1) << 31) * 8) { why = "too many particles"; return PM_ESHAPE; }
+  if (!std::isfinite(c->lattice_offset)) { why = "lattice_offset must be finite"; return PM_EINVAL; }
+  return PM_OK;
+}
+
+struct Sizes {
+  int64_t ncell, nspec;
+  size_t rb;
+  size_t mesh_bytes, spec_bytes, tw_bytes, part_bytes, scal_bytes;
+  size_t total() const { return mesh_bytes + spec_bytes + tw_bytes + part_bytes + scal_bytes; }
+};
+
+Sizes sizes_of(const pm_config* c) {
+  Sizes s;
+  s.ncell = int64_t(c->mesh[0]) * c->mesh[1] * c->mesh[2];
+  s.nspec = int64_t(c->mesh[0]) * c->mesh[1] * (c->mesh[2] / 2 + 1);
+  s.rb = c->mesh_dtype == PM_F64 ? 8 : 4;
+  s.mesh_bytes = size_t(4) * s.ncell * s.rb;
+  s.spec_bytes = size_t(4) * s.nspec * 2 * s.rb;
+  s.tw_bytes = size_t(kTwiddleSize) * 2 * s.rb;
+  s.part_bytes = size_t(kMaxPartials) * 4 * sizeof(double);
+  s.scal_bytes = 16 * sizeof(double);
+  return s;
+}
+
+Plan* P(pm_plan h) { return reinterpret_cast<Plan*>(h); }
+
+template <typename T>
+__global__ void k_finite(const T* x, int64_t n, int* bad) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  bool ok = true;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) ok = ok && isfinite(x[i]);
+  if (!ok) *bad = 1;
+}
+
+#define CHECK_PLAN(h)                                   \
+  Plan* p = P(h);                                       \
+  if (!p) return set_error(nullptr, PM_EINVAL, "plan is NULL")
+
+int check_ptr(Plan* p, const void* ptr, const char* name) {
+  if (!ptr) return set_error(p, PM_EINVAL, "%s is NULL", name);
+  return PM_OK;
+}
+
+int set_device(Plan* p) {
+  int cur = -1;
+  PM_HIP_CHECK(p, hipGetDevice(&cur));
+  if (cur != p->device) PM_HIP_CHECK(p, hipSetDevice(p->device));
+  return PM_OK;
+}
+
+FftShape mesh_shape(const Plan* p) { return FftShape{p->n[0], p->n[1], p->n[2]}; }
+
+template <typename T>
+T* mesh_ptr(Plan* p, int i) { return static_cast<T*>(p->mesh[i]); }
+template <typename T>
+cplx<T>* spec_ptr(Plan* p, int i) { return static_cast<cplx<T>*>(p->spec[i]); }
+
+// coefficient of the fused Poisson multiplier: coef * N_c / N_p (delta = rho N_c/N_p - 1)
+double mass_coef(const Plan* p, double coef) { return coef * double(p->ncell) / double(p->nptcl); }
+
+template <typename T>
+int force_fields(Plan* p, double coef, hipStream_t st) {
+  // mesh0 holds the painted mass; leaves g_0..2 in mesh0..2
+  const FftShape s = mesh_shape(p);
+  int rc = fft_r2c_3d<T>(p, s, mesh_ptr<T>(p, 0), spec_ptr<T>(p, 0), 1, p->ncell, p->nspec, st);
+  if (rc) return rc;
+  cplx<T>* specs[3] = {spec_ptr<T>(p, 0), spec_ptr<T>(p, 1), spec_ptr<T>(p, 2)};
+  T* outs[3] = {mesh_ptr<T>(p, 0), mesh_ptr<T>(p, 1), mesh_ptr<T>(p, 2)};
+  return fft_c2r_fused<T>(p, s, SPEC_GRAD3, specs, outs, T(mass_coef(p, coef)), st);
+}
+
+template <typename T>
+int vjp_fields(Plan* p, double coef, hipStream_t st) {
+  // mesh0..3 hold [rho, gbar_x, gbar_y, gbar_z]; leaves [g_x, g_y, g_z, rhobar]
+  const FftShape s = mesh_shape(p);
+  int rc = fft_r2c_3d<T>(p, s, mesh_ptr<T>(p, 0), spec_ptr<T>(p, 0), 4, p->ncell, p->nspec, st);
+  if (rc) return rc;
+  cplx<T>* specs[4] = {spec_ptr<T>(p, 0), spec_ptr<T>(p, 1), spec_ptr<T>(p, 2), spec_ptr<T>(p, 3)};
+  T* outs[4] = {mesh_ptr<T>(p, 0), mesh_ptr<T>(p, 1), mesh_ptr<T>(p, 2), mesh_ptr<T>(p, 3)};
+  return fft_c2r_fused<T>(p, s, SPEC_ADJ4, specs, outs, T(mass_coef(p, coef)), st);
+}
+
+int force_fields_any(Plan* p, double coef, hipStream_t st) {
+  return p->cfg.mesh_dtype == PM_F64 ? force_fields<double>(p, coef, st) : force_fields<float>(p, coef, st);
+}
+int vjp_fields_any(Plan* p, double coef, hipStream_t st) {
+  return p->cfg.mesh_dtype == PM_F64 ? vjp_fields<double>(p, coef, st) : vjp_fields<float>(p, coef, st);
+}
+
+int check_coef(Plan* p, double coef) {
+  if (!std::isfinite(coef) || coef <= 0) return set_error(p, PM_EINVAL, "coef must be finite and > 0");
+  return PM_OK;
+}
+
+int check_step(Plan* p, const pm_step_coef* c, const char* name) {
+  if (!c) return set_error(p, PM_EINVAL, "%s is NULL", name);
+  const double v[6] = {c->Ka, c->D, c->Kb, c->dKa, c->dD, c->dKb};
+  for (double x : v)
+    if (!std::isfinite(x)) return set_error(p, PM_EINVAL, "%s has a non-finite entry", name);
+  return PM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pm_strerror(int code) {
+  switch (code) {
+    case PM_OK: return "ok";
+    case PM_EINVAL: return "invalid argument";
+    case PM_ESHAPE: return "unsupported shape";
+    case PM_ENOMEM: return "device allocation failed";
+    case PM_EDEVICE: return "HIP error";
+    case PM_EUNSUPPORTED: return "unsupported configuration";
+    case PM_ENONFINITE: return "non-finite value";
+    default: return "unknown error";
+  }
+}
+
+const char* pm_last_error(pm_plan h) {
+  if (!h) return g_create_error.c_str();
+  return P(h)->err.c_str();
+}
+
+size_t pm_workspace_bytes(const pm_config* cfg) {
+  std::string why;
+  if (validate_cfg(cfg, why) != PM_OK) return 0;
+  return sizes_of(cfg).total();
+}
+
+int pm_plan_create(const pm_config* cfg, pm_plan* out) {
+  if (!out) return set_error(nullptr, PM_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  int rc = validate_cfg(cfg, why);
+  if (rc) return set_error(nullptr, rc, "%s", why.c_str());
+  Plan* p = new (std::nothrow) Plan();
+  if (!p) return set_error(nullptr, PM_ENOMEM, "host allocation failed");
+  p->cfg = *cfg;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return set_error(nullptr, PM_EDEVICE, "no HIP device");
+  }
+  for (int a = 0; a < 3; ++a) {
+    p->n[a] = cfg->mesh[a];
+    p->np[a] = cfg->ptcl[a];
+    p->r[a] = double(cfg->mesh[a]) / double(cfg->ptcl[a]);
+  }
+  p->nh = p->n[2] / 2 + 1;
+  const Sizes s = sizes_of(cfg);
+  p->ncell = s.ncell;
+  p->nspec = s.nspec;
+  p->nptcl = int64_t(p->np[0]) * p->np[1] * p->np[2];
+  p->real_bytes = s.rb;
+  void* mb = nullptr;
+  void* sb = nullptr;
+  if (hipMalloc(&mb, s.mesh_bytes) != hipSuccess || hipMalloc(&sb, s.spec_bytes) != hipSuccess ||
+      hipMalloc(&p->tw, s.tw_bytes) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&p->partials), s.part_bytes) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&p->scalars), s.scal_bytes) != hipSuccess) {
+    if (mb) (void)hipFree(mb);
+    if (sb) (void)hipFree(sb);
+    if (p->tw) (void)hipFree(p->tw);
+    if (p->partials) (void)hipFree(p->partials);
+    if (p->scalars) (void)hipFree(p->scalars);
+    (void)hipGetLastError();
+    delete p;
+    return set_error(nullptr, PM_ENOMEM, "could not allocate %zu bytes of plan scratch", s.total());
+  }
+  for (int i = 0; i < 4; ++i) {
+    p->mesh[i] = static_cast<char*>(mb) + size_t(i) * s.ncell * s.rb;
+    p->spec[i] = static_cast<char*>(sb) + size_t(i) * s.nspec * 2 * s.rb;
+  }
+  // twiddles exp(-2 pi i m / 4096), computed in double precision
+  if (s.rb == 8) {
+    Cx<double>* h = new Cx<double>[kTwiddleSize];
+    for (int m = 0; m < kTwiddleSize; ++m) {
+      const double a = -2.0 * M_PI * double(m) / double(kTwiddleSize);
+      h[m].x = std::cos(a);
+      h[m].y = std::sin(a);
+    }
+    (void)hipMemcpy(p->tw, h, s.tw_bytes, hipMemcpyHostToDevice);
+    delete[] h;
+  } else {
+    Cx<float>* h = new Cx<float>[kTwiddleSize];
+    for (int m = 0; m < kTwiddleSize; ++m) {
+      const double a = -2.0 * M_PI * double(m) / double(kTwiddleSize);
+      h[m].x = float(std::cos(a));
+      h[m].y = float(std::sin(a));
+    }
+    (void)hipMemcpy(p->tw, h, s.tw_bytes, hipMemcpyHostToDevice);
+    delete[] h;
+  }
+  (void)hipMemset(p->partials, 0, s.part_bytes);
+  (void)hipMemset(p->scalars, 0, s.scal_bytes);
+  if (hipDeviceSynchronize() != hipSuccess) {
+    (void)hipFree(mb);
+    (void)hipFree(sb);
+    (void)hipFree(p->tw);
+    (void)hipFree(p->partials);
+    (void)hipFree(p->scalars);
+    delete p;
+    return set_error(nullptr, PM_EDEVICE, "plan initialisation failed");
+  }
+  *out = reinterpret_cast<pm_plan>(p);
+  return PM_OK;
+}
+
+int pm_plan_destroy(pm_plan h) {
+  CHECK_PLAN(h);
+  (void)set_device(p);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(p->mesh[0]);
+  (void)hipFree(p->spec[0]);
+  (void)hipFree(p->tw);
+  (void)hipFree(p->partials);
+  (void)hipFree(p->scalars);
+  for (void* q : p->lreal) if (q) (void)hipFree(q);
+  for (void* q : p->lspec) if (q) (void)hipFree(q);
+  if (p->timing.created)
+    for (auto& e : p->timing.ev) (void)hipEventDestroy(e);
+  delete p;
+  return PM_OK;
+}
+
+int pm_paint(pm_plan h, const void* disp, const void* weights, int nch, void* mesh, hipStream_t st) {
+  CHECK_PLAN(h);
+  if (int rc = check_ptr(p, disp, "disp")) return rc;
+  if (int rc = check_ptr(p, mesh, "mesh")) return rc;
+  if (nch < 1 || nch > 4) return set_error(p, PM_EINVAL, "nch must be in 1..4");
+  if (!weights && nch != 1) return set_error(p, PM_EINVAL, "unit-mass paint needs nch = 1");
+  if (int rc = set_device(p)) return rc;
+  PaintArgs a{};
+  a.s = disp;
+  a.w = weights;
+  a.nw = weights ? nch : 0;
+  a.unit = weights ? 0 : 1;
+  a.mesh = mesh;
+  return paint_launch(p, DRIFT_NONE, a, st);
+}
+
+int pm_fft(pm_plan h, int dir, void* in, void* out, int batch, hipStream_t st) {
+  CHECK_PLAN(h);
+  if (int rc = check_ptr(p, in, "in")) return rc;
+  if (int rc = check_ptr(p, out, "out")) return rc;
+  if (dir != 1 && dir != -1) return set_error(p, PM_EINVAL, "dir must be +1 or -1");
+  if (batch < 1 || batch > 4) return set_error(p, PM_EINVAL, "batch must be in 1..4");
+  if (in == out) return set_error(p, PM_EINVAL, "in and out must not overlap");
+  if (int rc = set_device(p)) return rc;
+  const FftShape s = mesh_shape(p);
+  if (p->cfg.mesh_dtype == PM_F64) {
+    if (dir == 1)
+      return fft_r2c_3d<double>(p, s, static_cast<const double*>(in), static_cast<cplx<double>*>(out), batch,
+                                p->ncell, p->nspec, st);
+    return fft_c2r_3d<double>(p, s, static_cast<cplx<double>*>(in), static_cast<double*>(out), batch, p->nspec,
+                              p->ncell, 2.0 / double(p->ncell), st);
+  }
+  if (dir == 1)
+    return fft_r2c_3d<float>(p, s, static_cast<const float*>(in), static_cast<cplx<float>*>(out), batch, p->ncell,
+                             p->nspec, st);
+  return fft_c2r_3d<float>(p, s, static_cast<cplx<float>*>(in), static_cast<float*>(out), batch, p->nspec,
+                           p->ncell, float(2.0 / double(p->ncell)), st);
+}
+
+int pm_poisson_grad(pm_plan h, const void* delta_k, void* grad_k, double coef, hipStream_t st) {
+  CHECK_PLAN(h);
+  if (int rc = check_ptr(p, delta_k, "delta_k")) return rc;
+  if (int rc = check_ptr(p, grad_k, "grad_k")) return rc;
+  if (int rc = check_coef(p, coef)) return rc;
+  if (int rc = set_device(p)) return rc;
+  const FftShape s = mesh_shape(p);
+  if (p->cfg.mesh_dtype == PM_F64)
+    return poisson_grad_spec<double>(p, s, static_cast<const cplx<double>*>(delta_k),
+                                     static_cast<cplx<double>*>(grad_k), coef, st);
+  return poisson_grad_spec<float>(p, s, static_cast<const cplx<float>*>(delta_k), static_cast<cplx<float>*>(grad_k),
+                                  float(coef), st);
+}
+
+int pm_readout(pm_plan h, const void* disp, const void* mesh, int nch, void* out, hipStream_t st) {
+  CHECK_PLAN(h);
+  if (int rc = check_ptr(p, disp, "disp")) return rc;
+  if (int rc = check_ptr(p, mesh, "mesh")) return rc;
+  if (int rc = check_ptr(p, out, "out")) return rc;
+  if (nch < 1 || nch > 4) return set_error(p, PM_EINVAL, "nch must be in 1..4");
+  if (int rc = set_device(p)) return rc;
+  GatherArgs a{};
+  a.s = disp;
+  a.mesh = mesh;
+  a.nf = nch;
+  a.out = out;
+  return gather_launch(p, GATHER_PLAIN, a, st);
+}
+
+int pm_force(pm_plan h, const void* disp, double coef, void* acc, hipStream_t st) {
+  CHECK_PLAN(h);
+  if (int rc = check_ptr(p, disp, "disp")) return rc;
+  if (int rc = check_ptr(p, acc, "acc")) return rc;
+  if (int rc = check_coef(p, coef)) return rc;
+  if (int rc = set_device(p)) return rc;
+  PaintArgs pa{};
+  pa.s = disp;
+  pa.unit = 1;
+  pa.mesh = p->mesh[0];
+  if (int rc = paint_launch(p, DRIFT_NONE, pa, st)) return rc;
+  if (int rc = force_fields_any(p, coef, st)) return rc;
+  GatherArgs ga{};
+  ga.s = disp;
+  ga.mesh = p->mesh[0];
+  ga.nf = 3;
+  ga.out = acc;
+  return gather_launch(p, GATHER_PLAIN, ga, st);
+}
+
+int pm_force_vjp(pm_plan h, const void* disp, const void* acc_bar, double coef, void* disp_bar, double* coef_bar,
+                 void* acc_out, hipStream_t st) {
+  CHECK_PLAN(h);
+  if (int rc = check_ptr(p, disp, "disp")) return rc;
+  if (int rc = check_ptr(p, acc_bar, "acc_bar")) return rc;
+  if (int rc = check_ptr(p, disp_bar, "disp_bar")) return rc;
+  if (int rc = check_ptr(p, coef_bar, "coef_bar")) return rc;
+  if (int rc = check_coef(p, coef)) return rc;
+  if (int rc = set_device(p)) return rc;
+  PaintArgs pa{};
+  pa.s = disp;
+  pa.unit = 1;
+  pa.w = acc_bar;
+  pa.nw = 3;
+  pa.mesh = p->mesh[0];
+  if (int rc = paint_launch(p, DRIFT_NONE, pa, st)) return rc;
+  if (int rc = vjp_fields_any(p, coef, st)) return rc;
+  GatherArgs ga{};
+  ga.s = disp;
+  ga.mesh = p->mesh[0];
+  ga.nf = 4;
+  ga.out = disp_bar;
+  ga.acc = acc_out;
+  ga.cot = acc_bar;
+  ga.partials = p->partials;
+  if (int rc = gather_launch(p, GATHER_VJP, ga, st)) return rc;
+  const double f[4] = {0.0, 1.0 / coef, 0.0, 0.0};
+  return reduce_partials(p, blocks_for_particles(p), f, coef_bar, true, st);
+}
+
+int pm_fwd_init(pm_plan h, pm_state* stt, const pm_step_coef* first, double coef, hipStream_t st) {
+  CHECK_PLAN(h);
+  if (!stt) return set_error(p, PM_EINVAL, "state is NULL");
+  if (int rc = check_ptr(p, stt->s, "state.s")) return rc;
+  if (int rc = check_ptr(p, stt->p, "state.p")) return rc;
+  if (int rc = check_step(p, first, "first")) return rc;
+  if (int rc = check_coef(p, coef)) return rc;
+  if (int rc = set_device(p)) return rc;
+  PaintArgs pa{};
+  pa.s = stt->s;
+  pa.unit = 1;
+  pa.mesh = p->mesh[0];
+  if (int rc = paint_launch(p, DRIFT_NONE, pa, st)) return rc;
+  if (int rc = force_fields_any(p, coef, st)) return rc;
+  GatherArgs ga{};
+  ga.s = stt->s;
+  ga.mesh = p->mesh[0];
+  ga.nf = 3;
+  ga.p = stt->p;
+  ga.K = first->Ka;
+  return gather_launch(p, GATHER_KICK_FWD, ga, st);
+}
+
+int pm_step_fwd(pm_plan h, pm_state* stt, const pm_step_coef* cur, const pm_step_coef* next, double coef,
+                hipStream_t st) {
+  CHECK_PLAN(h);
+  if (!stt) return set_error(p, PM_EINVAL, "state is NULL");
+  if (int rc = check_ptr(p, stt->s, "state.s")) return rc;
+  if (int rc = check_ptr(p, stt->p, "state.p")) return rc;
+  if (int rc = check_step(p, cur, "cur")) return rc;
+  if (next)
+    if (int rc = check_step(p, next, "next")) return rc;
+  if (int rc = check_coef(p, coef)) return rc;
+  if (int rc = set_device(p)) return rc;
+  PaintArgs pa{};
+  pa.s = stt->s;
+  pa.p = stt->p;
+  pa.unit = 1;
+  pa.mesh = p->mesh[0];
+  pa.D = cur->D;
+  if (int rc = paint_launch(p, DRIFT_FWD, pa, st)) return rc;
+  if (int rc = force_fields_any(p, coef, st)) return rc;
+  GatherArgs ga{};
+  ga.s = stt->s;
+  ga.mesh = p->mesh[0];
+  ga.nf = 3;
+  ga.p = stt->p;
+  ga.K = cur->Kb + (next ? next->Ka : 0.0);
+  ga.acc = next ? nullptr : stt->acc;
+  return gather_launch(p, GATHER_KICK_FWD, ga, st);
+}
+
+int pm_adj_init(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* last, double coef, double* theta_bar,
+                hipStream_t st) {
+  CHECK_PLAN(h);
+  if (!stt || !adj) return set_error(p, PM_EINVAL, "state or adjoint is NULL");
+  if (int rc = check_ptr(p, stt->s, "state.s")) return rc;
+  if (int rc = check_ptr(p, stt->p, "state.p")) return rc;
+  if (int rc = check_ptr(p, adj->xi, "adj.xi")) return rc;
+  if (int rc = check_ptr(p, adj->pi, "adj.pi")) return rc;
+  if (int rc = check_ptr(p, theta_bar, "theta_bar")) return rc;
+  if (int rc = check_step(p, last, "last")) return rc;
+  if (int rc = check_coef(p, coef)) return rc;
+  if (int rc = set_device(p)) return rc;
+  PaintArgs pa{};
+  pa.s = stt->s;
+  pa.unit = 1;
+  pa.w = adj->pi;
+  pa.nw = 3;
+  pa.mesh = p->mesh[0];
+  if (int rc = paint_launch(p, DRIFT_NONE, pa, st)) return rc;
+  if (int rc = vjp_fields_any(p, coef, st)) return rc;
+  GatherArgs ga{};
+  ga.s = stt->s;
+  ga.mesh = p->mesh[0];
+  ga.nf = 4;
+  ga.p = stt->p;
+  ga.xi = adj->xi;
+  ga.cot = adj->pi;
+  ga.acc_in = stt->acc;
+  ga.K = last->Kb;
+  ga.partials = p->partials;
+  if (int rc = gather_launch(p, GATHER_KICK_ADJ, ga, st)) return rc;
+  // theta_bar[0] += (pi.a) dKb + zeta Kb,  zeta = (pi.a) * 1.5 / coef
+  const double f[4] = {0.0, last->dKb + last->Kb * 1.5 / coef, 0.0, 0.0};
+  return reduce_partials(p, blocks_for_particles(p), f, theta_bar, true, st);
+}
+
+int pm_step_adj(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* cur, const pm_step_coef* prev,
+                double coef, double* theta_bar, hipStream_t st) {
+  CHECK_PLAN(h);
+  if (!stt || !adj) return set_error(p, PM_EINVAL, "state or adjoint is NULL");
+  if (int rc = check_ptr(p, stt->s, "state.s")) return rc;
+  if (int rc = check_ptr(p, stt->p, "state.p")) return rc;
+  if (int rc = check_ptr(p, adj->xi, "adj.xi")) return rc;
+  if (int rc = check_ptr(p, adj->pi, "adj.pi")) return rc;
+  if (int rc = check_ptr(p, theta_bar, "theta_bar")) return rc;
+  if (int rc = check_step(p, cur, "cur")) return rc;
+  if (prev)
+    if (int rc = check_step(p, prev, "prev")) return rc;
+  if (int rc = check_coef(p, coef)) return rc;
+  if (int rc = set_device(p)) return rc;
+  PaintArgs pa{};
+  pa.s = stt->s;
+  pa.p = stt->p;
+  pa.xi = adj->xi;
+  pa.pi = adj->pi;
+  pa.unit = 1;
+  pa.nw = 3;
+  pa.mesh = p->mesh[0];
+  pa.D = cur->D;
+  pa.partials = p->partials;
+  if (int rc = paint_launch(p, DRIFT_ADJ, pa, st)) return rc;
+  if (int rc = vjp_fields_any(p, coef, st)) return rc;
+  const double K = cur->Ka + (prev ? prev->Kb : 0.0);
+  const double dK = cur->dKa + (prev ? prev->dKb : 0.0);
+  GatherArgs ga{};
+  ga.s = stt->s;
+  ga.mesh = p->mesh[0];
+  ga.nf = 4;
+  ga.p = stt->p;
+  ga.xi = adj->xi;
+  ga.cot = adj->pi;
+  ga.K = K;
+  ga.partials = p->partials;
+  if (int rc = gather_launch(p, GATHER_KICK_ADJ, ga, st)) return rc;
+  const double f[4] = {cur->dD, dK + K * 1.5 / coef, 0.0, 0.0};
+  return reduce_partials(p, blocks_for_particles(p), f, theta_bar, true, st);
+}
+
+int pm_run_fwd(pm_plan h, pm_state* stt, const pm_step_coef* coefs, int n, double coef, hipStream_t st) {
+  CHECK_PLAN(h);
+  if (!coefs || n < 1) return set_error(p, PM_EINVAL, "need n >= 1 step coefficients");
+  if (int rc = pm_fwd_init(h, stt, &coefs[0], coef, st)) return rc;
+  for (int i = 0; i < n; ++i)
+    if (int rc = pm_step_fwd(h, stt, &coefs[i], i + 1 < n ? &coefs[i + 1] : nullptr, coef, st)) return rc;
+  return PM_OK;
+}
+
+int pm_run_adj(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* coefs, int n, double coef,
+               double* theta_bar, hipStream_t st) {
+  CHECK_PLAN(h);
+  if (!coefs || n < 1) return set_error(p, PM_EINVAL, "need n >= 1 step coefficients");
+  if (int rc = pm_adj_init(h, stt, adj, &coefs[n - 1], coef, theta_bar, st)) return rc;
+  for (int i = n - 1; i >= 0; --i)
+    if (int rc = pm_step_adj(h, stt, adj, &coefs[i], i > 0 ? &coefs[i - 1] : nullptr, coef, theta_bar, st))
+      return rc;
+  return PM_OK;
+}
+
+int pm_density_mse(pm_plan h, const void* disp, const void* target, double* J, void* disp_bar, hipStream_t st) {
+  CHECK_PLAN(h);
+  if (int rc = check_ptr(p, disp, "disp")) return rc;
+  if (int rc = check_ptr(p, target, "target")) return rc;
+  if (int rc = check_ptr(p, J, "J")) return rc;
+  if (int rc = set_device(p)) return rc;
+  PaintArgs pa{};
+  pa.s = disp;
+  pa.unit = 1;
+  pa.mesh = p->mesh[0];
+  if (int rc = paint_launch(p, DRIFT_NONE, pa, st)) return rc;
+  const int nb = mse_mesh_launch(p, p->mesh[0], target, p->partials, st);
+  if (nb < 0) return nb;
+  const double f[4] = {0.0, 0.0, 1.0 / double(p->ncell), 0.0};
+  if (int rc = reduce_partials(p, nb, f, J, false, st)) return rc;
+  if (!disp_bar) return PM_OK;
+  GatherArgs ga{};
+  ga.s = disp;
+  ga.mesh = p->mesh[0];
+  ga.nf = 1;
+  ga.out = disp_bar;
+  return gather_launch(p, GATHER_MSE, ga, st);
+}
+
+int pm_density(pm_plan h, const void* disp, void* delta, hipStream_t st) {
+  CHECK_PLAN(h);
+  if (int rc = check_ptr(p, disp, "disp")) return rc;
+  if (int rc = check_ptr(p, delta, "delta")) return rc;
+  if (int rc = set_device(p)) return rc;
+  PaintArgs pa{};
+  pa.s = disp;
+  pa.unit = 1;
+  pa.mesh = delta;
+  if (int rc = paint_launch(p, DRIFT_NONE, pa, st)) return rc;
+  return contrast_launch(p, delta, st);
+}
+
+int pm_check_finite(pm_plan h, const void* x, int64_t n, int dtype, int* bad, hipStream_t st) {
+  CHECK_PLAN(h);
+  if (int rc = check_ptr(p, x, "x")) return rc;
+  if (int rc = check_ptr(p, bad, "bad")) return rc;
+  if (n < 0 || (dtype != PM_F32 && dtype != PM_F64)) return set_error(p, PM_EINVAL, "bad n or dtype");
+  if (n == 0) return PM_OK;
+  if (int rc = set_device(p)) return rc;
+  const int64_t need = (n + kThreads - 1) / kThreads;
+  const int blocks = int(need < 2048 ? need : 2048);
+  if (dtype == PM_F64)
+    hipLaunchKernelGGL((k_finite<double>), dim3(blocks), dim3(kThreads), 0, st, static_cast<const double*>(x), n, bad);
+  else
+    hipLaunchKernelGGL((k_finite<float>), dim3(blocks), dim3(kThreads), 0, st, static_cast<const float*>(x), n, bad);
+  PM_HIP_CHECK(p, hipGetLastError());
+  return PM_OK;
+}
+
+int pm_timing_enable(pm_plan h, int kernel, int on) {
+  CHECK_PLAN(h);
+  Timing& t = p->timing;
+  if (!t.created) {
+    for (auto& e : t.ev)
+      if (hipEventCreate(&e) != hipSuccess) return set_error(p, PM_EDEVICE, "hipEventCreate failed");
+    t.created = true;
+  }
+  t.kernel = on ? kernel : 0;
+  t.nev = 0;
+  t.total_ms = 0.0;
+  t.launches = 0;
+  return PM_OK;
+}
+
+int pm_timing_read(pm_plan h, double* total_ms, int64_t* launches) {
+  CHECK_PLAN(h);
+  Timing& t = p->timing;
+  for (int i = 0; i + 1 < t.nev; i += 2) {
+    float ms = 0.f;
+    PM_HIP_CHECK(p, hipEventSynchronize(t.ev[i + 1]));
+    PM_HIP_CHECK(p, hipEventElapsedTime(&ms, t.ev[i], t.ev[i + 1]));
+    t.total_ms += ms;
+    t.launches += 1;
+  }
+  t.nev = 0;
+  if (total_ms) *total_ms = t.total_ms;
+  if (launches) *launches = t.launches;
+  return PM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,206 @@
+// Internal declarations shared by the HIP sources of libpm (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "pm.h"
+
+namespace pmx {
+
+constexpr int kThreads = 256;        // threads per workgroup for all kernels
+constexpr int kTwiddleLog2 = 12;     // twiddle table exp(-2 pi i m / 4096)
+constexpr int kTwiddleSize = 1 << kTwiddleLog2;
+constexpr int kMaxPartials = 4096;   // per-block partial sums for reductions
+
+// ---------------------------------------------------------------------------
+// complex helpers
+// ---------------------------------------------------------------------------
+template <typename T> struct alignas(2 * sizeof(T)) Cx {
+  using value_type = T;
+  T x, y;
+};
+template <typename T> using cplx = Cx<T>;
+
+template <typename C> __host__ __device__ __forceinline__ C cmk(typename C::value_type re, typename C::value_type im) {
+  C c; c.x = re; c.y = im; return c;
+}
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return cmk<C>(a.x + b.x, a.y + b.y); }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return cmk<C>(a.x - b.x, a.y - b.y); }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+  return cmk<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename C> __device__ __forceinline__ C cconj(C a) { return cmk<C>(a.x, -a.y); }
+template <typename C> __device__ __forceinline__ C cscale(C a, typename C::value_type s) { return cmk<C>(a.x * s, a.y * s); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV, typename C> __device__ __forceinline__ C cmul_mi(C a) {
+  return INV ? cmk<C>(-a.y, a.x) : cmk<C>(a.y, -a.x);
+}
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+struct Timing {
+  int kernel = 0;
+  hipEvent_t ev[2 * 4096];
+  int nev = 0;
+  bool created = false;
+  double total_ms = 0.0;
+  int64_t launches = 0;
+};
+
+struct Plan {
+  pm_config cfg;
+  int device = 0;
+  int n[3];            // mesh shape
+  int nh;              // n[2]/2 + 1
+  int64_t ncell;       // n0 n1 n2
+  int64_t nspec;       // n0 n1 nh
+  int np[3];           // lattice shape
+  int64_t nptcl;
+  double r[3];         // lattice spacing in cells per axis
+  size_t real_bytes;   // bytes of one mesh-dtype scalar
+  // scratch owned by the plan
+  void* mesh[4] = {nullptr, nullptr, nullptr, nullptr};   // real meshes [ncell]
+  void* spec[4] = {nullptr, nullptr, nullptr, nullptr};   // half spectra [nspec]
+  void* tw = nullptr;                                      // twiddles (mesh dtype complex)
+  double* partials = nullptr;                              // [kMaxPartials * 4]
+  double* scalars = nullptr;                               // [16] device scalars
+  unsigned long long* fixed = nullptr;                     // deterministic paint accumulators
+  // lattice scratch for pm_lpt / pm_lpt_vjp (allocated lazily on first use)
+  void* lreal[10] = {};
+  void* lspec[2] = {};
+  bool lpt_ready = false;
+  Timing timing;
+  std::string err;
+};
+
+extern thread_local std::string g_create_error;
+
+int set_error(Plan* p, int code, const char* fmt, ...);
+
+#define PM_HIP_CHECK(plan, call)                                                   \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return pmx::set_error((plan), PM_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+// kernel-launch bracketing for the timing facility
+void timing_begin(Plan* p, int kernel, hipStream_t s);
+void timing_end(Plan* p, int kernel, hipStream_t s);
+
+inline int ilog2(int64_t v) { int l = 0; while ((int64_t(1) << l) < v) ++l; return l; }
+__host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
+
+// Map a linear workgroup id so that consecutive tiles land on the same XCD:
+// the hardware hands workgroup b to XCD b % 8, so tile (b % 8) * per + b / 8
+// gives each XCD a contiguous run of tiles (shared L2 for neighbours).
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nblocks) {
+  const int64_t nx = 8;
+  int64_t per = nblocks / nx;
+  int64_t rem = nblocks % nx;
+  int64_t x = b % nx, i = b / nx;
+  // XCDs x < rem own per + 1 tiles, the others per
+  return x * per + (x < rem ? x : rem) + i;
+}
+
+// ---------------------------------------------------------------------------
+// FFT launchers (fft.hip).  Shapes are explicit so that both the mesh and the
+// particle lattice can be transformed.  All arrays use the layouts of pm.h.
+// ---------------------------------------------------------------------------
+struct FftShape {
+  int n0, n1, n2;     // real shape, each a power of two in [4, 1024]
+};
+
+// Fused multipliers applied inside the first inverse pass along axis 0.
+enum SpecOp {
+  SPEC_NONE = 0,
+  SPEC_GRAD3 = 1,     // out_j = T_j * in0, j = 0..2 (Poisson gradient)
+  SPEC_ADJ4 = 2,      // out_0..2 = T_j * in0, out_3 = -sum_j T_j in_{1+j}
+};
+
+template <typename T>
+int fft_r2c_3d(Plan* p, const FftShape& s, const T* in, cplx<T>* out, int batch,
+               int64_t in_stride, int64_t out_stride, hipStream_t st);
+// out may alias nothing; in is destroyed (used in place for the two c2c passes)
+template <typename T>
+int fft_c2r_3d(Plan* p, const FftShape& s, cplx<T>* in, T* out, int batch,
+               int64_t in_stride, int64_t out_stride, T scale, hipStream_t st);
+// inverse with fused spectral multipliers (Poisson gradient / adjoint combine)
+template <typename T>
+int fft_c2r_fused(Plan* p, const FftShape& s, SpecOp op, cplx<T>* const* specs, T* const* outs,
+                  T coef, hipStream_t st);
+// elementwise spectral multiplies used by the standalone Poisson call
+template <typename T>
+int poisson_grad_spec(Plan* p, const FftShape& s, const cplx<T>* in, cplx<T>* out, T coef,
+                      hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// particle kernels (particles.hip)
+// ---------------------------------------------------------------------------
+enum DriftMode { DRIFT_NONE = 0, DRIFT_FWD = 1, DRIFT_ADJ = 2 };
+
+struct PaintArgs {
+  const void* s;        // [3][N] state
+  void* s_out;          // drift writes here (same as s, in place)
+  const void* p;        // momentum (drift)
+  const void* xi;       // adjoint drift
+  void* pi;             // adjoint drift (in/out)
+  const void* w;        // [nw][N] mesh-dtype weights or null
+  int nw;               // number of weighted channels
+  int unit;             // 1 if channel 0 is unit mass
+  void* mesh;           // [nch][ncell]
+  double D;             // drift coefficient
+  double* partials;     // per-block partial sum of xi.p (adjoint drift)
+};
+int paint_launch(Plan* p, DriftMode mode, const PaintArgs& a, hipStream_t st);
+
+enum GatherMode {
+  GATHER_PLAIN = 0,     // out[c] = readout(mesh[c])
+  GATHER_KICK_FWD = 1,  // a = readout(g), p += a K, optional store a
+  GATHER_VJP = 2,       // a, alpha from (g0..2, rhobar), cotangent abar; partial abar.a
+  GATHER_KICK_ADJ = 3,  // as VJP with cotangent pi, then p -= a K, xi += alpha K
+  GATHER_MSE = 4,       // xbar = sum dW (mesh0), mesh0 = 2 (delta - target)/Np
+};
+struct GatherArgs {
+  const void* s;        // [3][N] state
+  const void* mesh;     // [nf][ncell]
+  int nf;
+  void* out;            // plain: [nf][N]; VJP/MSE: xbar [3][N]
+  void* acc;            // acceleration out (optional)
+  void* p;              // kick target
+  void* xi;             // adjoint kick target
+  const void* cot;      // cotangent [3][N] (abar or pi)
+  const void* acc_in;   // cached accelerations for the adjoint kick (optional)
+  double K;
+  double* partials;     // per-block partial of cot . a
+};
+int gather_launch(Plan* p, GatherMode mode, const GatherArgs& a, hipStream_t st);
+
+// density-contrast difference for the MSE: m = 2 (rho Nc/Np - 1 - target)/Np,
+// with the per-block partial sums of (delta - target)^2
+int mse_mesh_launch(Plan* p, void* mesh, const void* target, double* partials, hipStream_t st);
+
+// mesh <- mesh N_c/N_p - 1 (density contrast of a unit-mass paint)
+int contrast_launch(Plan* p, void* mesh, hipStream_t st);
+
+// deterministic reduction of per-block partials: out[k] (+)= sum_b part[b*4+k]
+// scaled: out[o] (+)= sum_k f[k] * sum_b part[b*4+k] for up to 4 outputs
+int reduce_partials(Plan* p, int nblocks, const double* coef /*host [4]*/, double* out,
+                    bool accumulate, hipStream_t st);
+
+int blocks_for_particles(const Plan* p);
+
+// ---------------------------------------------------------------------------
+// initial conditions (lpt.hip)
+// ---------------------------------------------------------------------------
+int lpt_forward(Plan* p, const void* omega, const pm_cosmo* c, const pm_ic_coef* ic, pm_state* st,
+                hipStream_t s);
+int lpt_backward(Plan* p, const void* omega, const pm_cosmo* c, const pm_ic_coef* ic,
+                 const pm_adj* adj, void* omega_bar, double* theta_bar, hipStream_t s);
+
+}  // namespace pmx
