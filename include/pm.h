@@ -261,8 +261,10 @@ int pm_check_finite(pm_plan plan, const void* x, int64_t n, int dtype, int* bad,
 
 /* Kernel timing: while enabled, every launch of the kernel family `kernel`
  * (PM_K_* below) is bracketed by HIP events on its stream; pm_timing_read
- * synchronises those events and returns the summed milliseconds and the
- * number of launches since the last reset. */
+ * synchronises those events and returns the summed milliseconds, the number
+ * of launches and the summed algorithmic bytes (the HBM traffic each launch
+ * must at least move: inputs read once, outputs written once) since the last
+ * pm_timing_enable.  At most 4096 launches are recorded between reads. */
 #define PM_K_PAINT     1
 #define PM_K_FFT_R2C_Z 2
 #define PM_K_FFT_C2R_Z 3
@@ -270,7 +272,7 @@ int pm_check_finite(pm_plan plan, const void* x, int64_t n, int dtype, int* bad,
 #define PM_K_FFT_POISSON 5
 #define PM_K_GATHER    6
 int pm_timing_enable(pm_plan plan, int kernel, int on);
-int pm_timing_read(pm_plan plan, double* total_ms, int64_t* launches);
+int pm_timing_read(pm_plan plan, double* total_ms, int64_t* launches, double* total_bytes);
 
 #ifdef __cplusplus
 }

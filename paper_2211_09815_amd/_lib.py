@@ -89,7 +89,7 @@ _PROTOS = {
     "pm_lpt_vjp": (c_int, [c_vp, c_vp, P(PmCosmo), P(PmIcCoef), P(PmAdj), c_vp, c_vp, c_vp]),
     "pm_check_finite": (c_int, [c_vp, c_vp, c_i64, c_int, c_vp, c_vp]),
     "pm_timing_enable": (c_int, [c_vp, c_int, c_int]),
-    "pm_timing_read": (c_int, [c_vp, P(c_dbl), P(c_i64)]),
+    "pm_timing_read": (c_int, [c_vp, P(c_dbl), P(c_i64), P(c_dbl)]),
 }
 
 EXPORTED = tuple(_PROTOS.keys())

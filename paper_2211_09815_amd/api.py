@@ -301,7 +301,9 @@ class Plan:
         self._c(lib().pm_timing_enable(self._h, int(kernel), int(bool(on))))
 
     def timing_read(self):
+        """(total milliseconds, launches, total algorithmic bytes) since enable."""
         ms = ctypes.c_double()
         n = ctypes.c_int64()
-        self._c(lib().pm_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
-        return ms.value, n.value
+        b = ctypes.c_double()
+        self._c(lib().pm_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
+        return ms.value, n.value, b.value

@@ -33,11 +33,12 @@ void timing_begin(Plan* p, int kernel, hipStream_t s) {
   (void)hipEventRecord(t.ev[t.nev], s);
 }
 
-void timing_end(Plan* p, int kernel, hipStream_t s) {
+void timing_end(Plan* p, int kernel, hipStream_t s, double bytes) {
   Timing& t = p->timing;
   if (t.kernel != kernel || !t.created) return;
   if (t.nev + 2 > int(sizeof(t.ev) / sizeof(t.ev[0]))) return;
   (void)hipEventRecord(t.ev[t.nev + 1], s);
+  t.bytes[t.nev / 2] = bytes;
   t.nev += 2;
 }
 
@@ -62,18 +63,18 @@ int validate_cfg(const pm_config* c, std::string& why) {
     return PM_EUNSUPPORTED;
   }
   if (c->deterministic != 0 && c->deterministic != 1) { why = "deterministic must be 0 or 1"; return PM_EINVAL; }
-  if (c->deterministic) { why = "deterministic (fixed-point) paint is not built yet"; return PM_EUNSUPPORTED; }
   const int64_t np = int64_t(c->ptcl[0]) * c->ptcl[1] * c->ptcl[2];
-  if (np > (int64_t(1) << 31) * 8) { why = "too many particles"; return PM_ESHAPE; }
+  if (np > (int64_t(1) << 31)) { why = "at most 2^31 particles"; return PM_ESHAPE; }
   if (!std::isfinite(c->lattice_offset)) { why = "lattice_offset must be finite"; return PM_EINVAL; }
   return PM_OK;
 }
 
 struct Sizes {
-  int64_t ncell, nspec;
+  int64_t ncell, nspec, nptcl, ntiles;
+  int halo_cells;
   size_t rb;
-  size_t mesh_bytes, spec_bytes, tw_bytes, part_bytes, scal_bytes;
-  size_t total() const { return mesh_bytes + spec_bytes + tw_bytes + part_bytes + scal_bytes; }
+  size_t mesh_bytes, spec_bytes, tw_bytes, part_bytes, scal_bytes, bin_bytes;
+  size_t total() const { return mesh_bytes + spec_bytes + tw_bytes + part_bytes + scal_bytes + bin_bytes; }
 };
 
 Sizes sizes_of(const pm_config* c) {
@@ -86,6 +87,13 @@ Sizes sizes_of(const pm_config* c) {
   s.tw_bytes = size_t(kTwiddleSize) * 2 * s.rb;
   s.part_bytes = size_t(kMaxPartials) * 4 * sizeof(double);
   s.scal_bytes = 16 * sizeof(double);
+  int tile[3];
+  tile_dims(c->mesh, tile, s.ntiles, s.halo_cells);
+  s.nptcl = int64_t(c->ptcl[0]) * c->ptcl[1] * c->ptcl[2];
+  // keys, per-tile partials, halo faces, list, counts, offsets, block sums
+  s.bin_bytes = size_t(s.nptcl) * 8 + size_t(s.ntiles) * 4 * sizeof(double) +
+                size_t(4) * s.ntiles * s.halo_cells * s.rb + size_t(s.nptcl) * 4 + size_t(s.ntiles) * 4 +
+                size_t(s.ntiles + 1) * 4 + size_t(4 * kThreads) * 4;
   return s;
 }
 
@@ -219,14 +227,18 @@ int pm_plan_create(const pm_config* cfg, pm_plan* out) {
   p->nspec = s.nspec;
   p->nptcl = int64_t(p->np[0]) * p->np[1] * p->np[2];
   p->real_bytes = s.rb;
+  tile_dims(p->n, p->tile, p->ntiles, p->halo_cells);
   void* mb = nullptr;
   void* sb = nullptr;
+  void* bb = nullptr;
   if (hipMalloc(&mb, s.mesh_bytes) != hipSuccess || hipMalloc(&sb, s.spec_bytes) != hipSuccess ||
+      hipMalloc(&bb, s.bin_bytes) != hipSuccess ||
       hipMalloc(&p->tw, s.tw_bytes) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&p->partials), s.part_bytes) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&p->scalars), s.scal_bytes) != hipSuccess) {
     if (mb) (void)hipFree(mb);
     if (sb) (void)hipFree(sb);
+    if (bb) (void)hipFree(bb);
     if (p->tw) (void)hipFree(p->tw);
     if (p->partials) (void)hipFree(p->partials);
     if (p->scalars) (void)hipFree(p->scalars);
@@ -237,6 +249,22 @@ int pm_plan_create(const pm_config* cfg, pm_plan* out) {
   for (int i = 0; i < 4; ++i) {
     p->mesh[i] = static_cast<char*>(mb) + size_t(i) * s.ncell * s.rb;
     p->spec[i] = static_cast<char*>(sb) + size_t(i) * s.nspec * 2 * s.rb;
+  }
+  {
+    char* q = static_cast<char*>(bb);
+    p->bin_keys = q;  // 8-byte aligned first
+    q += size_t(s.nptcl) * 8;
+    p->tile_partials = reinterpret_cast<double*>(q);
+    q += size_t(s.ntiles) * 4 * sizeof(double);
+    p->bin_halo = q;
+    q += size_t(4) * s.ntiles * s.halo_cells * s.rb;
+    p->bin_list = reinterpret_cast<unsigned*>(q);
+    q += size_t(s.nptcl) * 4;
+    p->bin_counts = reinterpret_cast<unsigned*>(q);
+    q += size_t(s.ntiles) * 4;
+    p->bin_offs = reinterpret_cast<unsigned*>(q);
+    q += size_t(s.ntiles + 1) * 4;
+    p->bin_bsum = reinterpret_cast<unsigned*>(q);
   }
   // twiddles exp(-2 pi i m / 4096), computed in double precision
   if (s.rb == 8) {
@@ -263,6 +291,7 @@ int pm_plan_create(const pm_config* cfg, pm_plan* out) {
   if (hipDeviceSynchronize() != hipSuccess) {
     (void)hipFree(mb);
     (void)hipFree(sb);
+    (void)hipFree(bb);
     (void)hipFree(p->tw);
     (void)hipFree(p->partials);
     (void)hipFree(p->scalars);
@@ -279,6 +308,7 @@ int pm_plan_destroy(pm_plan h) {
   (void)hipDeviceSynchronize();
   (void)hipFree(p->mesh[0]);
   (void)hipFree(p->spec[0]);
+  (void)hipFree(p->bin_keys);
   (void)hipFree(p->tw);
   (void)hipFree(p->partials);
   (void)hipFree(p->scalars);
@@ -375,6 +405,7 @@ int pm_force(pm_plan h, const void* disp, double coef, void* acc, hipStream_t st
   ga.mesh = p->mesh[0];
   ga.nf = 3;
   ga.out = acc;
+  ga.binned = true;
   return gather_launch(p, GATHER_PLAIN, ga, st);
 }
 
@@ -402,10 +433,10 @@ int pm_force_vjp(pm_plan h, const void* disp, const void* acc_bar, double coef, 
   ga.out = disp_bar;
   ga.acc = acc_out;
   ga.cot = acc_bar;
-  ga.partials = p->partials;
+  ga.binned = true;
   if (int rc = gather_launch(p, GATHER_VJP, ga, st)) return rc;
   const double f[4] = {0.0, 1.0 / coef, 0.0, 0.0};
-  return reduce_partials(p, blocks_for_particles(p), f, coef_bar, true, st);
+  return reduce_buffer(p, p->tile_partials, p->ntiles, f, coef_bar, true, st);
 }
 
 int pm_fwd_init(pm_plan h, pm_state* stt, const pm_step_coef* first, double coef, hipStream_t st) {
@@ -428,6 +459,7 @@ int pm_fwd_init(pm_plan h, pm_state* stt, const pm_step_coef* first, double coef
   ga.nf = 3;
   ga.p = stt->p;
   ga.K = first->Ka;
+  ga.binned = true;
   return gather_launch(p, GATHER_KICK_FWD, ga, st);
 }
 
@@ -457,6 +489,7 @@ int pm_step_fwd(pm_plan h, pm_state* stt, const pm_step_coef* cur, const pm_step
   ga.p = stt->p;
   ga.K = cur->Kb + (next ? next->Ka : 0.0);
   ga.acc = next ? nullptr : stt->acc;
+  ga.binned = true;
   return gather_launch(p, GATHER_KICK_FWD, ga, st);
 }
 
@@ -489,11 +522,11 @@ int pm_adj_init(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* last,
   ga.cot = adj->pi;
   ga.acc_in = stt->acc;
   ga.K = last->Kb;
-  ga.partials = p->partials;
+  ga.binned = true;
   if (int rc = gather_launch(p, GATHER_KICK_ADJ, ga, st)) return rc;
   // theta_bar[0] += (pi.a) dKb + zeta Kb,  zeta = (pi.a) * 1.5 / coef
   const double f[4] = {0.0, last->dKb + last->Kb * 1.5 / coef, 0.0, 0.0};
-  return reduce_partials(p, blocks_for_particles(p), f, theta_bar, true, st);
+  return reduce_buffer(p, p->tile_partials, p->ntiles, f, theta_bar, true, st);
 }
 
 int pm_step_adj(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* cur, const pm_step_coef* prev,
@@ -532,10 +565,13 @@ int pm_step_adj(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* cur, 
   ga.xi = adj->xi;
   ga.cot = adj->pi;
   ga.K = K;
-  ga.partials = p->partials;
+  ga.binned = true;
   if (int rc = gather_launch(p, GATHER_KICK_ADJ, ga, st)) return rc;
-  const double f[4] = {cur->dD, dK + K * 1.5 / coef, 0.0, 0.0};
-  return reduce_partials(p, blocks_for_particles(p), f, theta_bar, true, st);
+  // theta_bar[0] += (xi.p) dD  (drift partials)  +  (pi.a)(dK + K 1.5/coef)  (tile partials)
+  const double fd[4] = {cur->dD, 0.0, 0.0, 0.0};
+  if (int rc = reduce_partials(p, blocks_for_particles(p), fd, theta_bar, true, st)) return rc;
+  const double fk[4] = {0.0, dK + K * 1.5 / coef, 0.0, 0.0};
+  return reduce_buffer(p, p->tile_partials, p->ntiles, fk, theta_bar, true, st);
 }
 
 int pm_run_fwd(pm_plan h, pm_state* stt, const pm_step_coef* coefs, int n, double coef, hipStream_t st) {
@@ -579,6 +615,7 @@ int pm_density_mse(pm_plan h, const void* disp, const void* target, double* J, v
   ga.mesh = p->mesh[0];
   ga.nf = 1;
   ga.out = disp_bar;
+  ga.binned = true;
   return gather_launch(p, GATHER_MSE, ga, st);
 }
 
@@ -623,11 +660,12 @@ int pm_timing_enable(pm_plan h, int kernel, int on) {
   t.kernel = on ? kernel : 0;
   t.nev = 0;
   t.total_ms = 0.0;
+  t.total_bytes = 0.0;
   t.launches = 0;
   return PM_OK;
 }
 
-int pm_timing_read(pm_plan h, double* total_ms, int64_t* launches) {
+int pm_timing_read(pm_plan h, double* total_ms, int64_t* launches, double* total_bytes) {
   CHECK_PLAN(h);
   Timing& t = p->timing;
   for (int i = 0; i + 1 < t.nev; i += 2) {
@@ -635,11 +673,13 @@ int pm_timing_read(pm_plan h, double* total_ms, int64_t* launches) {
     PM_HIP_CHECK(p, hipEventSynchronize(t.ev[i + 1]));
     PM_HIP_CHECK(p, hipEventElapsedTime(&ms, t.ev[i], t.ev[i + 1]));
     t.total_ms += ms;
+    t.total_bytes += t.bytes[i / 2];
     t.launches += 1;
   }
   t.nev = 0;
   if (total_ms) *total_ms = t.total_ms;
   if (launches) *launches = t.launches;
+  if (total_bytes) *total_bytes = t.total_bytes;
   return PM_OK;
 }
 

@@ -197,13 +197,20 @@ __global__ __launch_bounds__(kThreads) void k_fft_lines(cplx<T>* __restrict__ da
   C* base = data + int64_t(blockIdx.y) * bstride + o * ostride + c0;
   const int tid = threadIdx.x;
   const int wmask = W - 1;
-#pragma unroll 4
-  for (int i = 0; i < EPT; ++i) {
-    const int f = tid + i * kThreads;
-    const int c = f & wmask, j = f >> logW;
-    C v = cmk<C>(0, 0);
-    if (c0 + c < ncols) v = base[j * ls + c];
-    lds[j * pitch + c] = v;
+  {
+    // all loads in flight before the first LDS store
+    C v[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int f = tid + i * kThreads;
+      const int c = f & wmask, j = f >> logW;
+      v[i] = (c0 + c < ncols) ? base[j * ls + c] : cmk<C>(0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int f = tid + i * kThreads;
+      lds[(f >> logW) * pitch + (f & wmask)] = v[i];
+    }
   }
   fft_lds<EPT, INV>(lds, logM, logW, pitch, tw);
 #pragma unroll 4
@@ -235,13 +242,18 @@ __global__ __launch_bounds__(kThreads) void k_fft_r2c_z(const T* __restrict__ in
   C* dst = out + int64_t(blockIdx.y) * out_bstride + l0 * (M + 1);
   const int64_t lines_here = nlines - l0 < W ? nlines - l0 : W;
   const int tid = threadIdx.x;
-#pragma unroll 4
-  for (int i = 0; i < EPT; ++i) {
-    const int f = tid + i * kThreads;
-    const int l = f >> logM, j = f & (M - 1);
-    C v = cmk<C>(0, 0);
-    if (l < lines_here) v = src[f];
-    lds[j * pitch + l] = v;
+  {
+    C v[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int f = tid + i * kThreads;
+      v[i] = ((f >> logM) < lines_here) ? src[f] : cmk<C>(0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int f = tid + i * kThreads;
+      lds[(f & (M - 1)) * pitch + (f >> logM)] = v[i];
+    }
   }
   fft_lds<EPT, false>(lds, logM, logW, pitch, tw);
   const int total = int(lines_here) * (M + 1);
@@ -285,7 +297,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_c2r_z(const cplx<T>* __restric
   const int64_t lines_here = nlines - l0 < W ? nlines - l0 : W;
   const int tid = threadIdx.x;
   const int twsh = kTwiddleLog2 - (logM + 1);
-#pragma unroll 4
+#pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int f = tid + i * kThreads;
     const int l = f >> logM, k = f & (M - 1);
@@ -469,7 +481,7 @@ int lines_pass(Plan* p, cplx<T>* data, bool inv, int M, int64_t ls, int64_t ncol
   else
     hipLaunchKernelGGL((k_fft_lines<T, false>), grid, dim3(kThreads), 0, st, data, logM, ls, ncols, ostride,
                        nouter, bstride, tw);
-  timing_end(p, PM_K_FFT_LINES, st);
+  timing_end(p, PM_K_FFT_LINES, st, 2.0 * double(batch) * double(ncols) * double(nouter) * M * sizeof(cplx<T>));
   PM_HIP_CHECK(p, hipGetLastError());
   return PM_OK;
 }
@@ -488,7 +500,8 @@ int fft_r2c_3d(Plan* p, const FftShape& s, const T* in, cplx<T>* out, int batch,
   timing_begin(p, PM_K_FFT_R2C_Z, st);
   hipLaunchKernelGGL((k_fft_r2c_z<T>), dim3(unsigned(ntiles), unsigned(batch)), dim3(kThreads), 0, st, in, out,
                      logM, nlines, in_stride, out_stride, static_cast<const cplx<T>*>(p->tw));
-  timing_end(p, PM_K_FFT_R2C_Z, st);
+  timing_end(p, PM_K_FFT_R2C_Z, st,
+             double(batch) * double(nlines) * (double(s.n2) * sizeof(T) + double(nh) * sizeof(cplx<T>)));
   PM_HIP_CHECK(p, hipGetLastError());
   // y: lines of n1 with stride nh, columns kz (nh), outer x (stride n1*nh)
   int rc = lines_pass<T>(p, out, false, s.n1, nh, nh, int64_t(s.n1) * nh, s.n0, batch, out_stride, st);
@@ -511,7 +524,8 @@ static int c2r_tail(Plan* p, const FftShape& s, cplx<T>* in, T* out, int batch, 
   timing_begin(p, PM_K_FFT_C2R_Z, st);
   hipLaunchKernelGGL((k_fft_c2r_z<T>), dim3(unsigned(ntiles), unsigned(batch)), dim3(kThreads), 0, st, in, out,
                      logM, nlines, in_stride, out_stride, scale, static_cast<const cplx<T>*>(p->tw));
-  timing_end(p, PM_K_FFT_C2R_Z, st);
+  timing_end(p, PM_K_FFT_C2R_Z, st,
+             double(batch) * double(nlines) * (double(s.n2) * sizeof(T) + double(nh) * sizeof(cplx<T>)));
   PM_HIP_CHECK(p, hipGetLastError());
   return PM_OK;
 }
@@ -556,7 +570,8 @@ int fft_c2r_fused(Plan* p, const FftShape& s, SpecOp op, cplx<T>* const* specs, 
   else
     hipLaunchKernelGGL((k_fft_x_fused<T, SPEC_ADJ4>), dim3(unsigned(ntiles)), dim3(kThreads), 0, st, in, o, logM,
                        s.n1, s.n2, nh, coef, tw);
-  timing_end(p, PM_K_FFT_POISSON, st);
+  timing_end(p, PM_K_FFT_POISSON, st,
+             double(op == SPEC_GRAD3 ? 4 : 8) * double(ncols) * double(s.n0) * sizeof(cplx<T>));
   PM_HIP_CHECK(p, hipGetLastError());
   // remaining passes on each output spectrum (the spectra are p->spec-style
   // equal-stride blocks only by convention, so run them one at a time)

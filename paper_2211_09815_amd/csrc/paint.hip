@@ -1,0 +1,446 @@
+// CIC paint (Sec. 2.2, eq. cic) with the optional fused drift of the KDK step
+// (Sec. 2.3, eq. KDFK) or of the adjoint step (Sec. 4.2, eq. KDFKO_adj).
+//
+// Floating-point atomics to HBM are resolved far from the compute units on
+// this multi-die GPU, so the paint never issues them on the mesh.  Instead
+// particles are binned by the mesh tile that owns their base node, and each
+// tile is accumulated in LDS by one workgroup:
+//   bin:      drift (optional), base node, tile id; per-tile counts with one
+//             atomic per distinct tile per wavefront; (tile, rank) per particle
+//   scan:     exclusive prefix sum of the tile counts
+//   scatter:  particle ids into per-tile lists
+//   tiles:    one workgroup per tile sums the 8 CIC corners of its particles
+//             in an LDS box of (TX+1)(TY+1)(TZ+1) cells, writes the TX*TY*TZ
+//             core with plain stores and the upper faces to a halo buffer
+//   halo:     every core cell on a lower face adds the halo faces of the
+//             (up to 7) lower neighbour tiles
+// Tiles are 8 x 8 x 16 cells (z contiguous), smaller when the mesh is.
+//
+// The LDS sums are 64-bit fixed point: integer LDS atomics are several times
+// faster than floating-point ones here, and integer addition is associative,
+// so the painted mesh is bitwise identical from run to run.  Each tile picks
+// its own binary scale 2^e per channel so that the bound count * max|w| of
+// any cell sum stays below 2^61; the quantum 2^-e is far below the mesh
+// type's rounding (about 1e-15 relative for a tile of ~10^3 particles).
+#include "tiles.h"
+
+namespace pmx {
+
+namespace {
+
+template <typename S, typename T>
+struct BinP {
+  TileGeo g;
+  S* s;
+  const S* p;
+  const T* xi;
+  T* pi;
+  S D;
+  unsigned* counts;   // [ntiles]
+  uint2* keys;        // [N] (tile, rank)
+  double* partials;   // slot 0: xi.p (adjoint drift)
+};
+
+template <typename S, typename T, int MODE>
+__global__ __launch_bounds__(kThreads) void k_bin(BinP<S, T> a) {
+  const TileGeo& g = a.g;
+  int64_t start, end;
+  chunk_of(g.N, start, end);
+  const int lane = threadIdx.x & 63;
+  double xp = 0.0;
+  for (int64_t base = start; base < end; base += kThreads) {
+    const int64_t n = base + threadIdx.x;
+    const bool valid = n < end;
+    int tile = 0;
+    if (valid) {
+      S s[3];
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) s[ax] = a.s[ax * g.N + n];
+      if (MODE == DRIFT_FWD) {
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          s[ax] += a.p[ax * g.N + n] * a.D;
+          a.s[ax * g.N + n] = s[ax];
+        }
+      } else if (MODE == DRIFT_ADJ) {
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          const S pv = a.p[ax * g.N + n];
+          const T xv = a.xi[ax * g.N + n];
+          xp += double(xv) * double(pv);
+          s[ax] -= pv * a.D;
+          a.s[ax * g.N + n] = s[ax];
+          a.pi[ax * g.N + n] = a.pi[ax * g.N + n] + T(xv * T(a.D));
+        }
+      }
+      double q[3];
+      lattice_pos(g, n, q);
+      const int b0 = int(int64_t(floor(q[0] + double(s[0]))) & (g.n0 - 1));
+      const int b1 = int(int64_t(floor(q[1] + double(s[1]))) & (g.n1 - 1));
+      const int b2 = int(int64_t(floor(q[2] + double(s[2]))) & (g.n2 - 1));
+      tile = ((b0 / g.tx) * g.nty + b1 / g.ty) * g.ntz + b2 / g.tz;
+    }
+    // one atomic per distinct tile among the active lanes of the wavefront
+    unsigned long long pending = __ballot(valid);
+    unsigned rank = 0;
+    while (pending) {
+      const int leader = __ffsll(static_cast<long long>(pending)) - 1;
+      const int lt = __shfl(tile, leader, 64);
+      const unsigned long long same = __ballot(valid && tile == lt) & pending;
+      unsigned baseidx = 0;
+      if (lane == leader) baseidx = atomicAdd(a.counts + lt, unsigned(__popcll(same)));
+      baseidx = __shfl(baseidx, leader, 64);
+      if ((same >> lane) & 1ull) rank = baseidx + unsigned(__popcll(same & ((1ull << lane) - 1ull)));
+      pending &= ~same;
+    }
+    if (valid) a.keys[n] = make_uint2(unsigned(tile), rank);
+  }
+  if (MODE == DRIFT_ADJ) {
+    const double t = block_sum_d(xp);
+    if (threadIdx.x == 0) a.partials[blockIdx.x * 4 + 0] = t;
+  }
+}
+
+// exclusive scan of counts in blocks of 4 * kThreads: offs = local prefix,
+// bsum[block] = block total
+__global__ __launch_bounds__(kThreads) void k_scan_local(const unsigned* counts, unsigned* offs, unsigned* bsum,
+                                                         int64_t n) {
+  __shared__ unsigned sh[kThreads];
+  const int64_t b0 = int64_t(blockIdx.x) * 4 * kThreads;
+  unsigned v[4];
+  unsigned tsum = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t idx = b0 + threadIdx.x * 4 + i;
+    v[i] = idx < n ? counts[idx] : 0u;
+    tsum += v[i];
+  }
+  sh[threadIdx.x] = tsum;
+  __syncthreads();
+  for (int off = 1; off < kThreads; off <<= 1) {
+    const unsigned t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0u;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
+  }
+  unsigned run = sh[threadIdx.x] - tsum;  // exclusive prefix of this thread
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t idx = b0 + threadIdx.x * 4 + i;
+    if (idx < n) offs[idx] = run;
+    run += v[i];
+  }
+  if (threadIdx.x == kThreads - 1) bsum[blockIdx.x] = sh[kThreads - 1];
+}
+
+// exclusive scan of the block sums (one workgroup, nb <= 4 * kThreads)
+__global__ __launch_bounds__(kThreads) void k_scan_blocks(unsigned* bsum, int nb) {
+  __shared__ unsigned sh[kThreads];
+  unsigned v[4];
+  unsigned tsum = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int idx = threadIdx.x * 4 + i;
+    v[i] = idx < nb ? bsum[idx] : 0u;
+    tsum += v[i];
+  }
+  sh[threadIdx.x] = tsum;
+  __syncthreads();
+  for (int off = 1; off < kThreads; off <<= 1) {
+    const unsigned t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0u;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
+  }
+  unsigned run = sh[threadIdx.x] - tsum;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int idx = threadIdx.x * 4 + i;
+    if (idx < nb) bsum[idx] = run;
+    run += v[i];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_add(unsigned* offs, const unsigned* bsum, int64_t n,
+                                                       unsigned total) {
+  const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i < n) offs[i] += bsum[i / (4 * kThreads)];
+  if (i == n) offs[n] = total;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scatter(const uint2* keys, const unsigned* offs, unsigned* list,
+                                                      int64_t N) {
+  int64_t start, end;
+  chunk_of(N, start, end);
+  for (int64_t n = start + threadIdx.x; n < end; n += kThreads) {
+    const uint2 k = keys[n];
+    list[offs[k.x] + k.y] = unsigned(n);
+  }
+}
+
+// one workgroup per tile; weights: channel 0 unit mass if UNIT, then w[c]
+template <typename S, typename T, int NCH, bool UNIT>
+__global__ __launch_bounds__(kThreads) void k_paint_tiles(TileGeo g, const S* __restrict__ s,
+                                                          const T* __restrict__ w, const unsigned* __restrict__ offs,
+                                                          const unsigned* __restrict__ list, T* __restrict__ mesh,
+                                                          T* __restrict__ halo) {
+  __shared__ unsigned long long box[NCH * kBoxMax];
+  __shared__ double wmax[kThreads / 64][NCH];
+  __shared__ double scale[NCH], inv_scale[NCH];
+  const int64_t tile = xcd_tile(blockIdx.x, int64_t(gridDim.x));
+  const int ex = g.tx + 1, ey = g.ty + 1, ez = g.tz + 1;
+  const int nbox = ex * ey * ez;
+  int o0, o1, o2;
+  tile_origin(g, tile, o0, o1, o2);
+  const unsigned beg = offs[tile], fin = offs[tile + 1];
+  // per-channel bound of any cell sum: count * max|w| (unit mass: count)
+  double m[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) m[c] = 0.0;
+  if (NCH > (UNIT ? 1 : 0)) {
+    for (unsigned i = beg + threadIdx.x; i < fin; i += kThreads) {
+      const int64_t n = list[i];
+#pragma unroll
+      for (int c = (UNIT ? 1 : 0); c < NCH; ++c) {
+        const double a = fabs(double(w[int64_t(c - (UNIT ? 1 : 0)) * g.N + n]));
+        m[c] = (a > m[c] || a != a) ? a : m[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_down(m[c], off, 64);
+        m[c] = (o > m[c] || o != o) ? o : m[c];
+      }
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) wmax[threadIdx.x >> 6][c] = m[c];
+  }
+  for (int i = threadIdx.x; i < NCH * nbox; i += kThreads) box[(i / nbox) * kBoxMax + i % nbox] = 0ull;
+  __syncthreads();
+  if (threadIdx.x < NCH) {
+    const int c = threadIdx.x;
+    double mx = 1.0;
+    if (!(UNIT && c == 0)) {
+      mx = 0.0;
+      for (int wv = 0; wv < kThreads / 64; ++wv) mx = (wmax[wv][c] > mx || wmax[wv][c] != wmax[wv][c]) ? wmax[wv][c] : mx;
+    }
+    const double bound = mx * double(fin - beg);
+    int ebits = 0;
+    if (bound > 0.0 && bound <= 1.0e300) {
+      frexp(bound, &ebits);           // bound < 2^ebits
+      scale[c] = ldexp(1.0, 61 - ebits);
+      inv_scale[c] = ldexp(1.0, ebits - 61);
+    } else if (bound == 0.0) {
+      scale[c] = 0.0;
+      inv_scale[c] = 0.0;
+    } else {                          // non-finite weights: poison the tile
+      scale[c] = 0.0;
+      inv_scale[c] = __longlong_as_double(0x7ff8000000000000ll);
+    }
+  }
+  __syncthreads();
+  double sc[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) sc[c] = scale[c];
+  for (unsigned i = beg + threadIdx.x; i < fin; i += kThreads) {
+    const int64_t n = list[i];
+    double q[3];
+    lattice_pos(g, n, q);
+    const double x0 = q[0] + double(s[n]), x1 = q[1] + double(s[g.N + n]), x2 = q[2] + double(s[2 * g.N + n]);
+    const double f0 = floor(x0), f1 = floor(x1), f2 = floor(x2);
+    // local base node inside the tile (the particle was binned by it)
+    const int l0 = int(int64_t(f0) & (g.n0 - 1)) - o0;
+    const int l1 = int(int64_t(f1) & (g.n1 - 1)) - o1;
+    const int l2 = int(int64_t(f2) & (g.n2 - 1)) - o2;
+    const T d0 = T(x0 - f0), d1 = T(x1 - f1), d2 = T(x2 - f2);
+    const T wx[2] = {T(1) - d0, d0}, wy[2] = {T(1) - d1, d1}, wz[2] = {T(1) - d2, d2};
+    double wc[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+      wc[c] = ((UNIT && c == 0) ? 1.0 : double(w[int64_t(c - (UNIT ? 1 : 0)) * g.N + n])) * sc[c];
+#pragma unroll
+    for (int i0 = 0; i0 < 2; ++i0)
+#pragma unroll
+      for (int i1 = 0; i1 < 2; ++i1) {
+        const T wxy = wx[i0] * wy[i1];
+        const int rowb = ((l0 + i0) * ey + (l1 + i1)) * ez + l2;
+#pragma unroll
+        for (int i2 = 0; i2 < 2; ++i2) {
+          const double ww = double(wxy * wz[i2]);
+#pragma unroll
+          for (int c = 0; c < NCH; ++c)
+            atomicAdd(&box[c * kBoxMax + rowb + i2], (unsigned long long)__double2ll_rn(ww * wc[c]));
+        }
+      }
+  }
+  __syncthreads();
+  // core: plain stores, rows of tz contiguous cells
+  const int ncore = g.tx * g.ty * g.tz;
+  for (int i = threadIdx.x; i < NCH * ncore; i += kThreads) {
+    const int c = i / ncore;
+    const int r = i - c * ncore;
+    const int lz = r % g.tz;
+    const int lxy = r / g.tz;
+    const int ly = lxy % g.ty, lx = lxy / g.ty;
+    mesh[c * g.ncell + (int64_t(o0 + lx) * g.n1 + (o1 + ly)) * g.n2 + (o2 + lz)] =
+        T(double(static_cast<long long>(box[c * kBoxMax + (lx * ey + ly) * ez + lz])) * inv_scale[c]);
+  }
+  // halo faces: X (lx = tx, all ly, lz), Y (ly = ty, lx < tx), Z (lz = tz, lx < tx, ly < ty)
+  const int fx = ey * ez, fy = g.tx * ez;
+  for (int i = threadIdx.x; i < NCH * g.hc; i += kThreads) {
+    const int c = i / g.hc;
+    const int h = i - c * g.hc;
+    int lx, ly, lz;
+    if (h < fx) { lx = g.tx; ly = h / ez; lz = h % ez; }
+    else if (h < fx + fy) { const int k = h - fx; lx = k / ez; ly = g.ty; lz = k % ez; }
+    else { const int k = h - fx - fy; lx = k / g.ty; ly = k % g.ty; lz = g.tz; }
+    halo[(int64_t(c) * g.ntiles + tile) * g.hc + h] =
+        T(double(static_cast<long long>(box[c * kBoxMax + (lx * ey + ly) * ez + lz])) * inv_scale[c]);
+  }
+}
+
+// core cells on the lower faces of each tile gather the halo faces of the
+// lower neighbours d in {0,1}^3 \ {0} (wrapped), for every channel
+template <typename T, int NCH>
+__global__ __launch_bounds__(kThreads) void k_halo_add(TileGeo g, T* __restrict__ mesh, const T* __restrict__ halo) {
+  const int64_t tile = xcd_tile(blockIdx.x, int64_t(gridDim.x));
+  const int t2 = int(tile % g.ntz);
+  const int64_t t01 = tile / g.ntz;
+  const int t1 = int(t01 % g.nty);
+  const int t0 = int(t01 / g.nty);
+  const int ez = g.tz + 1, ey = g.ty + 1;
+  const int fx = ey * ez, fy = g.tx * ez;
+  const int nA = g.ty * g.tz, nB = (g.tx - 1) * g.tz, nC = (g.tx - 1) * (g.ty - 1);
+  const int nb = nA + nB + nC;
+  for (int i = threadIdx.x; i < nb; i += kThreads) {
+    int lx, ly, lz;
+    if (i < nA) { lx = 0; ly = i / g.tz; lz = i % g.tz; }
+    else if (i < nA + nB) { const int k = i - nA; lx = 1 + k / g.tz; ly = 0; lz = k % g.tz; }
+    else { const int k = i - nA - nB; lx = 1 + k / (g.ty - 1); ly = 1 + k % (g.ty - 1); lz = 0; }
+    T add[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) add[c] = T(0);
+#pragma unroll
+    for (int d = 1; d < 8; ++d) {
+      const int dx = d >> 2, dy = (d >> 1) & 1, dz = d & 1;
+      if ((dx && lx) || (dy && ly) || (dz && lz)) continue;
+      const int u0 = (t0 - dx + g.ntx) % g.ntx, u1 = (t1 - dy + g.nty) % g.nty, u2 = (t2 - dz + g.ntz) % g.ntz;
+      const int64_t u = (int64_t(u0) * g.nty + u1) * g.ntz + u2;
+      const int e1 = dy ? g.ty : ly, e2 = dz ? g.tz : lz;
+      int h;
+      if (dx) h = e1 * ez + e2;
+      else if (dy) h = fx + lx * ez + e2;
+      else h = fx + fy + lx * g.ty + ly;
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) add[c] += halo[(int64_t(c) * g.ntiles + u) * g.hc + h];
+    }
+    const int64_t cell = (int64_t(t0 * g.tx + lx) * g.n1 + (t1 * g.ty + ly)) * g.n2 + (t2 * g.tz + lz);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) mesh[c * g.ncell + cell] += add[c];
+  }
+}
+
+template <typename S, typename T>
+int bin_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
+  const TileGeo g = tile_geo(p);
+  const dim3 block(kThreads);
+  const int pblocks = blocks_for_particles(p);
+  PM_HIP_CHECK(p, hipMemsetAsync(p->bin_counts, 0, size_t(g.ntiles) * sizeof(unsigned), st));
+  BinP<S, T> b;
+  b.g = g;
+  b.s = static_cast<S*>(const_cast<void*>(in.s));
+  b.p = static_cast<const S*>(in.p);
+  b.xi = static_cast<const T*>(in.xi);
+  b.pi = static_cast<T*>(in.pi);
+  b.D = S(in.D);
+  b.counts = p->bin_counts;
+  b.keys = static_cast<uint2*>(p->bin_keys);
+  b.partials = in.partials;
+  if (mode == DRIFT_FWD) hipLaunchKernelGGL((k_bin<S, T, DRIFT_FWD>), dim3(pblocks), block, 0, st, b);
+  else if (mode == DRIFT_ADJ) hipLaunchKernelGGL((k_bin<S, T, DRIFT_ADJ>), dim3(pblocks), block, 0, st, b);
+  else hipLaunchKernelGGL((k_bin<S, T, DRIFT_NONE>), dim3(pblocks), block, 0, st, b);
+  const int64_t nt = g.ntiles;
+  const int nsb = int((nt + 4 * kThreads - 1) / (4 * kThreads));
+  hipLaunchKernelGGL(k_scan_local, dim3(nsb), block, 0, st, p->bin_counts, p->bin_offs, p->bin_bsum, nt);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), block, 0, st, p->bin_bsum, nsb);
+  hipLaunchKernelGGL(k_scan_add, dim3(unsigned((nt + 1 + kThreads - 1) / kThreads)), block, 0, st, p->bin_offs,
+                     p->bin_bsum, nt, unsigned(g.N));
+  hipLaunchKernelGGL(k_scatter, dim3(pblocks), block, 0, st, static_cast<const uint2*>(p->bin_keys), p->bin_offs,
+                     p->bin_list, g.N);
+  PM_HIP_CHECK(p, hipGetLastError());
+  return PM_OK;
+}
+
+template <typename S, typename T>
+int paint_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
+  const TileGeo g = tile_geo(p);
+  const int nch = in.unit + in.nw;
+  const dim3 block(kThreads);
+  const int64_t nt = g.ntiles;
+  timing_begin(p, PM_K_PAINT, st);
+  if (int rc = bin_typed<S, T>(p, mode, in, st)) return rc;
+  const S* s = static_cast<const S*>(in.s);
+  // in the adjoint drift the weighted channels are the updated pi
+  const T* w = static_cast<const T*>(mode == DRIFT_ADJ ? in.pi : in.w);
+  T* mesh = static_cast<T*>(in.mesh);
+  T* halo = static_cast<T*>(p->bin_halo);
+  const dim3 tg{unsigned(nt), 1, 1};
+#define PM_TILES(NCH, UNIT)                                                                                \
+  hipLaunchKernelGGL((k_paint_tiles<S, T, NCH, UNIT>), tg, block, 0, st, g, s, w, p->bin_offs, p->bin_list, \
+                     mesh, halo);                                                                          \
+  hipLaunchKernelGGL((k_halo_add<T, NCH>), tg, block, 0, st, g, mesh, halo)
+  if (in.unit) {
+    switch (nch) {
+      case 1: PM_TILES(1, true); break;
+      case 2: PM_TILES(2, true); break;
+      case 3: PM_TILES(3, true); break;
+      default: PM_TILES(4, true); break;
+    }
+  } else {
+    switch (nch) {
+      case 1: PM_TILES(1, false); break;
+      case 2: PM_TILES(2, false); break;
+      case 3: PM_TILES(3, false); break;
+      default: PM_TILES(4, false); break;
+    }
+  }
+#undef PM_TILES
+  {
+    // algorithmic traffic: particle state (+ drift and weights) and one write of each mesh channel
+    const double N = double(p->nptcl), sb = sizeof(S), mb = sizeof(T);
+    double bytes = 3 * N * sb + double(nch) * double(p->ncell) * mb + double(in.nw) * N * mb;
+    if (mode == DRIFT_FWD) bytes += 6 * N * sb;
+    if (mode == DRIFT_ADJ) bytes += 6 * N * sb + 9 * N * mb - double(in.nw) * N * mb;
+    timing_end(p, PM_K_PAINT, st, bytes);
+  }
+  PM_HIP_CHECK(p, hipGetLastError());
+  return PM_OK;
+}
+
+}  // namespace
+
+int bin_launch(Plan* p, DriftMode mode, const PaintArgs& a, hipStream_t st) {
+  const bool s64 = p->cfg.state_dtype == PM_F64, m64 = p->cfg.mesh_dtype == PM_F64;
+  if (m64) return bin_typed<double, double>(p, mode, a, st);
+  if (s64) return bin_typed<double, float>(p, mode, a, st);
+  return bin_typed<float, float>(p, mode, a, st);
+}
+
+int paint_launch(Plan* p, DriftMode mode, const PaintArgs& a, hipStream_t st) {
+  const bool s64 = p->cfg.state_dtype == PM_F64, m64 = p->cfg.mesh_dtype == PM_F64;
+  if (m64) return paint_typed<double, double>(p, mode, a, st);
+  if (s64) return paint_typed<double, float>(p, mode, a, st);
+  return paint_typed<float, float>(p, mode, a, st);
+}
+
+void tile_dims(const int n[3], int tile[3], int64_t& ntiles, int& halo_cells) {
+  tile[0] = n[0] < 8 ? n[0] : 8;
+  tile[1] = n[1] < 8 ? n[1] : 8;
+  tile[2] = n[2] < 16 ? n[2] : 16;
+  ntiles = int64_t(n[0] / tile[0]) * (n[1] / tile[1]) * (n[2] / tile[2]);
+  halo_cells = (tile[1] + 1) * (tile[2] + 1) + tile[0] * (tile[2] + 1) + tile[0] * tile[1];
+}
+
+}  // namespace pmx

@@ -1,161 +1,30 @@
-// Particle kernels: CIC paint with optional fused drift (Sec. 2.2 eq. cic and
-// Sec. 2.3 eq. KDFK), CIC gather with fused kick, force VJP gather
-// (Sec. 4.2, eq. KDFKO_adj) and the density-MSE mesh kernel (Sec. 5.2).
+// Particle kernels: CIC gather with fused kick (Sec. 2.2 and eq. KDFK), the
+// force-VJP gather (Sec. 4.2, eq. KDFKO_adj) and the density-MSE mesh kernel
+// (Sec. 5.2).  The paint and the particle binning live in paint.hip.
 //
-// Particles are processed in lattice order, so consecutive lanes paint to
-// and gather from neighbouring cells; the paint accumulates with hardware
-// floating-point atomics at L2 (no return value).  Positions are formed in
-// FP64 from the exact lattice coordinate and the stored displacement, then the
-// in-cell fraction is rounded to the mesh type.  Reductions that feed
-// gradients (xi.p, pi.a, (delta - target)^2) are written as per-workgroup
-// FP64 partial sums and combined by one workgroup in a fixed order, so they
-// are deterministic.
-#include "pm_internal.h"
+// The gather reuses the paint's tile binning: one workgroup per mesh tile
+// loads the tile's box of (tx+1)(ty+1)(tz+1) cells of every field into LDS
+// with coalesced row reads, then serves the 8 CIC corners of each of its
+// particles from LDS, so the random part of the access pattern never reaches
+// HBM or L2.  Positions are formed in FP64 from the exact lattice coordinate
+// and the stored displacement, then the in-cell fraction is rounded to the
+// mesh type.  Reductions that feed gradients (pi.a, (delta - target)^2) are
+// written as per-workgroup FP64 partial sums and combined in a fixed order,
+// so they are deterministic.
+#include "tiles.h"
 
 namespace pmx {
 
 namespace {
 
-struct Geo {
-  int64_t N;          // particles
-  int np1, np2;       // lattice dims 1 and 2
-  double r0, r1, r2;  // lattice spacing (cells)
-  double off;         // lattice offset (cells)
-  int n0, n1, n2;     // mesh dims (powers of two)
-  int64_t ncell;
-};
-
-__device__ __forceinline__ void lattice_of(const Geo& g, int64_t n, double q[3]) {
-  const int64_t row = n / g.np2;
-  const int k = int(n - row * g.np2);
-  const int64_t i = row / g.np1;
-  const int j = int(row - i * g.np1);
-  q[0] = double(i) * g.r0 + g.off;
-  q[1] = double(j) * g.r1 + g.off;
-  q[2] = double(k) * g.r2 + g.off;
-}
-
-// base node (wrapped) and fraction in [0, 1] for one axis
-template <typename T>
-__device__ __forceinline__ void cic_axis(double u, int nmask, int& i0, int& i1, T& f) {
-  const double fl = floor(u);
-  f = T(u - fl);
-  const int64_t b = int64_t(fl);
-  i0 = int(b & nmask);
-  i1 = int((b + 1) & nmask);
-}
-
-template <typename T>
-struct Cic {
-  int ix[2], iy[2], iz[2];
-  T wx[2], wy[2], wz[2];
-  __device__ __forceinline__ void init(const Geo& g, const double x[3]) {
-    T f;
-    cic_axis<T>(x[0], g.n0 - 1, ix[0], ix[1], f); wx[0] = T(1) - f; wx[1] = f;
-    cic_axis<T>(x[1], g.n1 - 1, iy[0], iy[1], f); wy[0] = T(1) - f; wy[1] = f;
-    cic_axis<T>(x[2], g.n2 - 1, iz[0], iz[1], f); wz[0] = T(1) - f; wz[1] = f;
-  }
-  __device__ __forceinline__ int64_t idx(int a, int b, int c, const Geo& g) const {
-    return (int64_t(ix[a]) * g.n1 + iy[b]) * g.n2 + iz[c];
-  }
-};
-
-__device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
-__device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
-
-__device__ __forceinline__ double block_sum(double v) {
-  __shared__ double ws[kThreads / 64];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) ws[wid] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0)
-    for (int w = 0; w < kThreads / 64; ++w) t += ws[w];
-  return t;
-}
-
-// ---------------------------------------------------------------------------
-// paint (+ drift)
-// ---------------------------------------------------------------------------
-template <typename S, typename T>
-struct PaintP {
-  Geo g;
-  S* s;
-  const S* p;
-  const T* xi;
-  T* pi;
-  const T* w;
-  T* mesh;
-  S D;
-  double* partials;  // slot 0: sum xi.p (adjoint drift)
-};
-
-template <typename S, typename T, int MODE, int NCH, bool UNIT>
-__global__ __launch_bounds__(kThreads) void k_paint(PaintP<S, T> a) {
-  const Geo& g = a.g;
-  const int64_t stride = int64_t(gridDim.x) * kThreads;
-  double xp = 0.0;
-  for (int64_t n = int64_t(blockIdx.x) * kThreads + threadIdx.x; n < g.N; n += stride) {
-    S s[3];
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) s[ax] = a.s[ax * g.N + n];
-    T wch[4];
-    if (MODE == DRIFT_FWD) {
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        s[ax] += a.p[ax * g.N + n] * a.D;
-        a.s[ax * g.N + n] = s[ax];
-      }
-    } else if (MODE == DRIFT_ADJ) {
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        const S pv = a.p[ax * g.N + n];
-        const T xv = a.xi[ax * g.N + n];
-        xp += double(xv) * double(pv);
-        s[ax] -= pv * a.D;
-        a.s[ax * g.N + n] = s[ax];
-        const T pin = a.pi[ax * g.N + n] + T(xv * T(a.D));
-        a.pi[ax * g.N + n] = pin;
-        wch[1 + ax] = pin;
-      }
-    }
-    if (UNIT) wch[0] = T(1);
-    if (MODE != DRIFT_ADJ) {
-#pragma unroll
-      for (int c = UNIT ? 1 : 0; c < NCH; ++c) wch[c] = a.w[int64_t(c - (UNIT ? 1 : 0)) * g.N + n];
-    }
-    double q[3];
-    lattice_of(g, n, q);
-    const double x[3] = {q[0] + double(s[0]), q[1] + double(s[1]), q[2] + double(s[2])};
-    Cic<T> cic;
-    cic.init(g, x);
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          const T w = cic.wx[i] * cic.wy[j] * cic.wz[k];
-          const int64_t idx = cic.idx(i, j, k, g);
-#pragma unroll
-          for (int c = 0; c < NCH; ++c) atomic_add(a.mesh + c * g.ncell + idx, w * wch[c]);
-        }
-  }
-  if (MODE == DRIFT_ADJ) {
-    const double t = block_sum(xp);
-    if (threadIdx.x == 0) a.partials[blockIdx.x * 4 + 0] = t;
-  }
-}
+__device__ __forceinline__ double block_sum(double v) { return block_sum_d(v); }
 
 // ---------------------------------------------------------------------------
 // gather (+ kick / VJP)
 // ---------------------------------------------------------------------------
 template <typename S, typename T>
 struct GatherP {
-  Geo g;
+  TileGeo g;
   const S* s;
   const T* mesh;   // [nf][ncell]
   T* out;          // plain: [nf][N]; VJP/MSE: xbar [3][N]
@@ -165,94 +34,118 @@ struct GatherP {
   const T* cot;    // cotangent [3][N]
   const T* acc_in; // if set, the kick and cot.a use these accelerations
   S K;             // kick coefficient
-  double* partials;  // slot 1: sum cot.a
+  const unsigned* offs;
+  const unsigned* list;
+  double* partials;  // per tile, slot 1: sum cot.a
 };
 
 template <typename S, typename T, int MODE, int NF>
-__global__ __launch_bounds__(kThreads) void k_gather(GatherP<S, T> a) {
-  const Geo& g = a.g;
-  const int64_t stride = int64_t(gridDim.x) * kThreads;
+__global__ __launch_bounds__(kThreads) void k_gather_tiles(GatherP<S, T> a) {
+  const TileGeo& g = a.g;
+  __shared__ T box[NF * kBoxMax];
+  const int64_t tile = xcd_tile(blockIdx.x, int64_t(gridDim.x));
+  const int ex = g.tx + 1, ey = g.ty + 1, ez = g.tz + 1;
+  const int nbox = ex * ey * ez;
+  int o0, o1, o2;
+  tile_origin(g, tile, o0, o1, o2);
+  const unsigned beg = a.offs[tile], fin = a.offs[tile + 1];
   double ca = 0.0;
-  for (int64_t n = int64_t(blockIdx.x) * kThreads + threadIdx.x; n < g.N; n += stride) {
-    double q[3];
-    lattice_of(g, n, q);
-    double x[3];
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) x[ax] = q[ax] + double(a.s[ax * g.N + n]);
-    Cic<T> cic;
-    cic.init(g, x);
-    T v[NF];
-#pragma unroll
-    for (int c = 0; c < NF; ++c) v[c] = T(0);
-    T cot[3] = {T(0), T(0), T(0)};
-    if (MODE == GATHER_VJP || MODE == GATHER_KICK_ADJ) {
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) cot[ax] = a.cot[ax * g.N + n];
+  if (fin > beg) {
+    for (int i = threadIdx.x; i < NF * nbox; i += kThreads) {
+      const int c = i / nbox;
+      const int r = i - c * nbox;
+      const int lz = r % ez;
+      const int lxy = r / ez;
+      const int ly = lxy % ey, lx = lxy / ey;
+      const int64_t cell = (int64_t((o0 + lx) & (g.n0 - 1)) * g.n1 + ((o1 + ly) & (g.n1 - 1))) * g.n2 +
+                           ((o2 + lz) & (g.n2 - 1));
+      box[c * kBoxMax + r] = a.mesh[c * g.ncell + cell];
     }
-    T dv[3] = {T(0), T(0), T(0)};  // sum_corner dW_k * h(corner)
+    __syncthreads();
+    for (unsigned i = beg + threadIdx.x; i < fin; i += kThreads) {
+      const int64_t n = a.list[i];
+      double q[3];
+      lattice_pos(g, n, q);
+      const double x0 = q[0] + double(a.s[n]), x1 = q[1] + double(a.s[g.N + n]), x2 = q[2] + double(a.s[2 * g.N + n]);
+      const double f0 = floor(x0), f1 = floor(x1), f2 = floor(x2);
+      const int l0 = int(int64_t(f0) & (g.n0 - 1)) - o0;
+      const int l1 = int(int64_t(f1) & (g.n1 - 1)) - o1;
+      const int l2 = int(int64_t(f2) & (g.n2 - 1)) - o2;
+      const T d0 = T(x0 - f0), d1 = T(x1 - f1), d2 = T(x2 - f2);
+      const T wx[2] = {T(1) - d0, d0}, wy[2] = {T(1) - d1, d1}, wz[2] = {T(1) - d2, d2};
+      T v[NF];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+      for (int c = 0; c < NF; ++c) v[c] = T(0);
+      T cot[3] = {T(0), T(0), T(0)};
+      if (MODE == GATHER_VJP || MODE == GATHER_KICK_ADJ) {
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+        for (int ax = 0; ax < 3; ++ax) cot[ax] = a.cot[ax * g.N + n];
+      }
+      T dv[3] = {T(0), T(0), T(0)};  // sum_corner dW_k * h(corner)
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          const int64_t idx = cic.idx(i, j, k, g);
-          const T w = cic.wx[i] * cic.wy[j] * cic.wz[k];
-          T m[NF];
+      for (int i0 = 0; i0 < 2; ++i0)
 #pragma unroll
-          for (int c = 0; c < NF; ++c) m[c] = a.mesh[c * g.ncell + idx];
-          if (MODE == GATHER_PLAIN || MODE == GATHER_KICK_FWD || MODE == GATHER_VJP ||
-              MODE == GATHER_KICK_ADJ) {
+        for (int i1 = 0; i1 < 2; ++i1)
 #pragma unroll
-            for (int c = 0; c < (MODE == GATHER_PLAIN || MODE == GATHER_KICK_FWD ? NF : 3); ++c) v[c] += w * m[c];
+          for (int i2 = 0; i2 < 2; ++i2) {
+            const int r = ((l0 + i0) * ey + (l1 + i1)) * ez + (l2 + i2);
+            const T w = wx[i0] * wy[i1] * wz[i2];
+            T m[NF];
+#pragma unroll
+            for (int c = 0; c < NF; ++c) m[c] = box[c * kBoxMax + r];
+            if (MODE == GATHER_PLAIN || MODE == GATHER_KICK_FWD || MODE == GATHER_VJP ||
+                MODE == GATHER_KICK_ADJ) {
+#pragma unroll
+              for (int c = 0; c < (MODE == GATHER_PLAIN || MODE == GATHER_KICK_FWD ? NF : 3); ++c) v[c] += w * m[c];
+            }
+            if (MODE == GATHER_VJP || MODE == GATHER_KICK_ADJ || MODE == GATHER_MSE) {
+              // h = sum_j cot_j g_j + rhobar   (VJP)   or   h = mbar   (MSE)
+              T h;
+              if (MODE == GATHER_MSE) h = m[0];
+              else h = cot[0] * m[0] + cot[1] * m[1] + cot[2] * m[2] + m[3];
+              const T sx = i0 ? T(1) : T(-1), sy = i1 ? T(1) : T(-1), sz = i2 ? T(1) : T(-1);
+              dv[0] += sx * wy[i1] * wz[i2] * h;
+              dv[1] += sy * wx[i0] * wz[i2] * h;
+              dv[2] += sz * wx[i0] * wy[i1] * h;
+            }
           }
-          if (MODE == GATHER_VJP || MODE == GATHER_KICK_ADJ || MODE == GATHER_MSE) {
-            // h = sum_j cot_j g_j + rhobar   (VJP)   or   h = mbar   (MSE)
-            T h;
-            if (MODE == GATHER_MSE) h = m[0];
-            else h = cot[0] * m[0] + cot[1] * m[1] + cot[2] * m[2] + m[3];
-            const T sx = i ? T(1) : T(-1), sy = j ? T(1) : T(-1), sz = k ? T(1) : T(-1);
-            dv[0] += sx * cic.wy[j] * cic.wz[k] * h;
-            dv[1] += sy * cic.wx[i] * cic.wz[k] * h;
-            dv[2] += sz * cic.wx[i] * cic.wy[j] * h;
-          }
+      if (MODE == GATHER_PLAIN) {
+#pragma unroll
+        for (int c = 0; c < NF; ++c) a.out[c * g.N + n] = v[c];
+      } else if (MODE == GATHER_KICK_FWD) {
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          a.p[ax * g.N + n] += S(v[ax]) * a.K;
+          if (a.acc) a.acc[ax * g.N + n] = v[ax];
         }
-    if (MODE == GATHER_PLAIN) {
+      } else if (MODE == GATHER_VJP) {
 #pragma unroll
-      for (int c = 0; c < NF; ++c) a.out[c * g.N + n] = v[c];
-    } else if (MODE == GATHER_KICK_FWD) {
+        for (int ax = 0; ax < 3; ++ax) {
+          a.out[ax * g.N + n] = dv[ax];
+          if (a.acc) a.acc[ax * g.N + n] = v[ax];
+          ca += double(cot[ax]) * double(v[ax]);
+        }
+      } else if (MODE == GATHER_KICK_ADJ) {
+        if (a.acc_in) {
 #pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        a.p[ax * g.N + n] += S(v[ax]) * a.K;
-        if (a.acc) a.acc[ax * g.N + n] = v[ax];
+          for (int ax = 0; ax < 3; ++ax) v[ax] = a.acc_in[ax * g.N + n];
+        }
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          ca += double(cot[ax]) * double(v[ax]);
+          a.p[ax * g.N + n] -= S(v[ax]) * a.K;
+          a.xi[ax * g.N + n] += dv[ax] * T(a.K);
+          if (a.acc) a.acc[ax * g.N + n] = v[ax];
+        }
+      } else if (MODE == GATHER_MSE) {
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) a.out[ax * g.N + n] = dv[ax];
       }
-    } else if (MODE == GATHER_VJP) {
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        a.out[ax * g.N + n] = dv[ax];
-        if (a.acc) a.acc[ax * g.N + n] = v[ax];
-        ca += double(cot[ax]) * double(v[ax]);
-      }
-    } else if (MODE == GATHER_KICK_ADJ) {
-      if (a.acc_in) {
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) v[ax] = a.acc_in[ax * g.N + n];
-      }
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        ca += double(cot[ax]) * double(v[ax]);
-        a.p[ax * g.N + n] -= S(v[ax]) * a.K;
-        a.xi[ax * g.N + n] += dv[ax] * T(a.K);
-        if (a.acc) a.acc[ax * g.N + n] = v[ax];
-      }
-    } else if (MODE == GATHER_MSE) {
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) a.out[ax * g.N + n] = dv[ax];
     }
   }
   if (MODE == GATHER_VJP || MODE == GATHER_KICK_ADJ) {
     const double t = block_sum(ca);
-    if (threadIdx.x == 0) a.partials[blockIdx.x * 4 + 1] = t;
+    if (threadIdx.x == 0) a.partials[tile * 4 + 1] = t;
   }
 }
 
@@ -282,7 +175,7 @@ __global__ __launch_bounds__(kThreads) void k_contrast(T* mesh, int64_t ncell, d
 
 // out[0] (+)= sum_k f[k] * sum_b part[b*4 + k]; summed in a fixed order
 // (slots whose factor is zero are skipped, so stale slots never contribute)
-__global__ __launch_bounds__(kThreads) void k_reduce(const double* part, int nblocks, double f0, double f1,
+__global__ __launch_bounds__(kThreads) void k_reduce(const double* part, int64_t nblocks, double f0, double f1,
                                                      double f2, double f3, double* out, int accumulate) {
   const double f[4] = {f0, f1, f2, f3};
   double v = 0.0;
@@ -290,7 +183,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const double* part, int nbl
   for (int k = 0; k < 4; ++k) {
     if (f[k] == 0.0) continue;
     double s = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += kThreads) s += part[b * 4 + k];
+    for (int64_t b = threadIdx.x; b < nblocks; b += kThreads) s += part[b * 4 + k];
     v += f[k] * s;
   }
   const double t = block_sum(v);
@@ -298,67 +191,9 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const double* part, int nbl
 }
 
 template <typename S, typename T>
-Geo make_geo(const Plan* p) {
-  Geo g;
-  g.N = p->nptcl;
-  g.np1 = p->np[1];
-  g.np2 = p->np[2];
-  g.r0 = p->r[0];
-  g.r1 = p->r[1];
-  g.r2 = p->r[2];
-  g.off = p->cfg.lattice_offset;
-  g.n0 = p->n[0];
-  g.n1 = p->n[1];
-  g.n2 = p->n[2];
-  g.ncell = p->ncell;
-  return g;
-}
-
-template <typename S, typename T>
-int paint_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
-  PaintP<S, T> a;
-  a.g = make_geo<S, T>(p);
-  a.s = static_cast<S*>(const_cast<void*>(in.s));
-  a.p = static_cast<const S*>(in.p);
-  a.xi = static_cast<const T*>(in.xi);
-  a.pi = static_cast<T*>(in.pi);
-  a.w = static_cast<const T*>(in.w);
-  a.mesh = static_cast<T*>(in.mesh);
-  a.D = S(in.D);
-  a.partials = in.partials;
-  const int nch = in.unit + in.nw;
-  const dim3 grid(blocks_for_particles(p)), block(kThreads);
-  timing_begin(p, PM_K_PAINT, st);
-#define PM_PAINT(MODE, NCH, UNIT) hipLaunchKernelGGL((k_paint<S, T, MODE, NCH, UNIT>), grid, block, 0, st, a)
-  if (mode == DRIFT_FWD) {
-    PM_PAINT(DRIFT_FWD, 1, true);
-  } else if (mode == DRIFT_ADJ) {
-    PM_PAINT(DRIFT_ADJ, 4, true);
-  } else if (in.unit) {
-    switch (nch) {
-      case 1: PM_PAINT(DRIFT_NONE, 1, true); break;
-      case 2: PM_PAINT(DRIFT_NONE, 2, true); break;
-      case 3: PM_PAINT(DRIFT_NONE, 3, true); break;
-      default: PM_PAINT(DRIFT_NONE, 4, true); break;
-    }
-  } else {
-    switch (nch) {
-      case 1: PM_PAINT(DRIFT_NONE, 1, false); break;
-      case 2: PM_PAINT(DRIFT_NONE, 2, false); break;
-      case 3: PM_PAINT(DRIFT_NONE, 3, false); break;
-      default: PM_PAINT(DRIFT_NONE, 4, false); break;
-    }
-  }
-#undef PM_PAINT
-  timing_end(p, PM_K_PAINT, st);
-  PM_HIP_CHECK(p, hipGetLastError());
-  return PM_OK;
-}
-
-template <typename S, typename T>
 int gather_typed(Plan* p, GatherMode mode, const GatherArgs& in, hipStream_t st) {
   GatherP<S, T> a;
-  a.g = make_geo<S, T>(p);
+  a.g = tile_geo(p);
   a.s = static_cast<const S*>(in.s);
   a.mesh = static_cast<const T*>(in.mesh);
   a.out = static_cast<T*>(in.out);
@@ -368,10 +203,12 @@ int gather_typed(Plan* p, GatherMode mode, const GatherArgs& in, hipStream_t st)
   a.cot = static_cast<const T*>(in.cot);
   a.acc_in = static_cast<const T*>(in.acc_in);
   a.K = S(in.K);
-  a.partials = in.partials;
-  const dim3 grid(blocks_for_particles(p)), block(kThreads);
+  a.offs = p->bin_offs;
+  a.list = p->bin_list;
+  a.partials = p->tile_partials;
+  const dim3 grid(unsigned(p->ntiles)), block(kThreads);
   timing_begin(p, PM_K_GATHER, st);
-#define PM_GATHER(MODE, NF) hipLaunchKernelGGL((k_gather<S, T, MODE, NF>), grid, block, 0, st, a)
+#define PM_GATHER(MODE, NF) hipLaunchKernelGGL((k_gather_tiles<S, T, MODE, NF>), grid, block, 0, st, a)
   switch (mode) {
     case GATHER_PLAIN:
       switch (in.nf) {
@@ -387,7 +224,17 @@ int gather_typed(Plan* p, GatherMode mode, const GatherArgs& in, hipStream_t st)
     case GATHER_MSE: PM_GATHER(GATHER_MSE, 1); break;
   }
 #undef PM_GATHER
-  timing_end(p, PM_K_GATHER, st);
+  {
+    // positions and the gathered mesh fields once, plus the per-mode particle traffic
+    const double N = double(p->nptcl), sb = sizeof(S), mb = sizeof(T);
+    double bytes = 3 * N * sb + double(in.nf) * double(p->ncell) * mb;
+    if (mode == GATHER_PLAIN) bytes += double(in.nf) * N * mb;
+    if (mode == GATHER_KICK_FWD) bytes += 6 * N * sb + (in.acc ? 3 * N * mb : 0.0);
+    if (mode == GATHER_VJP) bytes += 6 * N * mb + (in.acc ? 3 * N * mb : 0.0);
+    if (mode == GATHER_KICK_ADJ) bytes += 6 * N * sb + 9 * N * mb + (in.acc_in ? 3 * N * mb : 0.0);
+    if (mode == GATHER_MSE) bytes += 3 * N * mb;
+    timing_end(p, PM_K_GATHER, st, bytes);
+  }
   PM_HIP_CHECK(p, hipGetLastError());
   return PM_OK;
 }
@@ -400,16 +247,13 @@ int blocks_for_particles(const Plan* p) {
   return int(need < cap ? (need < 1 ? 1 : need) : cap);
 }
 
-int paint_launch(Plan* p, DriftMode mode, const PaintArgs& a, hipStream_t st) {
-  const int nch = a.unit + a.nw;
-  PM_HIP_CHECK(p, hipMemsetAsync(a.mesh, 0, size_t(nch) * p->ncell * p->real_bytes, st));
-  const bool s64 = p->cfg.state_dtype == PM_F64, m64 = p->cfg.mesh_dtype == PM_F64;
-  if (m64) return paint_typed<double, double>(p, mode, a, st);
-  if (s64) return paint_typed<double, float>(p, mode, a, st);
-  return paint_typed<float, float>(p, mode, a, st);
-}
-
 int gather_launch(Plan* p, GatherMode mode, const GatherArgs& a, hipStream_t st) {
+  if (!a.binned) {
+    // bin the particles by their current positions (no paint precedes this call)
+    PaintArgs b{};
+    b.s = a.s;
+    if (int rc = bin_launch(p, DRIFT_NONE, b, st)) return rc;
+  }
   const bool s64 = p->cfg.state_dtype == PM_F64, m64 = p->cfg.mesh_dtype == PM_F64;
   if (m64) return gather_typed<double, double>(p, mode, a, st);
   if (s64) return gather_typed<double, float>(p, mode, a, st);
@@ -446,7 +290,12 @@ int contrast_launch(Plan* p, void* mesh, hipStream_t st) {
 }
 
 int reduce_partials(Plan* p, int nblocks, const double* f, double* out, bool accumulate, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, st, p->partials, nblocks, f[0], f[1], f[2], f[3], out,
+  return reduce_buffer(p, p->partials, nblocks, f, out, accumulate, st);
+}
+
+int reduce_buffer(Plan* p, const double* buf, int64_t nblocks, const double* f, double* out, bool accumulate,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, st, buf, nblocks, f[0], f[1], f[2], f[3], out,
                      accumulate ? 1 : 0);
   PM_HIP_CHECK(p, hipGetLastError());
   return PM_OK;

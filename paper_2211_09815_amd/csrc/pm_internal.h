@@ -46,9 +46,11 @@ template <bool INV, typename C> __device__ __forceinline__ C cmul_mi(C a) {
 struct Timing {
   int kernel = 0;
   hipEvent_t ev[2 * 4096];
+  double bytes[4096];
   int nev = 0;
   bool created = false;
   double total_ms = 0.0;
+  double total_bytes = 0.0;
   int64_t launches = 0;
 };
 
@@ -69,7 +71,17 @@ struct Plan {
   void* tw = nullptr;                                      // twiddles (mesh dtype complex)
   double* partials = nullptr;                              // [kMaxPartials * 4]
   double* scalars = nullptr;                               // [16] device scalars
-  unsigned long long* fixed = nullptr;                     // deterministic paint accumulators
+  // paint binning (paint.hip): tiles of tile[0] x tile[1] x tile[2] cells
+  int tile[3] = {8, 8, 32};
+  int64_t ntiles = 0;
+  int halo_cells = 0;
+  unsigned* bin_counts = nullptr;   // [ntiles]
+  unsigned* bin_offs = nullptr;     // [ntiles + 1]
+  unsigned* bin_bsum = nullptr;     // [4 * kThreads]
+  void* bin_keys = nullptr;         // [N] (tile, rank)
+  unsigned* bin_list = nullptr;     // [N]
+  void* bin_halo = nullptr;         // [4][ntiles][halo_cells] mesh dtype
+  double* tile_partials = nullptr;  // [ntiles][4] per-tile reduction slots
   // lattice scratch for pm_lpt / pm_lpt_vjp (allocated lazily on first use)
   void* lreal[10] = {};
   void* lspec[2] = {};
@@ -89,9 +101,10 @@ int set_error(Plan* p, int code, const char* fmt, ...);
       return pmx::set_error((plan), PM_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
   } while (0)
 
-// kernel-launch bracketing for the timing facility
+// kernel-launch bracketing for the timing facility; `bytes` is the
+// algorithmic HBM traffic of the launch (what the operation must move)
 void timing_begin(Plan* p, int kernel, hipStream_t s);
-void timing_end(Plan* p, int kernel, hipStream_t s);
+void timing_end(Plan* p, int kernel, hipStream_t s, double bytes);
 
 inline int ilog2(int64_t v) { int l = 0; while ((int64_t(1) << l) < v) ++l; return l; }
 __host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
@@ -158,6 +171,10 @@ struct PaintArgs {
   double* partials;     // per-block partial sum of xi.p (adjoint drift)
 };
 int paint_launch(Plan* p, DriftMode mode, const PaintArgs& a, hipStream_t st);
+// tile binning only (drift + bins + per-tile lists), as done by paint_launch
+int bin_launch(Plan* p, DriftMode mode, const PaintArgs& a, hipStream_t st);
+// tile shape of the binned paint for a mesh
+void tile_dims(const int n[3], int tile[3], int64_t& ntiles, int& halo_cells);
 
 enum GatherMode {
   GATHER_PLAIN = 0,     // out[c] = readout(mesh[c])
@@ -176,6 +193,7 @@ struct GatherArgs {
   void* xi;             // adjoint kick target
   const void* cot;      // cotangent [3][N] (abar or pi)
   const void* acc_in;   // cached accelerations for the adjoint kick (optional)
+  bool binned;          // the plan's tile bins already match s (set after a paint of s)
   double K;
   double* partials;     // per-block partial of cot . a
 };
@@ -192,6 +210,8 @@ int contrast_launch(Plan* p, void* mesh, hipStream_t st);
 // scaled: out[o] (+)= sum_k f[k] * sum_b part[b*4+k] for up to 4 outputs
 int reduce_partials(Plan* p, int nblocks, const double* coef /*host [4]*/, double* out,
                     bool accumulate, hipStream_t st);
+int reduce_buffer(Plan* p, const double* buf, int64_t nblocks, const double* coef, double* out,
+                  bool accumulate, hipStream_t st);
 
 int blocks_for_particles(const Plan* p);
 

@@ -1,0 +1,93 @@
+// Device helpers shared by the tiled paint (paint.hip) and the tiled gather
+// (particles.hip).  The mesh is cut into tiles of tx * ty * tz cells; every
+// particle belongs to the tile that holds its CIC base node floor(x), so its
+// 8 CIC corners lie in the tile's "box" of (tx+1)(ty+1)(tz+1) cells.
+#pragma once
+
+#include "pm_internal.h"
+
+namespace pmx {
+
+constexpr int kBoxMax = 9 * 9 * 17;  // box cells for the largest tile (8 x 8 x 16)
+
+struct TileGeo {
+  int64_t N;
+  int np1, np2;
+  double r0, r1, r2, off;
+  int n0, n1, n2;
+  int64_t ncell;
+  int tx, ty, tz;        // tile dims (cells)
+  int ntx, nty, ntz;     // tiles per axis
+  int64_t ntiles;
+  int hc;                // halo cells per tile (the three upper faces of the box)
+};
+
+inline TileGeo tile_geo(const Plan* p) {
+  TileGeo g;
+  g.N = p->nptcl;
+  g.np1 = p->np[1];
+  g.np2 = p->np[2];
+  g.r0 = p->r[0];
+  g.r1 = p->r[1];
+  g.r2 = p->r[2];
+  g.off = p->cfg.lattice_offset;
+  g.n0 = p->n[0];
+  g.n1 = p->n[1];
+  g.n2 = p->n[2];
+  g.ncell = p->ncell;
+  g.tx = p->tile[0];
+  g.ty = p->tile[1];
+  g.tz = p->tile[2];
+  g.ntx = g.n0 / g.tx;
+  g.nty = g.n1 / g.ty;
+  g.ntz = g.n2 / g.tz;
+  g.ntiles = p->ntiles;
+  g.hc = p->halo_cells;
+  return g;
+}
+
+// Lagrangian position q = (i, j, k) r + offset of particle n (row-major lattice)
+__device__ __forceinline__ void lattice_pos(const TileGeo& g, int64_t n, double q[3]) {
+  const int64_t row = n / g.np2;
+  const int k = int(n - row * g.np2);
+  const int64_t i = row / g.np1;
+  const int j = int(row - i * g.np1);
+  q[0] = double(i) * g.r0 + g.off;
+  q[1] = double(j) * g.r1 + g.off;
+  q[2] = double(k) * g.r2 + g.off;
+}
+
+// tile coordinates and origin cell of a tile index
+__device__ __forceinline__ void tile_origin(const TileGeo& g, int64_t tile, int& o0, int& o1, int& o2) {
+  const int t2 = int(tile % g.ntz);
+  const int64_t t01 = tile / g.ntz;
+  const int t1 = int(t01 % g.nty);
+  const int t0 = int(t01 / g.nty);
+  o0 = t0 * g.tx;
+  o1 = t1 * g.ty;
+  o2 = t2 * g.tz;
+}
+
+// contiguous particle chunk of this workgroup (consecutive chunks on one XCD)
+__device__ __forceinline__ void chunk_of(int64_t N, int64_t& start, int64_t& end) {
+  const int64_t nb = gridDim.x;
+  const int64_t per = ((N + nb - 1) / nb + kThreads - 1) / kThreads * kThreads;
+  start = xcd_tile(blockIdx.x, nb) * per;
+  end = start + per < N ? start + per : N;
+}
+
+__device__ __forceinline__ double block_sum_d(double v) {
+  __shared__ double ws[kThreads / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) ws[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kThreads / 64; ++w) t += ws[w];
+  return t;
+}
+
+}  // namespace pmx
