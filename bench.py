@@ -30,14 +30,37 @@ WORKLOADS = {
 }
 HBM_PEAK_GBS = 8000.0
 
-KERNELS = {
-    "fft_lines": 4,
-    "fft_r2c_z": 2,
-    "fft_c2r_z": 3,
-    "fft_poisson": 5,
-    "paint": 1,
-    "gather": 6,
+# sources of each kernel family: a committed traffic summary under profiles/
+# applies only while these files are unchanged
+FAMILY_SOURCES = {
+    "gather": ["paper_2211_09815_amd/csrc/particles.hip", "paper_2211_09815_amd/csrc/tiles.h"],
+    "paint_tiles": ["paper_2211_09815_amd/csrc/paint.hip", "paper_2211_09815_amd/csrc/tiles.h"],
+    "bin": ["paper_2211_09815_amd/csrc/paint.hip", "paper_2211_09815_amd/csrc/tiles.h"],
+    "fft_lines": ["paper_2211_09815_amd/csrc/fft.hip"],
+    "fft_poisson": ["paper_2211_09815_amd/csrc/fft.hip"],
+    "fft_c2r_z": ["paper_2211_09815_amd/csrc/fft.hip"],
 }
+
+
+def measured_traffic(family):
+    """HBM bytes per launch of `family` from the rocprofv3 counter summary in
+    profiles/, or None if there is none or the kernel source changed since."""
+    import glob
+    import hashlib
+    import re
+    if family not in FAMILY_SOURCES:
+        return None
+    h = hashlib.sha256()
+    for f in FAMILY_SOURCES[family]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    digest = h.hexdigest()[:16]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            m = re.search(r"traffic_per_launch_bytes=([0-9.e+]+) family=(\w+) source_sha256=(\w+)", line)
+            if m and m.group(2) == family and m.group(3) == digest:
+                return float(m.group(1))
+    return None
+
 
 
 def log(msg):
@@ -83,8 +106,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="512", choices=sorted(WORKLOADS))
-    ap.add_argument("--kernel", default="fft_lines", choices=sorted(KERNELS),
-                    help="kernel family whose achieved bandwidth is reported")
+    ap.add_argument("--kernel", default="auto",
+                    help="kernel family for the roofline object (default: the one with the most time)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 1 GiB device copy first (reference for profiler byte counters)")
     ap.add_argument("--mesh-dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--state-dtype", default="f64", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -97,13 +122,22 @@ def main():
 
     import torch
 
-    from paper_2211_09815_amd import api, inputs
+    from paper_2211_09815_amd import _lib, api, inputs
     from paper_2211_09815_amd.simulate import SimConfig, Simulation
+    families = _lib.KERNEL_FAMILIES
 
     n, nm, box, nsteps, a0 = WORKLOADS[args.workload]
     mdt = torch.float32 if args.mesh_dtype == "f32" else torch.float64
     sdt = torch.float32 if args.state_dtype == "f32" else torch.float64
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 copies of 1 GiB done")
+        del x, y
     cfg = SimConfig(n, nm, box, a0, 1.0, nsteps, mdt, sdt)
     log("workload %s: %d^3 particles, %d^3 mesh, box %.0f, %d steps, mesh %s state %s"
         % (args.workload, n, nm, box, nsteps, args.mesh_dtype, args.state_dtype))
@@ -127,23 +161,28 @@ def main():
         torch.cuda.synchronize()
         log("warmup %d: %.3f s" % (w, time.perf_counter() - t0))
 
-    sim.plan.timing_enable(KERNELS[args.kernel], True)
+    sim.plan.timing_enable(families.values())
     torch.cuda.reset_peak_memory_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    kms = 0.0
-    kbytes = 0.0
-    klaunch = 0
+    fam = {k: [0.0, 0, 0.0] for k in families}
     for k in range(args.steps):
         J, g, th = sim.value_and_grad(omega, cosmo, target, tabs)
-        ms, nl, by = sim.plan.timing_read()   # waits for this pass's timed kernels
+        for name, kid in families.items():   # waits for this pass's timed kernels
+            fam[name] = list(sim.plan.timing_read(kid))
         log("step %d done (%.3f s elapsed)" % (k, time.perf_counter() - t0))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    kms, klaunch, kbytes = sim.plan.timing_read()
-    sim.plan.timing_enable(0, False)
+    sim.plan.timing_enable(())
     peak_mem = torch.cuda.max_memory_allocated()
-
+    kernels = {}
+    for name, (ms, nl, by) in fam.items():
+        if nl:
+            gbs = (by / 1e9) / (ms / 1e3)
+            kernels[name] = {"ms_per_step": ms / args.steps, "launches_per_step": nl / args.steps,
+                             "avg_launch_ms": ms / nl, "algorithmic_GBps": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
+    top = max(kernels, key=lambda k: kernels[k]["ms_per_step"]) if args.kernel == "auto" else args.kernel
+    kms, klaunch, kbytes = fam[top]
     ms_per_step = 1000.0 * elapsed / args.steps
     value = n ** 3 * nsteps / (elapsed / args.steps)
     achieved = (kbytes / 1e9) / (kms / 1e3) if kms > 0 else None
@@ -179,16 +218,18 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": args.kernel,
+            "kernel": top,
+            "symbol": _lib.KERNEL_SYMBOLS[top],
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": None,
+            "traffic": measured_traffic(top),
             "launches": klaunch,
             "avg_launch_ms": kms / klaunch if klaunch else None,
             "algorithmic_bytes_per_launch": kbytes / klaunch if klaunch else None,
         },
+        "kernels": kernels,
         "result": {"J": Jv, "dJ_dtheta": thv, "grad_omega_norm": gn, "finite": ok},
     }
     if not args.no_cpu_baseline:

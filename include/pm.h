@@ -259,20 +259,26 @@ int pm_lpt_vjp(pm_plan plan, const void* omega, const pm_cosmo* cosmo,
 int pm_check_finite(pm_plan plan, const void* x, int64_t n, int dtype, int* bad,
                     hipStream_t stream);
 
-/* Kernel timing: while enabled, every launch of the kernel family `kernel`
- * (PM_K_* below) is bracketed by HIP events on its stream; pm_timing_read
- * synchronises those events and returns the summed milliseconds, the number
- * of launches and the summed algorithmic bytes (the HBM traffic each launch
- * must at least move: inputs read once, outputs written once) since the last
- * pm_timing_enable.  At most 4096 launches are recorded between reads. */
-#define PM_K_PAINT     1
-#define PM_K_FFT_R2C_Z 2
-#define PM_K_FFT_C2R_Z 3
-#define PM_K_FFT_LINES 4
-#define PM_K_FFT_POISSON 5
-#define PM_K_GATHER    6
-int pm_timing_enable(pm_plan plan, int kernel, int on);
-int pm_timing_read(pm_plan plan, double* total_ms, int64_t* launches, double* total_bytes);
+/* Kernel timing.  pm_timing_enable(plan, mask) times every launch of the
+ * kernel families whose bit (1 << PM_K_*) is set in mask (0 switches timing
+ * off); each launch is bracketed by HIP events on the stream it runs on.
+ * pm_timing_read(plan, PM_K_*, ...) synchronises that family's events and
+ * returns, since the last pm_timing_enable, the summed milliseconds, the
+ * number of launches and the summed algorithmic bytes (the HBM traffic each
+ * launch must at least move: inputs read once, outputs written once).  At
+ * most 1024 launches per family are recorded between two reads; launches
+ * beyond that are counted and reported as a PM_EINVAL error by the read. */
+#define PM_K_BIN         1   /* paint: drift + tile binning                  */
+#define PM_K_FFT_R2C_Z   2   /* real-to-complex pass along z                 */
+#define PM_K_FFT_C2R_Z   3   /* complex-to-real pass along z                 */
+#define PM_K_FFT_LINES   4   /* strided complex passes along y and x         */
+#define PM_K_FFT_POISSON 5   /* first inverse pass with the Poisson kernel   */
+#define PM_K_GATHER      6   /* tiled CIC gather (+ kick / VJP)              */
+#define PM_K_SCATTER     7   /* paint: per-tile particle lists               */
+#define PM_K_PAINT_TILES 8   /* paint: LDS tile sums                         */
+#define PM_K_HALO        9   /* paint: halo faces into the mesh              */
+int pm_timing_enable(pm_plan plan, unsigned mask);
+int pm_timing_read(pm_plan plan, int kernel, double* total_ms, int64_t* launches, double* total_bytes);
 
 #ifdef __cplusplus
 }

@@ -20,12 +20,26 @@ PM_ENONFINITE = -6
 PM_F32 = 0
 PM_F64 = 1
 
-PM_K_PAINT = 1
+PM_K_BIN = 1
 PM_K_FFT_R2C_Z = 2
 PM_K_FFT_C2R_Z = 3
 PM_K_FFT_LINES = 4
 PM_K_FFT_POISSON = 5
 PM_K_GATHER = 6
+PM_K_SCATTER = 7
+PM_K_PAINT_TILES = 8
+PM_K_HALO = 9
+KERNEL_FAMILIES = {
+    "bin": PM_K_BIN, "scatter": PM_K_SCATTER, "paint_tiles": PM_K_PAINT_TILES, "halo_add": PM_K_HALO,
+    "fft_r2c_z": PM_K_FFT_R2C_Z, "fft_lines": PM_K_FFT_LINES, "fft_poisson": PM_K_FFT_POISSON,
+    "fft_c2r_z": PM_K_FFT_C2R_Z, "gather": PM_K_GATHER,
+}
+# device kernel symbol of each family (for matching profiler output)
+KERNEL_SYMBOLS = {
+    "bin": "k_bin", "scatter": "k_scatter", "paint_tiles": "k_paint_tiles", "halo_add": "k_halo_add",
+    "fft_r2c_z": "k_fft_r2c_z", "fft_lines": "k_fft_lines", "fft_poisson": "k_fft_x_fused",
+    "fft_c2r_z": "k_fft_c2r_z", "gather": "k_gather_tiles",
+}
 
 c_int = ctypes.c_int
 c_i32 = ctypes.c_int32
@@ -88,8 +102,8 @@ _PROTOS = {
     "pm_lpt": (c_int, [c_vp, c_vp, P(PmCosmo), P(PmIcCoef), P(PmState), c_vp]),
     "pm_lpt_vjp": (c_int, [c_vp, c_vp, P(PmCosmo), P(PmIcCoef), P(PmAdj), c_vp, c_vp, c_vp]),
     "pm_check_finite": (c_int, [c_vp, c_vp, c_i64, c_int, c_vp, c_vp]),
-    "pm_timing_enable": (c_int, [c_vp, c_int, c_int]),
-    "pm_timing_read": (c_int, [c_vp, P(c_dbl), P(c_i64), P(c_dbl)]),
+    "pm_timing_enable": (c_int, [c_vp, ctypes.c_uint]),
+    "pm_timing_read": (c_int, [c_vp, c_int, P(c_dbl), P(c_i64), P(c_dbl)]),
 }
 
 EXPORTED = tuple(_PROTOS.keys())

@@ -297,13 +297,18 @@ class Plan:
         self._c(lib().pm_check_finite(self._h, _ptr(x), x.numel(), _code(x.dtype), _ptr(bad), _stream()))
         return bad
 
-    def timing_enable(self, kernel, on=True):
-        self._c(lib().pm_timing_enable(self._h, int(kernel), int(bool(on))))
+    def timing_enable(self, kernels=()):
+        """Time the given PM_K_* kernel families (empty: switch timing off)."""
+        mask = 0
+        for k in kernels:
+            mask |= 1 << int(k)
+        self._c(lib().pm_timing_enable(self._h, mask))
 
-    def timing_read(self):
-        """(total milliseconds, launches, total algorithmic bytes) since enable."""
+    def timing_read(self, kernel):
+        """(total milliseconds, launches, total algorithmic bytes) of one
+        PM_K_* family since timing_enable."""
         ms = ctypes.c_double()
         n = ctypes.c_int64()
         b = ctypes.c_double()
-        self._c(lib().pm_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
+        self._c(lib().pm_timing_read(self._h, int(kernel), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
         return ms.value, n.value, b.value

@@ -28,18 +28,23 @@ int set_error(Plan* p, int code, const char* fmt, ...) {
 
 void timing_begin(Plan* p, int kernel, hipStream_t s) {
   Timing& t = p->timing;
-  if (t.kernel != kernel || !t.created) return;
-  if (t.nev + 2 > int(sizeof(t.ev) / sizeof(t.ev[0]))) return;
-  (void)hipEventRecord(t.ev[t.nev], s);
+  if (!t.created || kernel <= 0 || kernel >= kTimingFamilies || !(t.mask & (1u << kernel))) return;
+  TimingFamily& f = t.fam[kernel];
+  if (f.nev + 2 > 2 * kTimingSlots) return;
+  (void)hipEventRecord(f.ev[f.nev], s);
 }
 
 void timing_end(Plan* p, int kernel, hipStream_t s, double bytes) {
   Timing& t = p->timing;
-  if (t.kernel != kernel || !t.created) return;
-  if (t.nev + 2 > int(sizeof(t.ev) / sizeof(t.ev[0]))) return;
-  (void)hipEventRecord(t.ev[t.nev + 1], s);
-  t.bytes[t.nev / 2] = bytes;
-  t.nev += 2;
+  if (!t.created || kernel <= 0 || kernel >= kTimingFamilies || !(t.mask & (1u << kernel))) return;
+  TimingFamily& f = t.fam[kernel];
+  if (f.nev + 2 > 2 * kTimingSlots) {
+    ++f.dropped;
+    return;
+  }
+  (void)hipEventRecord(f.ev[f.nev + 1], s);
+  f.bytes[f.nev / 2] = bytes;
+  f.nev += 2;
 }
 
 }  // namespace pmx
@@ -315,7 +320,8 @@ int pm_plan_destroy(pm_plan h) {
   for (void* q : p->lreal) if (q) (void)hipFree(q);
   for (void* q : p->lspec) if (q) (void)hipFree(q);
   if (p->timing.created)
-    for (auto& e : p->timing.ev) (void)hipEventDestroy(e);
+    for (auto& f : p->timing.fam)
+      for (auto& e : f.ev) (void)hipEventDestroy(e);
   delete p;
   return PM_OK;
 }
@@ -649,37 +655,44 @@ int pm_check_finite(pm_plan h, const void* x, int64_t n, int dtype, int* bad, hi
   return PM_OK;
 }
 
-int pm_timing_enable(pm_plan h, int kernel, int on) {
+int pm_timing_enable(pm_plan h, unsigned mask) {
   CHECK_PLAN(h);
   Timing& t = p->timing;
-  if (!t.created) {
-    for (auto& e : t.ev)
-      if (hipEventCreate(&e) != hipSuccess) return set_error(p, PM_EDEVICE, "hipEventCreate failed");
+  if (mask && !t.created) {
+    for (int k = 1; k < kTimingFamilies; ++k)
+      for (auto& e : t.fam[k].ev)
+        if (hipEventCreate(&e) != hipSuccess) return set_error(p, PM_EDEVICE, "hipEventCreate failed");
     t.created = true;
   }
-  t.kernel = on ? kernel : 0;
-  t.nev = 0;
-  t.total_ms = 0.0;
-  t.total_bytes = 0.0;
-  t.launches = 0;
+  t.mask = mask;
+  for (auto& f : t.fam) {
+    f.nev = 0;
+    f.total_ms = 0.0;
+    f.total_bytes = 0.0;
+    f.launches = 0;
+    f.dropped = 0;
+  }
   return PM_OK;
 }
 
-int pm_timing_read(pm_plan h, double* total_ms, int64_t* launches, double* total_bytes) {
+int pm_timing_read(pm_plan h, int kernel, double* total_ms, int64_t* launches, double* total_bytes) {
   CHECK_PLAN(h);
-  Timing& t = p->timing;
-  for (int i = 0; i + 1 < t.nev; i += 2) {
+  if (kernel <= 0 || kernel >= kTimingFamilies) return set_error(p, PM_EINVAL, "unknown kernel family %d", kernel);
+  TimingFamily& f = p->timing.fam[kernel];
+  for (int i = 0; i + 1 < f.nev; i += 2) {
     float ms = 0.f;
-    PM_HIP_CHECK(p, hipEventSynchronize(t.ev[i + 1]));
-    PM_HIP_CHECK(p, hipEventElapsedTime(&ms, t.ev[i], t.ev[i + 1]));
-    t.total_ms += ms;
-    t.total_bytes += t.bytes[i / 2];
-    t.launches += 1;
+    PM_HIP_CHECK(p, hipEventSynchronize(f.ev[i + 1]));
+    PM_HIP_CHECK(p, hipEventElapsedTime(&ms, f.ev[i], f.ev[i + 1]));
+    f.total_ms += ms;
+    f.total_bytes += f.bytes[i / 2];
+    f.launches += 1;
   }
-  t.nev = 0;
-  if (total_ms) *total_ms = t.total_ms;
-  if (launches) *launches = t.launches;
-  if (total_bytes) *total_bytes = t.total_bytes;
+  f.nev = 0;
+  if (total_ms) *total_ms = f.total_ms;
+  if (launches) *launches = f.launches;
+  if (total_bytes) *total_bytes = f.total_bytes;
+  if (f.dropped) return set_error(p, PM_EINVAL, "%lld launches were not recorded (read more often)",
+                                  static_cast<long long>(f.dropped));
   return PM_OK;
 }
 

@@ -358,17 +358,28 @@ int bin_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
   b.counts = p->bin_counts;
   b.keys = static_cast<uint2*>(p->bin_keys);
   b.partials = in.partials;
+  timing_begin(p, PM_K_BIN, st);
   if (mode == DRIFT_FWD) hipLaunchKernelGGL((k_bin<S, T, DRIFT_FWD>), dim3(pblocks), block, 0, st, b);
   else if (mode == DRIFT_ADJ) hipLaunchKernelGGL((k_bin<S, T, DRIFT_ADJ>), dim3(pblocks), block, 0, st, b);
   else hipLaunchKernelGGL((k_bin<S, T, DRIFT_NONE>), dim3(pblocks), block, 0, st, b);
+  {
+    // s read (+ p read, s write; adjoint: xi read, pi read/write), key write
+    const double N = double(g.N), sb = sizeof(S), mb = sizeof(T);
+    double bytes = 3 * N * sb + 8 * N;
+    if (mode == DRIFT_FWD) bytes += 6 * N * sb;
+    if (mode == DRIFT_ADJ) bytes += 6 * N * sb + 9 * N * mb;
+    timing_end(p, PM_K_BIN, st, bytes);
+  }
   const int64_t nt = g.ntiles;
   const int nsb = int((nt + 4 * kThreads - 1) / (4 * kThreads));
   hipLaunchKernelGGL(k_scan_local, dim3(nsb), block, 0, st, p->bin_counts, p->bin_offs, p->bin_bsum, nt);
   hipLaunchKernelGGL(k_scan_blocks, dim3(1), block, 0, st, p->bin_bsum, nsb);
   hipLaunchKernelGGL(k_scan_add, dim3(unsigned((nt + 1 + kThreads - 1) / kThreads)), block, 0, st, p->bin_offs,
                      p->bin_bsum, nt, unsigned(g.N));
+  timing_begin(p, PM_K_SCATTER, st);
   hipLaunchKernelGGL(k_scatter, dim3(pblocks), block, 0, st, static_cast<const uint2*>(p->bin_keys), p->bin_offs,
                      p->bin_list, g.N);
+  timing_end(p, PM_K_SCATTER, st, 12.0 * double(g.N));  // key read, list write
   PM_HIP_CHECK(p, hipGetLastError());
   return PM_OK;
 }
@@ -379,7 +390,6 @@ int paint_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
   const int nch = in.unit + in.nw;
   const dim3 block(kThreads);
   const int64_t nt = g.ntiles;
-  timing_begin(p, PM_K_PAINT, st);
   if (int rc = bin_typed<S, T>(p, mode, in, st)) return rc;
   const S* s = static_cast<const S*>(in.s);
   // in the adjoint drift the weighted channels are the updated pi
@@ -387,10 +397,22 @@ int paint_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
   T* mesh = static_cast<T*>(in.mesh);
   T* halo = static_cast<T*>(p->bin_halo);
   const dim3 tg{unsigned(nt), 1, 1};
+  const double N = double(g.N), sb = sizeof(S), mb = sizeof(T);
+  const double core_bytes = double(nch) * double(p->ncell) * mb;
+  const double halo_bytes = double(nch) * double(nt) * g.hc * mb;
+  // tiles: list + s + weights read, core and halo faces written
+  const double tile_bytes = 4 * N + 3 * N * sb + double(nch - in.unit) * N * mb + core_bytes + halo_bytes;
+  // halo: halo faces read, the lower-face core cells read and written
+  const double lower = double(g.ty * g.tz + (g.tx - 1) * g.tz + (g.tx - 1) * (g.ty - 1)) / (g.tx * g.ty * g.tz);
+  const double hadd_bytes = halo_bytes + 2.0 * lower * core_bytes;
 #define PM_TILES(NCH, UNIT)                                                                                \
+  timing_begin(p, PM_K_PAINT_TILES, st);                                                                   \
   hipLaunchKernelGGL((k_paint_tiles<S, T, NCH, UNIT>), tg, block, 0, st, g, s, w, p->bin_offs, p->bin_list, \
                      mesh, halo);                                                                          \
-  hipLaunchKernelGGL((k_halo_add<T, NCH>), tg, block, 0, st, g, mesh, halo)
+  timing_end(p, PM_K_PAINT_TILES, st, tile_bytes);                                                         \
+  timing_begin(p, PM_K_HALO, st);                                                                          \
+  hipLaunchKernelGGL((k_halo_add<T, NCH>), tg, block, 0, st, g, mesh, halo);                               \
+  timing_end(p, PM_K_HALO, st, hadd_bytes)
   if (in.unit) {
     switch (nch) {
       case 1: PM_TILES(1, true); break;
@@ -407,14 +429,7 @@ int paint_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
     }
   }
 #undef PM_TILES
-  {
-    // algorithmic traffic: particle state (+ drift and weights) and one write of each mesh channel
-    const double N = double(p->nptcl), sb = sizeof(S), mb = sizeof(T);
-    double bytes = 3 * N * sb + double(nch) * double(p->ncell) * mb + double(in.nw) * N * mb;
-    if (mode == DRIFT_FWD) bytes += 6 * N * sb;
-    if (mode == DRIFT_ADJ) bytes += 6 * N * sb + 9 * N * mb - double(in.nw) * N * mb;
-    timing_end(p, PM_K_PAINT, st, bytes);
-  }
+  (void)sb;
   PM_HIP_CHECK(p, hipGetLastError());
   return PM_OK;
 }

@@ -43,15 +43,21 @@ template <bool INV, typename C> __device__ __forceinline__ C cmul_mi(C a) {
 // ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
-struct Timing {
-  int kernel = 0;
-  hipEvent_t ev[2 * 4096];
-  double bytes[4096];
+constexpr int kTimingFamilies = 10;    // PM_K_* ids are 1..9
+constexpr int kTimingSlots = 1024;     // launches recorded per family between reads
+struct TimingFamily {
+  hipEvent_t ev[2 * kTimingSlots];
+  double bytes[kTimingSlots];
   int nev = 0;
-  bool created = false;
   double total_ms = 0.0;
   double total_bytes = 0.0;
   int64_t launches = 0;
+  int64_t dropped = 0;
+};
+struct Timing {
+  unsigned mask = 0;                   // bit k set: family k is timed
+  bool created = false;
+  TimingFamily fam[kTimingFamilies];
 };
 
 struct Plan {
