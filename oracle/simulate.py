@@ -101,18 +101,21 @@ class FixedThetaObjective:
         return J
 
 
-def value_and_grad(omega, cfg, target, mode="stored"):
+def value_and_grad(omega, cfg, target, mode="stored", final_state_out=None):
     """J and (dJ/domega, dJ/dOmega_m, dJ/dsigma8).
 
     mode = "stored": discrete adjoint along the stored trajectory (plain chain
     rule, Sec. 4.1); mode = "reverse": adjoint with reverse-time integration
-    (eq. KDFKO_adj)."""
+    (eq. KDFKO_adj).  If `final_state_out` is a dict, the final forward state
+    is stored in it as "s" and "p" ((N, 3) arrays)."""
     q = lattice(cfg)
     s0, p0 = initial_state(omega, cfg)
     om = cfg.cosmo.omega_m
     coefs, dcoefs = cosmology.step_coefficients_with_derivative(cfg.a_grid(), om)
     F = integrate.ForceModel(cfg.mesh_shape, cfg.n_particles, om)
     s, p, a, traj = integrate.forward(q, s0, p0, coefs, F, store=(mode == "stored"))
+    if final_state_out is not None:
+        final_state_out["s"], final_state_out["p"] = s.copy(), p.copy()
     J, xbar = objective.density_mse(q + s, target, cfg.n_particles)
     pbar = np.zeros_like(xbar)
     if mode == "stored":

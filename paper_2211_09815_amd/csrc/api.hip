@@ -141,23 +141,17 @@ double mass_coef(const Plan* p, double coef) { return coef * double(p->ncell) / 
 template <typename T>
 int force_fields(Plan* p, double coef, hipStream_t st) {
   // mesh0 holds the painted mass; leaves g_0..2 in mesh0..2
-  const FftShape s = mesh_shape(p);
-  int rc = fft_r2c_3d<T>(p, s, mesh_ptr<T>(p, 0), spec_ptr<T>(p, 0), 1, p->ncell, p->nspec, st);
-  if (rc) return rc;
+  T* reals[3] = {mesh_ptr<T>(p, 0), mesh_ptr<T>(p, 1), mesh_ptr<T>(p, 2)};
   cplx<T>* specs[3] = {spec_ptr<T>(p, 0), spec_ptr<T>(p, 1), spec_ptr<T>(p, 2)};
-  T* outs[3] = {mesh_ptr<T>(p, 0), mesh_ptr<T>(p, 1), mesh_ptr<T>(p, 2)};
-  return fft_c2r_fused<T>(p, s, SPEC_GRAD3, specs, outs, T(mass_coef(p, coef)), st);
+  return fft_spectral_op<T>(p, mesh_shape(p), SPEC_GRAD3, reals, specs, T(mass_coef(p, coef)), st);
 }
 
 template <typename T>
 int vjp_fields(Plan* p, double coef, hipStream_t st) {
   // mesh0..3 hold [rho, gbar_x, gbar_y, gbar_z]; leaves [g_x, g_y, g_z, rhobar]
-  const FftShape s = mesh_shape(p);
-  int rc = fft_r2c_3d<T>(p, s, mesh_ptr<T>(p, 0), spec_ptr<T>(p, 0), 4, p->ncell, p->nspec, st);
-  if (rc) return rc;
+  T* reals[4] = {mesh_ptr<T>(p, 0), mesh_ptr<T>(p, 1), mesh_ptr<T>(p, 2), mesh_ptr<T>(p, 3)};
   cplx<T>* specs[4] = {spec_ptr<T>(p, 0), spec_ptr<T>(p, 1), spec_ptr<T>(p, 2), spec_ptr<T>(p, 3)};
-  T* outs[4] = {mesh_ptr<T>(p, 0), mesh_ptr<T>(p, 1), mesh_ptr<T>(p, 2), mesh_ptr<T>(p, 3)};
-  return fft_c2r_fused<T>(p, s, SPEC_ADJ4, specs, outs, T(mass_coef(p, coef)), st);
+  return fft_spectral_op<T>(p, mesh_shape(p), SPEC_ADJ4, reals, specs, T(mass_coef(p, coef)), st);
 }
 
 int force_fields_any(Plan* p, double coef, hipStream_t st) {

@@ -135,7 +135,8 @@ struct FftShape {
   int n0, n1, n2;     // real shape, each a power of two in [4, 1024]
 };
 
-// Fused multipliers applied inside the first inverse pass along axis 0.
+// Spectral multipliers of the force path, applied between the forward and
+// inverse transforms along axis 0 (T_j = i k_j coef / k^2).
 enum SpecOp {
   SPEC_NONE = 0,
   SPEC_GRAD3 = 1,     // out_j = T_j * in0, j = 0..2 (Poisson gradient)
@@ -149,10 +150,13 @@ int fft_r2c_3d(Plan* p, const FftShape& s, const T* in, cplx<T>* out, int batch,
 template <typename T>
 int fft_c2r_3d(Plan* p, const FftShape& s, cplx<T>* in, T* out, int batch,
                int64_t in_stride, int64_t out_stride, T scale, hipStream_t st);
-// inverse with fused spectral multipliers (Poisson gradient / adjoint combine)
+// real fields -> spectral multipliers -> real fields, in place:
+//   GRAD3: reals[0] -> reals[0..2] = g_0..2;
+//   ADJ4:  reals[0..3] = [rho, gbar_0..2] -> [g_0..2, rhobar].
+// specs[0..3] are half-spectrum scratch buffers (clobbered).
 template <typename T>
-int fft_c2r_fused(Plan* p, const FftShape& s, SpecOp op, cplx<T>* const* specs, T* const* outs,
-                  T coef, hipStream_t st);
+int fft_spectral_op(Plan* p, const FftShape& s, SpecOp op, T* const* reals, cplx<T>* const* specs,
+                    T coef, hipStream_t st);
 // elementwise spectral multiplies used by the standalone Poisson call
 template <typename T>
 int poisson_grad_spec(Plan* p, const FftShape& s, const cplx<T>* in, cplx<T>* out, T coef,
