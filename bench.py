@@ -17,6 +17,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -36,9 +38,12 @@ FAMILY_SOURCES = {
     "gather": ["paper_2211_09815_amd/csrc/particles.hip", "paper_2211_09815_amd/csrc/tiles.h"],
     "paint_tiles": ["paper_2211_09815_amd/csrc/paint.hip", "paper_2211_09815_amd/csrc/tiles.h"],
     "bin": ["paper_2211_09815_amd/csrc/paint.hip", "paper_2211_09815_amd/csrc/tiles.h"],
-    "fft_lines": ["paper_2211_09815_amd/csrc/fft.hip"],
-    "fft_poisson": ["paper_2211_09815_amd/csrc/fft.hip"],
-    "fft_c2r_z": ["paper_2211_09815_amd/csrc/fft.hip"],
+    "scatter": ["paper_2211_09815_amd/csrc/paint.hip", "paper_2211_09815_amd/csrc/tiles.h"],
+    "halo_add": ["paper_2211_09815_amd/csrc/paint.hip", "paper_2211_09815_amd/csrc/tiles.h"],
+    "fft_lines": ["paper_2211_09815_amd/csrc/fft_lines.hip", "paper_2211_09815_amd/csrc/fft_core.h"],
+    "fft_poisson": ["paper_2211_09815_amd/csrc/fft_fused.hip", "paper_2211_09815_amd/csrc/fft_core.h"],
+    "fft_r2c_z": ["paper_2211_09815_amd/csrc/fft_z.hip", "paper_2211_09815_amd/csrc/fft_core.h"],
+    "fft_c2r_z": ["paper_2211_09815_amd/csrc/fft_z.hip", "paper_2211_09815_amd/csrc/fft_core.h"],
 }
 
 
@@ -100,6 +105,235 @@ def cpu_baseline(seconds_hint=20.0):
     }
 
 
+def _setup_run(n, nm, box, nsteps, a0, mdt, sdt, seed=None):
+    import torch
+    from paper_2211_09815_amd import api, inputs
+    from paper_2211_09815_amd.simulate import SimConfig, Simulation
+    sim = Simulation(SimConfig(n, nm, box, a0, 1.0, nsteps, mdt, sdt))
+    cosmo = api.Cosmology()
+    tabs = sim.tables(cosmo)
+    npdt = "float32" if mdt == torch.float32 else "float64"
+    omega = torch.as_tensor(inputs.white_noise(n, inputs.SEED_RUN if seed is None else seed, dtype=npdt),
+                            device="cuda")
+    return sim, cosmo, tabs, omega
+
+
+def _timed_pass(sim, omega, cosmo, target, tabs):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, g, th = sim.value_and_grad(omega, cosmo, target, tabs)
+    torch.cuda.synchronize()
+    return J, g, th, time.perf_counter() - t0
+
+
+def _rel_l2(a, b):
+    import torch
+    return float(torch.linalg.vector_norm((a.double() - b.double()).reshape(-1))
+                 / torch.linalg.vector_norm(b.double().reshape(-1)))
+
+
+def fp64_reference(args, target64, g_mixed, th_mixed):
+    """One all-FP64 pass on the same workload (same white noise and target):
+    its throughput and the relative L2 error of the benchmarked gradients."""
+    import torch
+    n, nm, box, nsteps, a0 = WORKLOADS[args.workload]
+    log("all-FP64 reference pass")
+    sim, cosmo, tabs, omega = _setup_run(n, nm, box, nsteps, a0, torch.float64, torch.float64)
+    _timed_pass(sim, omega, cosmo, target64, tabs)  # warm-up
+    J, g, th, dt = _timed_pass(sim, omega, cosmo, target64, tabs)
+    return {
+        "fp64_reference": {"value": n ** 3 * nsteps / dt, "unit": "particle-steps/s", "ms_per_step": 1000 * dt,
+                           "J": float(J.cpu()[0]), "dJ_dtheta": th.cpu().tolist()},
+        "grad_omega_rel_l2_vs_fp64": _rel_l2(g_mixed, g),
+        "dJ_dtheta_rel_err_vs_fp64": [abs(float(a) - float(b)) / abs(float(b)) for a, b in zip(th_mixed.cpu(), th.cpu())],
+    }
+
+
+def study_precision(args):
+    """FP32 throughout vs FP32 mesh + FP64 state vs all-FP64 at one workload:
+    reversibility of the recovered initial state, gradient error against the
+    FP64 run, throughput, and peak memory against the number of steps."""
+    import torch
+    from paper_2211_09815_amd import inputs
+    n, nm, box, nsteps, a0 = WORKLOADS[args.workload]
+    modes = [("f64", "f64"), ("f32", "f64"), ("f32", "f32")]
+    dt_of = {"f32": torch.float32, "f64": torch.float64}
+    # target: the all-FP64 run of the target seed
+    sim, cosmo, tabs, omega_t = _setup_run(n, nm, box, nsteps, a0, torch.float64, torch.float64,
+                                           seed=inputs.SEED_TARGET)
+    sim.forward(omega_t, cosmo, tabs)
+    target64 = sim.plan.density(sim.s).clone()
+    del sim, omega_t
+    torch.cuda.empty_cache()
+    res = {}
+    grads = {}
+    for mdt, sdt in modes:
+        key = "%s-mesh/%s-state" % (mdt, sdt)
+        log("precision: " + key)
+        sim, cosmo, tabs, omega = _setup_run(n, nm, box, nsteps, a0, dt_of[mdt], dt_of[sdt])
+        target = target64.to(dt_of[mdt])
+        coefs, ic = tabs
+        st0 = {"s": torch.zeros_like(sim.s), "p": torch.zeros_like(sim.p), "acc": None}
+        sim.plan.lpt(omega, cosmo, ic, st0)
+        _timed_pass(sim, omega, cosmo, target, tabs)  # warm-up
+        J, g, th, dt = _timed_pass(sim, omega, cosmo, target, tabs)
+        s0, p0 = st0["s"].double(), st0["p"].double()
+        ds = (sim.s.double() - s0)
+        dp = (sim.p.double() - p0)
+        res[key] = {
+            "particle_steps_per_s": n ** 3 * nsteps / dt,
+            "ms_per_pass": 1000 * dt,
+            "J": float(J.cpu()[0]),
+            "dJ_dtheta": th.cpu().tolist(),
+            "reversibility": {
+                "s0_rms_err_cells": float(ds.pow(2).mean().sqrt()),
+                "s0_rms_err_over_std": float(ds.pow(2).mean().sqrt() / s0.std()),
+                "s0_max_err_cells": float(ds.abs().max()),
+                "p0_rms_err_over_std": float(dp.pow(2).mean().sqrt() / p0.std()),
+            },
+        }
+        grads[key] = (g.double().clone(), th.clone())
+        del sim, omega, target, st0, s0, p0, ds, dp, g
+        torch.cuda.empty_cache()
+    g64, th64 = grads["f64-mesh/f64-state"]
+    for key, (g, th) in grads.items():
+        res[key]["grad_omega_rel_l2_vs_fp64"] = _rel_l2(g, g64)
+        res[key]["dJ_dtheta_rel_err_vs_fp64"] = [abs(float(a) - float(b)) / abs(float(b))
+                                                 for a, b in zip(th.cpu(), th64.cpu())]
+    del grads, g64
+    torch.cuda.empty_cache()
+    # adjoint memory against the number of steps (mixed precision)
+    mem = {}
+    for steps in (10, 31, 63):
+        log("memory: %d steps" % steps)
+        torch.cuda.reset_peak_memory_stats()
+        base = torch.cuda.memory_allocated()
+        sim, cosmo, tabs, omega = _setup_run(n, nm, box, steps, a0, torch.float32, torch.float64)
+        sim.value_and_grad(omega, cosmo, target64.float(), tabs)
+        torch.cuda.synchronize()
+        ws = sim.plan.workspace_bytes((nm,) * 3, (n,) * 3, torch.float32, torch.float64)
+        mem[str(steps)] = {"torch_peak_gb": (torch.cuda.max_memory_allocated() - base) / 1e9,
+                           "plan_workspace_gb": ws / 1e9,
+                           "total_gb": (torch.cuda.max_memory_allocated() - base + ws) / 1e9}
+        del sim, omega
+        torch.cuda.empty_cache()
+    return {"study": "precision", "workload": "%d^3 particles, %d^3 mesh, %.0f Mpc/h, %d steps a=%.5f..1"
+            % (n, nm, box, nsteps, a0), "modes": res, "peak_memory_vs_steps": mem,
+            "reversibility_metric": "recovered minus true 2LPT initial state after the reverse-time pass; "
+                                    "rms over all particles and axes, in cells and relative to the std of s0 / p0"}
+
+
+def study_force(args, reps=10):
+    """Single force and force VJP, stage by stage: 256^3 particles displaced by
+    2LPT at a = 0.5, painted to a 512^3 FP32 mesh in a 512 Mpc/h box; the VJP
+    uses a seeded Gaussian cotangent.  Algorithmic bytes per stage: particles
+    and meshes read or written once (FP32 displacements and fields)."""
+    import torch
+    from paper_2211_09815_amd import _lib, api, inputs
+    n, nm, box = 256, 512, 512.0
+    plan = api.Plan(nm, n, box=box, mesh_dtype=torch.float32, state_dtype=torch.float32)
+    cosmo = api.Cosmology()
+    _, ic = api.tables(cosmo, [0.5, 1.0])
+    omega = torch.as_tensor(inputs.white_noise(n, inputs.SEED_RUN, dtype="float32"), device="cuda")
+    st = {"s": torch.zeros((3, n ** 3), dtype=torch.float32, device="cuda"),
+          "p": torch.zeros((3, n ** 3), dtype=torch.float32, device="cuda"), "acc": None}
+    plan.lpt(omega, cosmo, ic, st)
+    s = st["s"]
+    cot = torch.as_tensor(inputs.normal((3, n ** 3), inputs.SEED_COTANGENT, dtype=np.float32), device="cuda")
+    coef = 1.5 * cosmo.omega_m
+    N, Nc = n ** 3, nm ** 3
+    Ns = nm * nm * (nm // 2 + 1)
+    f4, c8 = 4.0, 8.0
+    rho = plan.paint(s)
+    dk = plan.fft_r2c(rho)
+    gk = plan.poisson_grad(dk[0], coef)
+    g = plan.fft_c2r(gk)
+    stages = [
+        ("paint", lambda: plan.paint(s, out=rho), N * 12 + Nc * f4),
+        ("r2c", lambda: plan.fft_r2c(rho, out=dk), Nc * f4 + Ns * c8),
+        ("poisson_grad (unfused)", lambda: plan.poisson_grad(dk[0], coef, out=gk), 4 * Ns * c8),
+        # the inverse transform works in place on its input; the timing of a
+        # transform does not depend on the values it is given
+        ("3x c2r", lambda: plan.fft_c2r(gk, out=g, destroy_input=True), 3 * (Ns * c8 + Nc * f4)),
+        ("readout (3 fields)", lambda: plan.readout(s, g), N * 12 + 3 * Nc * f4 + 3 * N * f4),
+        ("force (fused: paint, r2c, gradient in the x pass, 3x c2r, readout)", lambda: plan.force(s, coef),
+         N * 12 + Nc * f4 + (Nc * f4 + Ns * c8) + 3 * (Ns * c8 + Nc * f4) + 3 * Nc * f4 + 3 * N * f4),
+        ("force VJP (4-channel paint, 4x r2c, combine in the x pass, 4x c2r, 4-field gather)",
+         lambda: plan.force_vjp(s, cot, coef, want_acc=False),
+         N * 12 + 3 * N * f4 + 4 * Nc * f4 + 4 * (Nc * f4 + Ns * c8) + 4 * (Ns * c8 + Nc * f4) + 4 * Nc * f4
+         + N * 12 + 3 * N * f4 + 3 * N * f4),
+    ]
+    rows = []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for name, fn, by in stages:
+        fn()
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        rows.append({"stage": name, "ms": ms, "algorithmic_GB": by / 1e9, "GBps": by / 1e9 / (ms / 1e3),
+                     "frac_of_peak": by / 1e9 / (ms / 1e3) / HBM_PEAK_GBS})
+    # kernel families inside the fused force and the VJP
+    fams = {}
+    for label, fn in (("force", lambda: plan.force(s, coef)),
+                      ("force_vjp", lambda: plan.force_vjp(s, cot, coef, want_acc=False))):
+        plan.timing_enable(_lib.KERNEL_FAMILIES.values())
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        fams[label] = {}
+        for fam, kid in _lib.KERNEL_FAMILIES.items():
+            ms, nl, b = plan.timing_read(kid)
+            if nl:
+                fams[label][fam] = {"ms": ms / reps, "GBps": (b / 1e9) / (ms / 1e3)}
+        plan.timing_enable(())
+    return {"study": "force", "workload": "256^3 particles (2LPT at a=0.5), 512^3 FP32 mesh, 512 Mpc/h, "
+            "FP32 displacements; cotangent seed %d" % inputs.SEED_COTANGENT, "reps": reps, "stages": rows,
+            "kernel_families": fams, "peak_GBps": HBM_PEAK_GBS}
+
+
+def study_fd_theta(args, hs=(1e-3, 3e-4)):
+    """dJ/d(Omega_m, sigma8) from the adjoint pass against central finite
+    differences of the forward model (two step sizes, relative to theta)."""
+    import torch
+    from paper_2211_09815_amd import inputs
+    n, nm, box, nsteps, a0 = WORKLOADS[args.workload]
+    mdt = torch.float32 if args.mesh_dtype == "f32" else torch.float64
+    sdt = torch.float32 if args.state_dtype == "f32" else torch.float64
+    sim, cosmo, tabs, omega_t = _setup_run(n, nm, box, nsteps, a0, mdt, sdt, seed=inputs.SEED_TARGET)
+    log("fd-theta: target run")
+    sim.forward(omega_t, cosmo, tabs)
+    target = sim.plan.density(sim.s).clone()
+    del omega_t
+    npdt = "float32" if mdt == torch.float32 else "float64"
+    omega = torch.as_tensor(inputs.white_noise(n, inputs.SEED_RUN, dtype=npdt), device="cuda")
+    log("fd-theta: adjoint pass")
+    J, g, th, dt = _timed_pass(sim, omega, cosmo, target, tabs)
+    del g
+    fd = {}
+    for name, idx in (("omega_m", 0), ("sigma8", 1)):
+        base = getattr(cosmo, name)
+        fd[name] = []
+        for h in hs:
+            vals = []
+            for sg in (1, -1):
+                c = cosmo.replace(**{name: base * (1 + sg * h)})
+                sim.forward(omega, c)
+                Jp, _ = sim.plan.density_mse(sim.s, target, want_grad=False)
+                vals.append(float(Jp.cpu()[0]))
+                log("fd-theta: %s h=%g sign=%d J=%.12e" % (name, h, sg, vals[-1]))
+            d = (vals[0] - vals[1]) / (2 * h * base)
+            fd[name].append({"h_rel": h, "fd": d, "adjoint": float(th[idx]),
+                             "rel_diff": abs(d - float(th[idx])) / abs(d)})
+    return {"study": "fd-theta", "workload": "%d^3 particles, %d^3 mesh, %.0f Mpc/h, %d steps a=%.5f..1, %s-mesh/%s-state"
+            % (n, nm, box, nsteps, a0, args.mesh_dtype, args.state_dtype), "J": float(J.cpu()[0]),
+            "adjoint_pass_s": dt, "particle_steps_per_s": n ** 3 * nsteps / dt, "fd": fd}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +347,13 @@ def main():
     ap.add_argument("--mesh-dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--state-dtype", default="f64", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-ref", action="store_true",
+                    help="skip the all-FP64 reference pass used for the gradient rel-L2")
+    ap.add_argument("--study", choices=["precision", "force", "fd-theta"],
+                    help="print a study instead of the benchmark line: precision = FP32 / mixed / FP64 "
+                         "reversibility, gradient error and memory vs steps; force = single force and VJP "
+                         "per stage at 256^3 particles on a 512^3 mesh; fd-theta = dJ/dtheta against central "
+                         "differences")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -125,6 +366,10 @@ def main():
     from paper_2211_09815_amd import _lib, api, inputs
     from paper_2211_09815_amd.simulate import SimConfig, Simulation
     families = _lib.KERNEL_FAMILIES
+    if args.study:
+        out = {"precision": study_precision, "force": study_force, "fd-theta": study_fd_theta}[args.study](args)
+        print(json.dumps(out), flush=True)
+        return
 
     n, nm, box, nsteps, a0 = WORKLOADS[args.workload]
     mdt = torch.float32 if args.mesh_dtype == "f32" else torch.float64
@@ -175,6 +420,7 @@ def main():
     elapsed = time.perf_counter() - t0
     sim.plan.timing_enable(())
     peak_mem = torch.cuda.max_memory_allocated()
+    plan_ws = sim.plan.workspace_bytes((nm,) * 3, (n,) * 3, mdt, sdt)
     kernels = {}
     for name, (ms, nl, by) in fam.items():
         if nl:
@@ -191,6 +437,12 @@ def main():
     gn = float(torch.linalg.vector_norm(g.double()).cpu())
     ok = math.isfinite(Jv) and all(math.isfinite(x) for x in thv) and math.isfinite(gn)
     log("J %.6e  |dJ/domega| %.6e  dJ/dtheta %s  finite %s" % (Jv, gn, thv, ok))
+    ref = None
+    if not args.no_fp64_ref and (args.mesh_dtype, args.state_dtype) != ("f64", "f64"):
+        g_keep, th_keep = g.double().clone(), th.clone()
+        del sim
+        torch.cuda.empty_cache()
+        ref = fp64_reference(args, target.double(), g_keep, th_keep)
 
     out = {
         "metric": "particle-steps/s for forward+adjoint at %d^3" % n,
@@ -214,7 +466,8 @@ def main():
             "kdk_steps": nsteps,
             "mesh_dtype": args.mesh_dtype,
             "state_dtype": args.state_dtype,
-            "peak_mem_gb": peak_mem / 1e9,
+            "peak_mem_gb": (peak_mem + plan_ws) / 1e9,
+            "peak_mem_note": "torch allocator peak plus the plan's own workspace",
         },
         "roofline": {
             "bound": "hbm",
@@ -232,6 +485,8 @@ def main():
         "kernels": kernels,
         "result": {"J": Jv, "dJ_dtheta": thv, "grad_omega_norm": gn, "finite": ok},
     }
+    if ref is not None:
+        out["result"].update(ref)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline()

@@ -32,17 +32,19 @@
  *  - Ownership: the caller owns every pointer argument; all pointers except
  *    host-struct arguments are DEVICE pointers on the plan's device.  The
  *    plan owns only its scratch (meshes, spectra, twiddles, reduction space),
- *    allocated once in pm_plan_create and sized by pm_workspace_bytes.  Hot
- *    calls allocate nothing.
+ *    allocated once in pm_plan_create, plus the 2LPT lattice scratch that
+ *    the first pm_lpt / pm_lpt_vjp call allocates; pm_workspace_bytes
+ *    reports both.  The other calls allocate nothing.
  *  - Streams: every call is asynchronous on the given stream (0 = default).
  *    Scalars reported on the device (J, coef_bar, theta_bar) are ready after
  *    the stream is synchronised.  A plan is not thread-safe; calls made with
  *    one plan on different streams must be ordered by the caller.
- *  - Determinism: with cfg.deterministic = 0 the paint accumulates with
- *    floating-point atomics, so results differ between runs at the rounding
- *    level (the paper's Table rep discusses the same effect on GPUs).  With
- *    cfg.deterministic = 1 the paint accumulates in 64-bit fixed point and
- *    every call is bitwise reproducible.
+ *  - Determinism: the paint sums each mesh tile in 64-bit fixed point with
+ *    a per-tile binary scale, so painted meshes, forces and every particle
+ *    output are bitwise reproducible (GPU float atomics would not be; the
+ *    paper's Table rep discusses that effect).  Only the FP64 per-tile
+ *    partial sums behind theta_bar depend on the order of particles within
+ *    a tile, at the 1e-15 relative level.
  */
 #ifndef PM_H
 #define PM_H
@@ -78,16 +80,21 @@ typedef struct {
     double  lattice_offset; /* offset of the lattice in mesh cells (all axes)  */
     int32_t mesh_dtype;     /* PM_F32 or PM_F64: mesh, FFT, force, adjoint     */
     int32_t state_dtype;    /* PM_F32 or PM_F64: s and p accumulators          */
-    int32_t deterministic;  /* 1: fixed-point paint, bitwise reproducible      */
+    int32_t deterministic;  /* accepted for compatibility: the paint always    */
+                            /* sums in 64-bit fixed point, so every mesh and   */
+                            /* particle output is bitwise reproducible         */
 } pm_config;
 
 /* Creates a plan on the current HIP device and allocates its scratch.
  * Errors: PM_EINVAL (NULL), PM_ESHAPE (mesh not a power of two in 4..1024,
- * ptcl < 1), PM_EUNSUPPORTED (mesh_dtype F32 with state_dtype F64 is allowed;
- * mesh F64 with state F32 is not), PM_ENOMEM, PM_EDEVICE. */
+ * a ptcl side outside 1..65536, more than 2^31 particles), PM_EUNSUPPORTED
+ * (mesh_dtype F32 with state_dtype F64 is allowed; mesh F64 with state F32
+ * is not), PM_ENOMEM, PM_EDEVICE. */
 int pm_plan_create(const pm_config* cfg, pm_plan* out);
 int pm_plan_destroy(pm_plan plan);
-/* Bytes of device scratch pm_plan_create allocates for cfg (0 if invalid). */
+/* Bytes of device scratch a plan for cfg holds (0 if invalid): what
+ * pm_plan_create allocates, plus, for a cubic lattice, the 2LPT lattice
+ * scratch that the first pm_lpt / pm_lpt_vjp call allocates. */
 size_t pm_workspace_bytes(const pm_config* cfg);
 const char* pm_last_error(pm_plan plan);
 const char* pm_strerror(int code);

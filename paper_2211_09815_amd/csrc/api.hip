@@ -57,7 +57,7 @@ int validate_cfg(const pm_config* c, std::string& why) {
   if (!c) { why = "config is NULL"; return PM_EINVAL; }
   for (int a = 0; a < 3; ++a) {
     if (!pow2_in(c->mesh[a], 4, 1024)) { why = "mesh sizes must be powers of two in [4, 1024]"; return PM_ESHAPE; }
-    if (c->ptcl[a] < 1) { why = "particle lattice sizes must be >= 1"; return PM_ESHAPE; }
+    if (c->ptcl[a] < 1 || c->ptcl[a] > 65536) { why = "particle lattice sizes must be in [1, 65536]"; return PM_ESHAPE; }
   }
   if ((c->mesh_dtype != PM_F32 && c->mesh_dtype != PM_F64) || (c->state_dtype != PM_F32 && c->state_dtype != PM_F64)) {
     why = "dtype must be PM_F32 or PM_F64";
@@ -199,7 +199,15 @@ const char* pm_last_error(pm_plan h) {
 size_t pm_workspace_bytes(const pm_config* cfg) {
   std::string why;
   if (validate_cfg(cfg, why) != PM_OK) return 0;
-  return sizes_of(cfg).total();
+  size_t total = sizes_of(cfg).total();
+  // 2LPT lattice scratch (16 real fields, 3 half spectra), allocated by the
+  // first pm_lpt / pm_lpt_vjp call on a cubic lattice
+  const int64_t n = cfg->ptcl[0];
+  if (cfg->ptcl[1] == n && cfg->ptcl[2] == n) {
+    const size_t rb = cfg->mesh_dtype == PM_F64 ? 8 : 4;
+    total += size_t(16) * n * n * n * rb + size_t(3) * n * n * (n / 2 + 1) * 2 * rb;
+  }
+  return total;
 }
 
 int pm_plan_create(const pm_config* cfg, pm_plan* out) {
@@ -313,9 +321,11 @@ int pm_plan_destroy(pm_plan h) {
   (void)hipFree(p->scalars);
   for (void* q : p->lreal) if (q) (void)hipFree(q);
   for (void* q : p->lspec) if (q) (void)hipFree(q);
-  if (p->timing.created)
-    for (auto& f : p->timing.fam)
-      for (auto& e : f.ev) (void)hipEventDestroy(e);
+  for (auto& f : p->timing.fam)
+    for (auto& e : f.ev)
+      if (e) (void)hipEventDestroy(e);
+  // nothing above may leave a sticky error for the caller's next HIP call
+  (void)hipGetLastError();
   delete p;
   return PM_OK;
 }

@@ -19,7 +19,7 @@
 #include <cmath>
 
 #include "cosmo_eh.h"
-#include "pm_internal.h"
+#include "tiles.h"
 
 namespace pmx {
 
@@ -41,11 +41,11 @@ enum MulKind {
 __constant__ int kPairI[6] = {0, 1, 2, 0, 0, 1};
 __constant__ int kPairJ[6] = {0, 1, 2, 1, 2, 2};
 
-__device__ __forceinline__ void decode(int64_t idx, int n, int nh, int& x, int& y, int& z) {
-  z = int(idx % nh);
-  const int64_t t = idx / nh;
-  y = int(t % n);
-  x = int(t / n);
+// (x, y, z) of half-spectrum index idx < 2^31 on an n^3 lattice (n a power of two)
+__device__ __forceinline__ void decode(int idx, int logn, int nh, double inv_nh, int& x, int& y, int& z) {
+  const int row = divmod_small(idx, nh, inv_nh, z);
+  y = row & ((1 << logn) - 1);
+  x = row >> logn;
 }
 
 // amplitude A(k) and its Omega_m derivative at lattice mode (x, y, z)
@@ -65,17 +65,17 @@ __device__ void amp_at(const AmpP& ap, int x, int y, int z, double& A, double& d
   dA = A * (0.5 * ap.dA / ap.A + T.d / T.v);
 }
 
-// out = [out +] M(k) [A(k)] in, M conj'ed if CONJ
+// out = [out +] M(k) [A(k)] in, M conj'ed if CONJ; one workgroup per
+// (x, y) row of the half spectrum (blockIdx.x = x n + y)
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_mul(const Cx<T>* __restrict__ in, Cx<T>* __restrict__ out, int n,
-                                                  int kind, int use_amp, int conj, int accumulate, AmpP ap) {
+                                                  int logn, int kind, int use_amp, int conj, int accumulate, AmpP ap) {
   const int nh = n / 2 + 1;
-  const int64_t total = int64_t(n) * n * nh;
-  const int64_t stride = int64_t(gridDim.x) * kThreads;
+  const int row = blockIdx.x;
+  const int y = row & (n - 1), x = row >> logn;
   const double tp = 6.283185307179586476925286766559;
-  for (int64_t idx = int64_t(blockIdx.x) * kThreads + threadIdx.x; idx < total; idx += stride) {
-    int x, y, z;
-    decode(idx, n, nh, x, y, z);
+  for (int z = threadIdx.x; z < nh; z += kThreads) {
+    const int64_t idx = int64_t(row) * nh + z;
     const int f[3] = {x < n / 2 ? x : x - n, y < n / 2 ? y : y - n, z};
     const bool nyq[3] = {2 * x == n, 2 * y == n, 2 * z == n};
     double k[3];
@@ -192,14 +192,15 @@ __global__ __launch_bounds__(kThreads) void k_hbar(const T* __restrict__ Sb, T* 
 // partial sums (slot 0) of w_k Re[dA W conj(G)] over the half spectrum
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_theta_amp(const Cx<T>* __restrict__ W, const Cx<T>* __restrict__ G,
-                                                        int n, AmpP ap, double* partials) {
+                                                        int n, int logn, AmpP ap, double* partials) {
   const int nh = n / 2 + 1;
-  const int64_t total = int64_t(n) * n * nh;
-  const int64_t stride = int64_t(gridDim.x) * kThreads;
+  const int total = n * n * nh;
+  const int stride = gridDim.x * kThreads;
+  const double inv_nh = 1.0 / double(nh);
   double acc = 0.0;
-  for (int64_t idx = int64_t(blockIdx.x) * kThreads + threadIdx.x; idx < total; idx += stride) {
+  for (int idx = blockIdx.x * kThreads + threadIdx.x; idx < total; idx += stride) {
     int x, y, z;
-    decode(idx, n, nh, x, y, z);
+    decode(idx, logn, nh, inv_nh, x, y, z);
     double A, dA;
     amp_at(ap, x, y, z, A, dA);
     const double w = (z == 0 || 2 * z == n) ? 1.0 : 2.0;
@@ -270,26 +271,28 @@ AmpP amp_params(const Plan* p, const pm_cosmo* c, const pm_ic_coef* ic) {
 template <typename T>
 int mul(Plan* p, const Lat<T>& L, const Cx<T>* in, Cx<T>* out, int kind, bool amp, bool conj, bool acc,
         const AmpP& ap, hipStream_t st) {
-  hipLaunchKernelGGL((k_mul<T>), dim3(grid_for(L.ns)), dim3(kThreads), 0, st, in, out, L.n, kind, amp ? 1 : 0,
-                     conj ? 1 : 0, acc ? 1 : 0, ap);
+  hipLaunchKernelGGL((k_mul<T>), dim3(unsigned(L.n) * unsigned(L.n)), dim3(kThreads), 0, st, in, out, L.n,
+                     ilog2(L.n), kind, amp ? 1 : 0, conj ? 1 : 0, acc ? 1 : 0, ap);
   PM_HIP_CHECK(p, hipGetLastError());
   return PM_OK;
 }
 
 // forward fields: s1 -> real 0..2, H -> real 3..8, s2 -> real 10..12;
-// W = rfft(omega) stays in spec 0
+// W = rfft(omega) stays in spec 0, delta1(k) = A(k) W(k) is formed once in
+// spec 2 (overwritten by the second-order step)
 template <typename T>
 int forward_fields(Plan* p, const Lat<T>& L, const T* omega, const AmpP& ap, hipStream_t st) {
   const FftShape fs{L.n, L.n, L.n};
   const T scale = T(2.0 / double(L.N));
   int rc = fft_r2c_3d<T>(p, fs, omega, L.spec(p, 0), 1, L.N, L.ns, st);
   if (rc) return rc;
+  if ((rc = mul<T>(p, L, L.spec(p, 0), L.spec(p, 2), MUL_ONE, true, false, false, ap, st))) return rc;
   for (int j = 0; j < 3; ++j) {
-    if ((rc = mul<T>(p, L, L.spec(p, 0), L.spec(p, 1), MUL_D1 + j, true, false, false, ap, st))) return rc;
+    if ((rc = mul<T>(p, L, L.spec(p, 2), L.spec(p, 1), MUL_D1 + j, false, false, false, ap, st))) return rc;
     if ((rc = fft_c2r_3d<T>(p, fs, L.spec(p, 1), L.real(p, j), 1, L.ns, L.N, scale, st))) return rc;
   }
   for (int q = 0; q < 6; ++q) {
-    if ((rc = mul<T>(p, L, L.spec(p, 0), L.spec(p, 1), MUL_D2 + q, true, false, false, ap, st))) return rc;
+    if ((rc = mul<T>(p, L, L.spec(p, 2), L.spec(p, 1), MUL_D2 + q, false, false, false, ap, st))) return rc;
     if ((rc = fft_c2r_3d<T>(p, fs, L.spec(p, 1), L.real(p, 3 + q), 1, L.ns, L.N, scale, st))) return rc;
   }
   hipLaunchKernelGGL((k_second_order<T>), dim3(grid_for(L.N)), dim3(kThreads), 0, st, L.real(p, 3), L.real(p, 9),
@@ -365,8 +368,8 @@ int lpt_bwd_typed(Plan* p, const void* omega, const pm_cosmo* c, const pm_ic_coe
   // theta_bar[0] += (1/N) sum w Re[dA W conj(G)]
   {
     const int nb = grid_for(L.ns);
-    hipLaunchKernelGGL((k_theta_amp<T>), dim3(nb), dim3(kThreads), 0, st, L.spec(p, 0), L.spec(p, 2), L.n, ap,
-                       p->partials);
+    hipLaunchKernelGGL((k_theta_amp<T>), dim3(nb), dim3(kThreads), 0, st, L.spec(p, 0), L.spec(p, 2), L.n,
+                       ilog2(L.n), ap, p->partials);
     PM_HIP_CHECK(p, hipGetLastError());
     const double f[4] = {1.0 / double(L.N), 0.0, 0.0, 0.0};
     if ((rc = reduce_partials(p, nb, f, theta_bar, true, st))) return rc;

@@ -41,59 +41,96 @@ struct BinP {
   double* partials;   // slot 0: xi.p (adjoint drift)
 };
 
+// Each thread takes U particles per round, all loads issued first.  Lanes of
+// a wavefront that share a tile form a group; the group leaders then issue
+// their count atomics together (one instruction, one round trip), and every
+// lane takes its rank from its leader's result.
 template <typename S, typename T, int MODE>
 __global__ __launch_bounds__(kThreads) void k_bin(BinP<S, T> a) {
+  constexpr int U = 4;
   const TileGeo& g = a.g;
   int64_t start, end;
   chunk_of(g.N, start, end);
   const int lane = threadIdx.x & 63;
   double xp = 0.0;
-  for (int64_t base = start; base < end; base += kThreads) {
-    const int64_t n = base + threadIdx.x;
-    const bool valid = n < end;
-    int tile = 0;
-    if (valid) {
-      S s[3];
+  for (int64_t base = start; base < end; base += U * kThreads) {
+    S sv[U][3], pv[U][3];
+    T xv[U][3], piv[U][3];
+    bool valid[U];
+    int tile[U];
 #pragma unroll
-      for (int ax = 0; ax < 3; ++ax) s[ax] = a.s[ax * g.N + n];
+    for (int u = 0; u < U; ++u) {
+      const int64_t n = base + threadIdx.x + u * kThreads;
+      valid[u] = n < end;
+      if (!valid[u]) continue;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        sv[u][ax] = a.s[ax * g.N + n];
+        if (MODE != DRIFT_NONE) pv[u][ax] = a.p[ax * g.N + n];
+        if (MODE == DRIFT_ADJ) {
+          xv[u][ax] = a.xi[ax * g.N + n];
+          piv[u][ax] = a.pi[ax * g.N + n];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      tile[u] = 0;
+      if (!valid[u]) continue;
+      const int64_t n = base + threadIdx.x + u * kThreads;
       if (MODE == DRIFT_FWD) {
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-          s[ax] += a.p[ax * g.N + n] * a.D;
-          a.s[ax * g.N + n] = s[ax];
+          sv[u][ax] += pv[u][ax] * a.D;
+          a.s[ax * g.N + n] = sv[u][ax];
         }
       } else if (MODE == DRIFT_ADJ) {
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-          const S pv = a.p[ax * g.N + n];
-          const T xv = a.xi[ax * g.N + n];
-          xp += double(xv) * double(pv);
-          s[ax] -= pv * a.D;
-          a.s[ax * g.N + n] = s[ax];
-          a.pi[ax * g.N + n] = a.pi[ax * g.N + n] + T(xv * T(a.D));
+          xp += double(xv[u][ax]) * double(pv[u][ax]);
+          sv[u][ax] -= pv[u][ax] * a.D;
+          a.s[ax * g.N + n] = sv[u][ax];
+          a.pi[ax * g.N + n] = piv[u][ax] + T(xv[u][ax] * T(a.D));
         }
       }
       double q[3];
       lattice_pos(g, n, q);
-      const int b0 = int(int64_t(floor(q[0] + double(s[0]))) & (g.n0 - 1));
-      const int b1 = int(int64_t(floor(q[1] + double(s[1]))) & (g.n1 - 1));
-      const int b2 = int(int64_t(floor(q[2] + double(s[2]))) & (g.n2 - 1));
-      tile = ((b0 / g.tx) * g.nty + b1 / g.ty) * g.ntz + b2 / g.tz;
+      const int b0 = int(int64_t(floor(q[0] + double(sv[u][0]))) & (g.n0 - 1));
+      const int b1 = int(int64_t(floor(q[1] + double(sv[u][1]))) & (g.n1 - 1));
+      const int b2 = int(int64_t(floor(q[2] + double(sv[u][2]))) & (g.n2 - 1));
+      tile[u] = ((b0 >> g.ltx) * g.nty + (b1 >> g.lty)) * g.ntz + (b2 >> g.ltz);
     }
-    // one atomic per distinct tile among the active lanes of the wavefront
-    unsigned long long pending = __ballot(valid);
-    unsigned rank = 0;
-    while (pending) {
-      const int leader = __ffsll(static_cast<long long>(pending)) - 1;
-      const int lt = __shfl(tile, leader, 64);
-      const unsigned long long same = __ballot(valid && tile == lt) & pending;
-      unsigned baseidx = 0;
-      if (lane == leader) baseidx = atomicAdd(a.counts + lt, unsigned(__popcll(same)));
-      baseidx = __shfl(baseidx, leader, 64);
-      if ((same >> lane) & 1ull) rank = baseidx + unsigned(__popcll(same & ((1ull << lane) - 1ull)));
-      pending &= ~same;
+    int leader[U];
+    unsigned within[U], gsize[U], baseidx[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      leader[u] = lane;
+      within[u] = 0;
+      gsize[u] = 0;
+      unsigned long long pending = __ballot(valid[u]);
+      while (pending) {
+        const int ld = __ffsll(static_cast<long long>(pending)) - 1;
+        const int lt = __shfl(tile[u], ld, 64);
+        const unsigned long long same = __ballot(valid[u] && tile[u] == lt) & pending;
+        if ((same >> lane) & 1ull) {
+          leader[u] = ld;
+          within[u] = unsigned(__popcll(same & ((1ull << lane) - 1ull)));
+        }
+        if (lane == ld) gsize[u] = unsigned(__popcll(same));
+        pending &= ~same;
+      }
     }
-    if (valid) a.keys[n] = make_uint2(unsigned(tile), rank);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      baseidx[u] = 0;
+      if (valid[u] && leader[u] == lane) baseidx[u] = atomicAdd(a.counts + tile[u], gsize[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const unsigned b = __shfl(baseidx[u], leader[u], 64);
+      const int64_t n = base + threadIdx.x + u * kThreads;
+      if (valid[u]) a.keys[n] = make_uint2(unsigned(tile[u]), b + within[u]);
+    }
   }
   if (MODE == DRIFT_ADJ) {
     const double t = block_sum_d(xp);
@@ -178,14 +215,25 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint2* keys, const u
   }
 }
 
-// one workgroup per tile; weights: channel 0 unit mass if UNIT, then w[c]
+constexpr int kPaintThreads = 512;  // threads per tile workgroup of the paint
+
+// One workgroup per tile; weights: channel 0 unit mass if UNIT, then w[c].
+// Particles are taken in chunks of P per thread whose loads are all issued
+// before any is used.  A tile whose particles fit in one chunk (the common
+// case) takes the per-channel bound max|w| from the registers; larger tiles
+// read their weights once more for it.
 template <typename S, typename T, int NCH, bool UNIT>
-__global__ __launch_bounds__(kThreads) void k_paint_tiles(TileGeo g, const S* __restrict__ s,
+__global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const S* __restrict__ s,
                                                           const T* __restrict__ w, const unsigned* __restrict__ offs,
                                                           const unsigned* __restrict__ list, T* __restrict__ mesh,
                                                           T* __restrict__ halo) {
+  constexpr int NW = NCH - (UNIT ? 1 : 0);   // weighted channels
+  constexpr int NWR = NW > 0 ? NW : 1;
+  constexpr int P = 2048 / kPaintThreads;
+  constexpr unsigned CHUNK = P * kPaintThreads;
+  constexpr unsigned NONE = 0xffffffffu;
   __shared__ unsigned long long box[NCH * kBoxMax];
-  __shared__ double wmax[kThreads / 64][NCH];
+  __shared__ double wmax[kPaintThreads / 64][NCH];
   __shared__ double scale[NCH], inv_scale[NCH];
   const int64_t tile = xcd_tile(blockIdx.x, int64_t(gridDim.x));
   const int ex = g.tx + 1, ey = g.ty + 1, ez = g.tz + 1;
@@ -193,38 +241,104 @@ __global__ __launch_bounds__(kThreads) void k_paint_tiles(TileGeo g, const S* __
   int o0, o1, o2;
   tile_origin(g, tile, o0, o1, o2);
   const unsigned beg = offs[tile], fin = offs[tile + 1];
+  const int tid = threadIdx.x;
+
+  unsigned nn[P];
+  S xs[P][3];
+  T ws[P][NWR];
+  auto load = [&](unsigned c0) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const unsigned i = c0 + tid + k * kPaintThreads;
+      nn[k] = i < fin ? list[i] : NONE;
+    }
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      if (nn[k] == NONE) continue;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) xs[k][ax] = s[ax * g.N + nn[k]];
+#pragma unroll
+      for (int c = 0; c < NW; ++c) ws[k][c] = w[c * g.N + nn[k]];
+    }
+  };
+  auto paint = [&]() {
+    double sc[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) sc[c] = scale[c];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      if (nn[k] == NONE) continue;
+      double q[3];
+      lattice_pos(g, nn[k], q);
+      const double x0 = q[0] + double(xs[k][0]), x1 = q[1] + double(xs[k][1]), x2 = q[2] + double(xs[k][2]);
+      const double f0 = floor(x0), f1 = floor(x1), f2 = floor(x2);
+      // local base node inside the tile (the particle was binned by it)
+      const int l0 = int(int64_t(f0) & (g.n0 - 1)) - o0;
+      const int l1 = int(int64_t(f1) & (g.n1 - 1)) - o1;
+      const int l2 = int(int64_t(f2) & (g.n2 - 1)) - o2;
+      const T d0 = T(x0 - f0), d1 = T(x1 - f1), d2 = T(x2 - f2);
+      const T wx[2] = {T(1) - d0, d0}, wy[2] = {T(1) - d1, d1}, wz[2] = {T(1) - d2, d2};
+      double wc[NCH];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+        wc[c] = ((UNIT && c == 0) ? 1.0 : double(ws[k][c - (UNIT ? 1 : 0)])) * sc[c];
+#pragma unroll
+      for (int i0 = 0; i0 < 2; ++i0)
+#pragma unroll
+        for (int i1 = 0; i1 < 2; ++i1) {
+          const T wxy = wx[i0] * wy[i1];
+          const int rowb = ((l0 + i0) * ey + (l1 + i1)) * ez + l2;
+#pragma unroll
+          for (int i2 = 0; i2 < 2; ++i2) {
+            const double ww = double(wxy * wz[i2]);
+#pragma unroll
+            for (int c = 0; c < NCH; ++c)
+              atomicAdd(&box[c * kBoxMax + rowb + i2], (unsigned long long)__double2ll_rn(ww * wc[c]));
+          }
+        }
+    }
+  };
+
+  const bool one_chunk = fin - beg <= CHUNK;
+  if (one_chunk) load(beg);
+  for (int i = tid; i < NCH * nbox; i += kPaintThreads) {
+    const int c = i / nbox;
+    box[c * kBoxMax + (i - c * nbox)] = 0ull;
+  }
   // per-channel bound of any cell sum: count * max|w| (unit mass: count)
-  double m[NCH];
+  if (NW > 0) {
+    double m[NCH];
 #pragma unroll
-  for (int c = 0; c < NCH; ++c) m[c] = 0.0;
-  if (NCH > (UNIT ? 1 : 0)) {
-    for (unsigned i = beg + threadIdx.x; i < fin; i += kThreads) {
-      const int64_t n = list[i];
+    for (int c = 0; c < NCH; ++c) m[c] = 0.0;
+    auto fold = [&](int c, double a) { m[c] = (a > m[c] || a != a) ? a : m[c]; };
+    if (one_chunk) {
 #pragma unroll
-      for (int c = (UNIT ? 1 : 0); c < NCH; ++c) {
-        const double a = fabs(double(w[int64_t(c - (UNIT ? 1 : 0)) * g.N + n]));
-        m[c] = (a > m[c] || a != a) ? a : m[c];
+      for (int k = 0; k < P; ++k)
+        if (nn[k] != NONE)
+#pragma unroll
+          for (int c = 0; c < NW; ++c) fold(c + (UNIT ? 1 : 0), fabs(double(ws[k][c])));
+    } else {
+      for (unsigned i = beg + tid; i < fin; i += kPaintThreads) {
+        const unsigned n = list[i];
+#pragma unroll
+        for (int c = 0; c < NW; ++c) fold(c + (UNIT ? 1 : 0), fabs(double(w[c * g.N + n])));
       }
     }
 #pragma unroll
     for (int c = 0; c < NCH; ++c)
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double o = __shfl_down(m[c], off, 64);
-        m[c] = (o > m[c] || o != o) ? o : m[c];
-      }
-    if ((threadIdx.x & 63) == 0)
+      for (int off = 32; off > 0; off >>= 1) fold(c, __shfl_down(m[c], off, 64));
+    if ((tid & 63) == 0)
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) wmax[threadIdx.x >> 6][c] = m[c];
+      for (int c = 0; c < NCH; ++c) wmax[tid >> 6][c] = m[c];
   }
-  for (int i = threadIdx.x; i < NCH * nbox; i += kThreads) box[(i / nbox) * kBoxMax + i % nbox] = 0ull;
   __syncthreads();
-  if (threadIdx.x < NCH) {
-    const int c = threadIdx.x;
+  if (tid < NCH) {
+    const int c = tid;
     double mx = 1.0;
     if (!(UNIT && c == 0)) {
       mx = 0.0;
-      for (int wv = 0; wv < kThreads / 64; ++wv) mx = (wmax[wv][c] > mx || wmax[wv][c] != wmax[wv][c]) ? wmax[wv][c] : mx;
+      for (int wv = 0; wv < kPaintThreads / 64; ++wv) mx = (wmax[wv][c] > mx || wmax[wv][c] != wmax[wv][c]) ? wmax[wv][c] : mx;
     }
     const double bound = mx * double(fin - beg);
     int ebits = 0;
@@ -241,61 +355,36 @@ __global__ __launch_bounds__(kThreads) void k_paint_tiles(TileGeo g, const S* __
     }
   }
   __syncthreads();
-  double sc[NCH];
-#pragma unroll
-  for (int c = 0; c < NCH; ++c) sc[c] = scale[c];
-  for (unsigned i = beg + threadIdx.x; i < fin; i += kThreads) {
-    const int64_t n = list[i];
-    double q[3];
-    lattice_pos(g, n, q);
-    const double x0 = q[0] + double(s[n]), x1 = q[1] + double(s[g.N + n]), x2 = q[2] + double(s[2 * g.N + n]);
-    const double f0 = floor(x0), f1 = floor(x1), f2 = floor(x2);
-    // local base node inside the tile (the particle was binned by it)
-    const int l0 = int(int64_t(f0) & (g.n0 - 1)) - o0;
-    const int l1 = int(int64_t(f1) & (g.n1 - 1)) - o1;
-    const int l2 = int(int64_t(f2) & (g.n2 - 1)) - o2;
-    const T d0 = T(x0 - f0), d1 = T(x1 - f1), d2 = T(x2 - f2);
-    const T wx[2] = {T(1) - d0, d0}, wy[2] = {T(1) - d1, d1}, wz[2] = {T(1) - d2, d2};
-    double wc[NCH];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c)
-      wc[c] = ((UNIT && c == 0) ? 1.0 : double(w[int64_t(c - (UNIT ? 1 : 0)) * g.N + n])) * sc[c];
-#pragma unroll
-    for (int i0 = 0; i0 < 2; ++i0)
-#pragma unroll
-      for (int i1 = 0; i1 < 2; ++i1) {
-        const T wxy = wx[i0] * wy[i1];
-        const int rowb = ((l0 + i0) * ey + (l1 + i1)) * ez + l2;
-#pragma unroll
-        for (int i2 = 0; i2 < 2; ++i2) {
-          const double ww = double(wxy * wz[i2]);
-#pragma unroll
-          for (int c = 0; c < NCH; ++c)
-            atomicAdd(&box[c * kBoxMax + rowb + i2], (unsigned long long)__double2ll_rn(ww * wc[c]));
-        }
-      }
+  if (one_chunk) {
+    paint();
+  } else {
+    for (unsigned c0 = beg; c0 < fin; c0 += CHUNK) {
+      load(c0);
+      paint();
+    }
   }
   __syncthreads();
   // core: plain stores, rows of tz contiguous cells
   const int ncore = g.tx * g.ty * g.tz;
-  for (int i = threadIdx.x; i < NCH * ncore; i += kThreads) {
-    const int c = i / ncore;
-    const int r = i - c * ncore;
-    const int lz = r % g.tz;
-    const int lxy = r / g.tz;
-    const int ly = lxy % g.ty, lx = lxy / g.ty;
+  for (int i = tid; i < NCH * ncore; i += kPaintThreads) {
+    const int c = i >> (g.ltx + g.lty + g.ltz);
+    const int r = i & (ncore - 1);
+    const int lz = r & (g.tz - 1);
+    const int ly = (r >> g.ltz) & (g.ty - 1);
+    const int lx = r >> (g.ltz + g.lty);
     mesh[c * g.ncell + (int64_t(o0 + lx) * g.n1 + (o1 + ly)) * g.n2 + (o2 + lz)] =
         T(double(static_cast<long long>(box[c * kBoxMax + (lx * ey + ly) * ez + lz])) * inv_scale[c]);
   }
   // halo faces: X (lx = tx, all ly, lz), Y (ly = ty, lx < tx), Z (lz = tz, lx < tx, ly < ty)
   const int fx = ey * ez, fy = g.tx * ez;
-  for (int i = threadIdx.x; i < NCH * g.hc; i += kThreads) {
+  const unsigned mez = 0xffffffffu / unsigned(ez) + 1u;
+  for (int i = tid; i < NCH * g.hc; i += kPaintThreads) {
     const int c = i / g.hc;
     const int h = i - c * g.hc;
     int lx, ly, lz;
-    if (h < fx) { lx = g.tx; ly = h / ez; lz = h % ez; }
-    else if (h < fx + fy) { const int k = h - fx; lx = k / ez; ly = g.ty; lz = k % ez; }
-    else { const int k = h - fx - fy; lx = k / g.ty; ly = k % g.ty; lz = g.tz; }
+    if (h < fx) { lx = g.tx; ly = fdiv_small(h, mez); lz = h - ly * ez; }
+    else if (h < fx + fy) { const int k = h - fx; lx = fdiv_small(k, mez); ly = g.ty; lz = k - lx * ez; }
+    else { const int k = h - fx - fy; lx = k >> g.lty; ly = k & (g.ty - 1); lz = g.tz; }
     halo[(int64_t(c) * g.ntiles + tile) * g.hc + h] =
         T(double(static_cast<long long>(box[c * kBoxMax + (lx * ey + ly) * ez + lz])) * inv_scale[c]);
   }
@@ -407,7 +496,8 @@ int paint_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
   const double hadd_bytes = halo_bytes + 2.0 * lower * core_bytes;
 #define PM_TILES(NCH, UNIT)                                                                                \
   timing_begin(p, PM_K_PAINT_TILES, st);                                                                   \
-  hipLaunchKernelGGL((k_paint_tiles<S, T, NCH, UNIT>), tg, block, 0, st, g, s, w, p->bin_offs, p->bin_list, \
+  hipLaunchKernelGGL((k_paint_tiles<S, T, NCH, UNIT>), tg, dim3(kPaintThreads), 0, st, g, s, w, p->bin_offs,    \
+                     p->bin_list,                                                                          \
                      mesh, halo);                                                                          \
   timing_end(p, PM_K_PAINT_TILES, st, tile_bytes);                                                         \
   timing_begin(p, PM_K_HALO, st);                                                                          \

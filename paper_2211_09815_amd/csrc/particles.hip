@@ -17,7 +17,7 @@ namespace pmx {
 
 namespace {
 
-__device__ __forceinline__ double block_sum(double v) { return block_sum_d(v); }
+__device__ __forceinline__ double block_sum(double v) { return block_sum_d<kThreads>(v); }
 
 // ---------------------------------------------------------------------------
 // gather (+ kick / VJP)
@@ -39,8 +39,15 @@ struct GatherP {
   double* partials;  // per tile, slot 1: sum cot.a
 };
 
+constexpr int kGatherThreads = 512;  // threads per tile workgroup of the gather
+
 template <typename S, typename T, int MODE, int NF>
-__global__ __launch_bounds__(kThreads) void k_gather_tiles(GatherP<S, T> a) {
+__global__ __launch_bounds__(kGatherThreads) void k_gather_tiles(GatherP<S, T> a) {
+  constexpr int P = 1024 / kGatherThreads;     // particles per thread per chunk
+  constexpr unsigned CHUNK = P * kGatherThreads;
+  constexpr unsigned NONE = 0xffffffffu;
+  constexpr bool KICKF = MODE == GATHER_KICK_FWD, KICKA = MODE == GATHER_KICK_ADJ;
+  constexpr bool COT = MODE == GATHER_VJP || KICKA;
   const TileGeo& g = a.g;
   __shared__ T box[NF * kBoxMax];
   const int64_t tile = xcd_tile(blockIdx.x, int64_t(gridDim.x));
@@ -49,102 +56,137 @@ __global__ __launch_bounds__(kThreads) void k_gather_tiles(GatherP<S, T> a) {
   int o0, o1, o2;
   tile_origin(g, tile, o0, o1, o2);
   const unsigned beg = a.offs[tile], fin = a.offs[tile + 1];
+  const int tid = threadIdx.x;
   double ca = 0.0;
   if (fin > beg) {
-    for (int i = threadIdx.x; i < NF * nbox; i += kThreads) {
-      const int c = i / nbox;
+    // particle chunk: all loads issued before any is used
+    unsigned nn[P];
+    S xs[P][3], ps[P][KICKF || KICKA ? 3 : 1];
+    T cs[P][COT ? 3 : 1], xis[P][KICKA ? 3 : 1];
+    auto load = [&](unsigned c0) {
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        const unsigned i = c0 + tid + k * kGatherThreads;
+        nn[k] = i < fin ? a.list[i] : NONE;
+      }
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        if (nn[k] == NONE) continue;
+        const int64_t n = nn[k];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          xs[k][ax] = a.s[ax * g.N + n];
+          if (KICKF || KICKA) ps[k][ax] = a.p[ax * g.N + n];
+          if (COT) cs[k][ax] = a.cot[ax * g.N + n];
+          if (KICKA) xis[k][ax] = a.xi[ax * g.N + n];
+        }
+      }
+    };
+    load(beg);
+    // the tile's box of every field, (lx, ly) rows of ez cells
+    const unsigned mez = 0xffffffffu / unsigned(ez) + 1u, mey = 0xffffffffu / unsigned(ey) + 1u;
+    const unsigned mbox = 0xffffffffu / unsigned(nbox) + 1u;
+    for (int i = tid; i < NF * nbox; i += kGatherThreads) {
+      const int c = fdiv_small(i, mbox);
       const int r = i - c * nbox;
-      const int lz = r % ez;
-      const int lxy = r / ez;
-      const int ly = lxy % ey, lx = lxy / ey;
+      const int lxy = fdiv_small(r, mez);
+      const int lz = r - lxy * ez;
+      const int lx = fdiv_small(lxy, mey);
+      const int ly = lxy - lx * ey;
       const int64_t cell = (int64_t((o0 + lx) & (g.n0 - 1)) * g.n1 + ((o1 + ly) & (g.n1 - 1))) * g.n2 +
                            ((o2 + lz) & (g.n2 - 1));
       box[c * kBoxMax + r] = a.mesh[c * g.ncell + cell];
     }
     __syncthreads();
-    for (unsigned i = beg + threadIdx.x; i < fin; i += kThreads) {
-      const int64_t n = a.list[i];
-      double q[3];
-      lattice_pos(g, n, q);
-      const double x0 = q[0] + double(a.s[n]), x1 = q[1] + double(a.s[g.N + n]), x2 = q[2] + double(a.s[2 * g.N + n]);
-      const double f0 = floor(x0), f1 = floor(x1), f2 = floor(x2);
-      const int l0 = int(int64_t(f0) & (g.n0 - 1)) - o0;
-      const int l1 = int(int64_t(f1) & (g.n1 - 1)) - o1;
-      const int l2 = int(int64_t(f2) & (g.n2 - 1)) - o2;
-      const T d0 = T(x0 - f0), d1 = T(x1 - f1), d2 = T(x2 - f2);
-      const T wx[2] = {T(1) - d0, d0}, wy[2] = {T(1) - d1, d1}, wz[2] = {T(1) - d2, d2};
-      T v[NF];
+    for (unsigned c0 = beg;;) {
 #pragma unroll
-      for (int c = 0; c < NF; ++c) v[c] = T(0);
-      T cot[3] = {T(0), T(0), T(0)};
-      if (MODE == GATHER_VJP || MODE == GATHER_KICK_ADJ) {
+      for (int k = 0; k < P; ++k) {
+        if (nn[k] == NONE) continue;
+        const int64_t n = nn[k];
+        double q[3];
+        lattice_pos(g, n, q);
+        const double x0 = q[0] + double(xs[k][0]), x1 = q[1] + double(xs[k][1]), x2 = q[2] + double(xs[k][2]);
+        const double f0 = floor(x0), f1 = floor(x1), f2 = floor(x2);
+        const int l0 = int(int64_t(f0) & (g.n0 - 1)) - o0;
+        const int l1 = int(int64_t(f1) & (g.n1 - 1)) - o1;
+        const int l2 = int(int64_t(f2) & (g.n2 - 1)) - o2;
+        const T d0 = T(x0 - f0), d1 = T(x1 - f1), d2 = T(x2 - f2);
+        const T wx[2] = {T(1) - d0, d0}, wy[2] = {T(1) - d1, d1}, wz[2] = {T(1) - d2, d2};
+        T v[NF];
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) cot[ax] = a.cot[ax * g.N + n];
-      }
-      T dv[3] = {T(0), T(0), T(0)};  // sum_corner dW_k * h(corner)
+        for (int c = 0; c < NF; ++c) v[c] = T(0);
+        T cot[3] = {T(0), T(0), T(0)};
+        if (COT) {
 #pragma unroll
-      for (int i0 = 0; i0 < 2; ++i0)
+          for (int ax = 0; ax < 3; ++ax) cot[ax] = cs[k][ax];
+        }
+        T dv[3] = {T(0), T(0), T(0)};  // sum_corner dW_k * h(corner)
 #pragma unroll
-        for (int i1 = 0; i1 < 2; ++i1)
+        for (int i0 = 0; i0 < 2; ++i0)
 #pragma unroll
-          for (int i2 = 0; i2 < 2; ++i2) {
-            const int r = ((l0 + i0) * ey + (l1 + i1)) * ez + (l2 + i2);
-            const T w = wx[i0] * wy[i1] * wz[i2];
-            T m[NF];
+          for (int i1 = 0; i1 < 2; ++i1)
 #pragma unroll
-            for (int c = 0; c < NF; ++c) m[c] = box[c * kBoxMax + r];
-            if (MODE == GATHER_PLAIN || MODE == GATHER_KICK_FWD || MODE == GATHER_VJP ||
-                MODE == GATHER_KICK_ADJ) {
+            for (int i2 = 0; i2 < 2; ++i2) {
+              const int r = ((l0 + i0) * ey + (l1 + i1)) * ez + (l2 + i2);
+              const T w = wx[i0] * wy[i1] * wz[i2];
+              T m[NF];
 #pragma unroll
-              for (int c = 0; c < (MODE == GATHER_PLAIN || MODE == GATHER_KICK_FWD ? NF : 3); ++c) v[c] += w * m[c];
+              for (int c = 0; c < NF; ++c) m[c] = box[c * kBoxMax + r];
+              if (MODE == GATHER_PLAIN || KICKF || COT) {
+#pragma unroll
+                for (int c = 0; c < (MODE == GATHER_PLAIN || KICKF ? NF : 3); ++c) v[c] += w * m[c];
+              }
+              if (COT || MODE == GATHER_MSE) {
+                // h = sum_j cot_j g_j + rhobar   (VJP)   or   h = mbar   (MSE)
+                T h;
+                if (MODE == GATHER_MSE) h = m[0];
+                else h = cot[0] * m[0] + cot[1] * m[1] + cot[2] * m[2] + m[3];
+                const T sx = i0 ? T(1) : T(-1), sy = i1 ? T(1) : T(-1), sz = i2 ? T(1) : T(-1);
+                dv[0] += sx * wy[i1] * wz[i2] * h;
+                dv[1] += sy * wx[i0] * wz[i2] * h;
+                dv[2] += sz * wx[i0] * wy[i1] * h;
+              }
             }
-            if (MODE == GATHER_VJP || MODE == GATHER_KICK_ADJ || MODE == GATHER_MSE) {
-              // h = sum_j cot_j g_j + rhobar   (VJP)   or   h = mbar   (MSE)
-              T h;
-              if (MODE == GATHER_MSE) h = m[0];
-              else h = cot[0] * m[0] + cot[1] * m[1] + cot[2] * m[2] + m[3];
-              const T sx = i0 ? T(1) : T(-1), sy = i1 ? T(1) : T(-1), sz = i2 ? T(1) : T(-1);
-              dv[0] += sx * wy[i1] * wz[i2] * h;
-              dv[1] += sy * wx[i0] * wz[i2] * h;
-              dv[2] += sz * wx[i0] * wy[i1] * h;
-            }
+        if (MODE == GATHER_PLAIN) {
+#pragma unroll
+          for (int c = 0; c < NF; ++c) a.out[c * g.N + n] = v[c];
+        } else if (KICKF) {
+#pragma unroll
+          for (int ax = 0; ax < 3; ++ax) {
+            a.p[ax * g.N + n] = ps[k][ax] + S(v[ax]) * a.K;
+            if (a.acc) a.acc[ax * g.N + n] = v[ax];
           }
-      if (MODE == GATHER_PLAIN) {
+        } else if (MODE == GATHER_VJP) {
 #pragma unroll
-        for (int c = 0; c < NF; ++c) a.out[c * g.N + n] = v[c];
-      } else if (MODE == GATHER_KICK_FWD) {
+          for (int ax = 0; ax < 3; ++ax) {
+            a.out[ax * g.N + n] = dv[ax];
+            if (a.acc) a.acc[ax * g.N + n] = v[ax];
+            ca += double(cot[ax]) * double(v[ax]);
+          }
+        } else if (KICKA) {
+          if (a.acc_in) {
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-          a.p[ax * g.N + n] += S(v[ax]) * a.K;
-          if (a.acc) a.acc[ax * g.N + n] = v[ax];
+            for (int ax = 0; ax < 3; ++ax) v[ax] = a.acc_in[ax * g.N + n];
+          }
+#pragma unroll
+          for (int ax = 0; ax < 3; ++ax) {
+            ca += double(cot[ax]) * double(v[ax]);
+            a.p[ax * g.N + n] = ps[k][ax] - S(v[ax]) * a.K;
+            a.xi[ax * g.N + n] = xis[k][ax] + dv[ax] * T(a.K);
+            if (a.acc) a.acc[ax * g.N + n] = v[ax];
+          }
+        } else if (MODE == GATHER_MSE) {
+#pragma unroll
+          for (int ax = 0; ax < 3; ++ax) a.out[ax * g.N + n] = dv[ax];
         }
-      } else if (MODE == GATHER_VJP) {
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-          a.out[ax * g.N + n] = dv[ax];
-          if (a.acc) a.acc[ax * g.N + n] = v[ax];
-          ca += double(cot[ax]) * double(v[ax]);
-        }
-      } else if (MODE == GATHER_KICK_ADJ) {
-        if (a.acc_in) {
-#pragma unroll
-          for (int ax = 0; ax < 3; ++ax) v[ax] = a.acc_in[ax * g.N + n];
-        }
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-          ca += double(cot[ax]) * double(v[ax]);
-          a.p[ax * g.N + n] -= S(v[ax]) * a.K;
-          a.xi[ax * g.N + n] += dv[ax] * T(a.K);
-          if (a.acc) a.acc[ax * g.N + n] = v[ax];
-        }
-      } else if (MODE == GATHER_MSE) {
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) a.out[ax * g.N + n] = dv[ax];
       }
+      c0 += CHUNK;
+      if (c0 >= fin) break;
+      load(c0);
     }
   }
-  if (MODE == GATHER_VJP || MODE == GATHER_KICK_ADJ) {
-    const double t = block_sum(ca);
+  if (COT) {
+    const double t = block_sum_d<kGatherThreads>(ca);
     if (threadIdx.x == 0) a.partials[tile * 4 + 1] = t;
   }
 }
@@ -206,7 +248,7 @@ int gather_typed(Plan* p, GatherMode mode, const GatherArgs& in, hipStream_t st)
   a.offs = p->bin_offs;
   a.list = p->bin_list;
   a.partials = p->tile_partials;
-  const dim3 grid(unsigned(p->ntiles)), block(kThreads);
+  const dim3 grid(unsigned(p->ntiles)), block(kGatherThreads);
   timing_begin(p, PM_K_GATHER, st);
 #define PM_GATHER(MODE, NF) hipLaunchKernelGGL((k_gather_tiles<S, T, MODE, NF>), grid, block, 0, st, a)
   switch (mode) {

@@ -13,10 +13,12 @@ constexpr int kBoxMax = 9 * 9 * 17;  // box cells for the largest tile (8 x 8 x 
 struct TileGeo {
   int64_t N;
   int np1, np2;
+  double inv_np1, inv_np2;   // 1/np1, 1/np2 (quotient estimates, corrected)
   double r0, r1, r2, off;
   int n0, n1, n2;
   int64_t ncell;
-  int tx, ty, tz;        // tile dims (cells)
+  int tx, ty, tz;        // tile dims (cells), powers of two
+  int ltx, lty, ltz;     // their log2
   int ntx, nty, ntz;     // tiles per axis
   int64_t ntiles;
   int hc;                // halo cells per tile (the three upper faces of the box)
@@ -27,6 +29,8 @@ inline TileGeo tile_geo(const Plan* p) {
   g.N = p->nptcl;
   g.np1 = p->np[1];
   g.np2 = p->np[2];
+  g.inv_np1 = 1.0 / double(g.np1);
+  g.inv_np2 = 1.0 / double(g.np2);
   g.r0 = p->r[0];
   g.r1 = p->r[1];
   g.r2 = p->r[2];
@@ -38,6 +42,9 @@ inline TileGeo tile_geo(const Plan* p) {
   g.tx = p->tile[0];
   g.ty = p->tile[1];
   g.tz = p->tile[2];
+  g.ltx = ilog2(g.tx);
+  g.lty = ilog2(g.ty);
+  g.ltz = ilog2(g.tz);
   g.ntx = g.n0 / g.tx;
   g.nty = g.n1 / g.ty;
   g.ntz = g.n2 / g.tz;
@@ -46,16 +53,30 @@ inline TileGeo tile_geo(const Plan* p) {
   return g;
 }
 
+// q = n / d and n - q d for 0 <= n < 2^31: the FP64 estimate n * (1/d) is
+// within one of the quotient, and one correction step makes it exact
+__device__ __forceinline__ int divmod_small(int n, int d, double inv, int& rem) {
+  int q = int(double(n) * inv);
+  int r = n - q * d;
+  if (r < 0) { --q; r += d; }
+  if (r >= d) { ++q; r -= d; }
+  rem = r;
+  return q;
+}
+
 // Lagrangian position q = (i, j, k) r + offset of particle n (row-major lattice)
 __device__ __forceinline__ void lattice_pos(const TileGeo& g, int64_t n, double q[3]) {
-  const int64_t row = n / g.np2;
-  const int k = int(n - row * g.np2);
-  const int64_t i = row / g.np1;
-  const int j = int(row - i * g.np1);
+  int k, j;
+  const int row = divmod_small(int(n), g.np2, g.inv_np2, k);
+  const int i = divmod_small(row, g.np1, g.inv_np1, j);
   q[0] = double(i) * g.r0 + g.off;
   q[1] = double(j) * g.r1 + g.off;
   q[2] = double(k) * g.r2 + g.off;
 }
+
+// r / d for 0 <= r < 2^20 and 1 <= d < 2^10 with m = 0xffffffff / d + 1:
+// the high word of r m is exact in that range
+__device__ __forceinline__ int fdiv_small(int r, unsigned m) { return int(__umulhi(unsigned(r), m)); }
 
 // tile coordinates and origin cell of a tile index
 __device__ __forceinline__ void tile_origin(const TileGeo& g, int64_t tile, int& o0, int& o1, int& o2) {
@@ -76,8 +97,10 @@ __device__ __forceinline__ void chunk_of(int64_t N, int64_t& start, int64_t& end
   end = start + per < N ? start + per : N;
 }
 
+// sum over a workgroup of NT threads; the result is valid in thread 0
+template <int NT = kThreads>
 __device__ __forceinline__ double block_sum_d(double v) {
-  __shared__ double ws[kThreads / 64];
+  __shared__ double ws[NT / 64];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -86,7 +109,7 @@ __device__ __forceinline__ double block_sum_d(double v) {
   __syncthreads();
   double t = 0.0;
   if (threadIdx.x == 0)
-    for (int w = 0; w < kThreads / 64; ++w) t += ws[w];
+    for (int w = 0; w < NT / 64; ++w) t += ws[w];
   return t;
 }
 

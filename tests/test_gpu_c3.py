@@ -1,0 +1,75 @@
+"""GPU parity at the full size of the single-force configuration: 256^3
+particles displaced by 2LPT at a = 0.5 (float32 displacements), a 512^3 FP32
+mesh, 512 Mpc/h; force and force VJP against the FP64 oracle's stored results
+(tests/golden/c3_oracle.json, written by tests/golden/make_c3_golden.py from
+the oracle alone), on 4096 sampled particles, plus properties that hold at
+any size.
+
+The displacements come from the oracle's 2LPT (rounded to float32, as the
+golden script does), so both sides see identical positions.  Tolerances: the
+stated 1e-5 relative L2 on a single force, 2e-5 on the VJP outputs.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import announce, dev, host, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def case():
+    import sys
+    sys.path.insert(0, GOLDEN_DIR)
+    import make_c3_golden as G
+    from paper_2211_09815_amd.api import Plan
+    with open(os.path.join(GOLDEN_DIR, "c3_oracle.json")) as f:
+        gold = json.load(f)
+    announce("c3 inputs (oracle 2LPT at 256^3)")
+    s = G.displacements()
+    cot = G.cotangent()
+    plan = Plan(G.NM, G.N, box=G.BOX, mesh_dtype=torch.float32, state_dtype=torch.float32)
+    s_dev = dev(s.T, torch.float32)
+    return gold, plan, s_dev, dev(cot.T, torch.float32), G.COEF
+
+
+def test_c3_force_vs_oracle(case):
+    gold, plan, s_dev, _, coef = case
+    announce("c3 force")
+    a = host(plan.force(s_dev, coef))
+    idx = np.asarray(gold["sample_idx"])
+    assert rel_l2(a[:, idx].T, gold["acc_sample"]) < 1e-5
+    # momentum conservation of the mesh force, and the overall scale
+    assert np.abs(a.sum(1)).max() < 1e-5 * gold["acc_rms"] * a.shape[1] ** 0.5
+    assert np.sqrt(np.mean(a * a)) == pytest.approx(gold["acc_rms"], rel=1e-5)
+
+
+def test_c3_force_vjp_vs_oracle(case):
+    gold, plan, s_dev, cot, coef = case
+    announce("c3 force vjp")
+    xbar, cbar, acc = plan.force_vjp(s_dev, cot, coef)
+    idx = np.asarray(gold["sample_idx"])
+    assert rel_l2(host(xbar)[:, idx].T, gold["xbar_sample"]) < 2e-5
+    assert rel_l2(host(acc)[:, idx].T, gold["acc_sample"]) < 1e-5
+    assert host(cbar)[0] == pytest.approx(gold["coef_bar"], rel=2e-5)
+
+
+def test_c3_unfused_stages_match_fused_force(case):
+    # paint -> R2C -> Poisson gradient -> 3 C2R -> readout through the
+    # separate entry points equals the fused pm_force
+    _, plan, s_dev, _, coef = case
+    announce("c3 unfused stages")
+    n_cells = float(np.prod(plan.mesh))
+    rho = plan.paint(s_dev)
+    dk = plan.fft_r2c(rho)
+    gk = plan.poisson_grad(dk[0], coef * n_cells / plan.n_particles)
+    g = plan.fft_c2r(gk)
+    a_unfused = host(plan.readout(s_dev, g))
+    a_fused = host(plan.force(s_dev, coef))
+    assert rel_l2(a_unfused, a_fused) < 1e-6

@@ -171,3 +171,48 @@ def test_autograd_function_returns_adjoint_gradients():
     assert float(J) == pytest.approx(host(J2)[0], rel=1e-12)
     assert rel_l2(host(omega.grad), host(g2)) < 1e-12
     assert rel_l2(host(theta.grad), host(t2)) < 1e-12
+
+
+@pytest.mark.parametrize("sdt,tol", [(torch.float64, 1e-9), (torch.float32, 1e-3)])
+def test_reverse_time_pass_recovers_initial_state(sdt, tol):
+    # after the adjoint pass the state holds the reverse-integrated (s_0, p_0)
+    from paper_2211_09815_amd.simulate import SimConfig, Simulation
+    api = _api()
+    announce("reversibility 32^3/64^3 10 steps state %s" % sdt)
+    n, nm, box, steps = 32, 64, 128.0, 10
+    sim = Simulation(SimConfig(n, nm, box, 1 / 16, 1.0, steps, torch.float32, sdt))
+    cos = api.Cosmology()
+    coefs, ic = sim.tables(cos)
+    target = sim.final_density(dev(inputs.white_noise(n, 1), torch.float32), cos).clone()
+    omega = dev(inputs.white_noise(n, 0), torch.float32)
+    st0 = {"s": torch.zeros_like(sim.s), "p": torch.zeros_like(sim.p), "acc": None}
+    sim.plan.lpt(omega, cos, ic, st0)
+    sim.value_and_grad(omega, cos, target)
+    s0, p0 = host(st0["s"]), host(st0["p"])
+    assert np.sqrt(np.mean((host(sim.s) - s0) ** 2)) / s0.std() < tol
+    assert np.sqrt(np.mean((host(sim.p) - p0) ** 2)) / p0.std() < tol
+
+
+def test_adjoint_memory_is_flat_in_step_count():
+    # reverse-time integration stores no trajectory: the device memory of a
+    # forward+adjoint pass does not grow with the number of steps
+    from paper_2211_09815_amd.simulate import SimConfig, Simulation
+    api = _api()
+    n, nm, box = 32, 64, 128.0
+    cos = api.Cosmology()
+    target = dev(np.zeros((nm,) * 3), torch.float32)
+    omega = dev(inputs.white_noise(n, 0), torch.float32)
+    peaks = []
+    for steps in (5, 20, 40):
+        announce("memory %d steps" % steps)
+        sim = Simulation(SimConfig(n, nm, box, 1 / 16, 1.0, steps, torch.float32, torch.float64))
+        sim.value_and_grad(omega, cos, target)     # first pass allocates the lattice scratch
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats()
+        base = torch.cuda.memory_allocated()
+        sim.value_and_grad(omega, cos, target)
+        torch.cuda.synchronize()
+        peaks.append(torch.cuda.max_memory_allocated() - base)
+        del sim
+        torch.cuda.empty_cache()
+    assert max(peaks) - min(peaks) == 0, peaks

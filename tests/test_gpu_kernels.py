@@ -188,3 +188,18 @@ def test_density_and_mse_vs_oracle():
     J_ref, xb_ref = oobj.density_mse(q + s, target, len(q))
     assert host(J)[0] == pytest.approx(J_ref, rel=1e-12)
     assert rel_l2(aos(host(xbar)), xb_ref) < 1e-12
+
+
+def test_plan_destroy_leaves_no_pending_hip_error():
+    # destroying a plan (with and without kernel timing) must not leave an
+    # error behind for the caller's next HIP call
+    from paper_2211_09815_amd import _lib
+    announce("plan destroy")
+    for timed in (False, True):
+        plan = _plan((16, 16, 16), (8, 8, 8))
+        if timed:
+            plan.timing_enable(_lib.KERNEL_FAMILIES.values())
+        plan.close()
+        x = torch.ones(1024, device="cuda")
+        assert float((x * 2).sum()) == 2048.0
+        torch.cuda.synchronize()
