@@ -20,8 +20,12 @@
 // faster than floating-point ones here, and integer addition is associative,
 // so the painted mesh is bitwise identical from run to run.  Each tile picks
 // its own binary scale 2^e per channel so that the bound count * max|w| of
-// any cell sum stays below 2^61; the quantum 2^-e is far below the mesh
-// type's rounding (about 1e-15 relative for a tile of ~10^3 particles).
+// any cell sum stays below 2^H, H = 61 for FP64 meshes and 51 for FP32
+// meshes; the quantum 2^-e is far below the mesh type's rounding (about
+// 1e-15 and 1e-12 relative for a tile of ~10^3 particles).  With H = 51 every
+// contribution is below 2^51 in magnitude, so it is rounded to an integer by
+// one FP64 fused multiply-add with 1.5 * 2^52 and read back from the bits,
+// instead of a general double-to-int64 conversion.
 #include "tiles.h"
 
 namespace pmx {
@@ -229,6 +233,8 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
                                                           T* __restrict__ halo) {
   constexpr int NW = NCH - (UNIT ? 1 : 0);   // weighted channels
   constexpr int NWR = NW > 0 ? NW : 1;
+  constexpr bool F32 = sizeof(T) == 4;
+  constexpr int kHead = F32 ? 51 : 61;         // bits of headroom of the fixed point
   constexpr int P = 2048 / kPaintThreads;
   constexpr unsigned CHUNK = P * kPaintThreads;
   constexpr unsigned NONE = 0xffffffffu;
@@ -292,8 +298,17 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
           for (int i2 = 0; i2 < 2; ++i2) {
             const double ww = double(wxy * wz[i2]);
 #pragma unroll
-            for (int c = 0; c < NCH; ++c)
-              atomicAdd(&box[c * kBoxMax + rowb + i2], (unsigned long long)__double2ll_rn(ww * wc[c]));
+            for (int c = 0; c < NCH; ++c) {
+              long long q;
+              if constexpr (F32) {
+                // |ww wc| < 2^51: round to the nearest integer (ties to even)
+                // in the low mantissa bits of 1.5 * 2^52 + ww wc
+                q = __double_as_longlong(fma(ww, wc[c], 6755399441055744.0)) - 0x4338000000000000ll;
+              } else {
+                q = __double2ll_rn(ww * wc[c]);
+              }
+              atomicAdd(&box[c * kBoxMax + rowb + i2], (unsigned long long)q);
+            }
           }
         }
     }
@@ -344,8 +359,8 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
     int ebits = 0;
     if (bound > 0.0 && bound <= 1.0e300) {
       frexp(bound, &ebits);           // bound < 2^ebits
-      scale[c] = ldexp(1.0, 61 - ebits);
-      inv_scale[c] = ldexp(1.0, ebits - 61);
+      scale[c] = ldexp(1.0, kHead - ebits);
+      inv_scale[c] = ldexp(1.0, ebits - kHead);
     } else if (bound == 0.0) {
       scale[c] = 0.0;
       inv_scale[c] = 0.0;
