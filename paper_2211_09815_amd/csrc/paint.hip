@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
   __shared__ unsigned long long box[NCH * kBoxMax];
   __shared__ double wmax[kPaintThreads / 64][NCH];
   __shared__ double scale[NCH], inv_scale[NCH];
-  const int64_t tile = xcd_tile(blockIdx.x, int64_t(gridDim.x));
+  const int64_t tile = tile_order(g, xcd_tile(blockIdx.x, int64_t(gridDim.x)));
   const int ex = g.tx + 1, ey = g.ty + 1, ez = g.tz + 1;
   const int nbox = ex * ey * ez;
   int o0, o1, o2;

@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_tiles(GatherP<S, T> a
   constexpr bool COT = MODE == GATHER_VJP || KICKA;
   const TileGeo& g = a.g;
   __shared__ T box[NF * kBoxMax];
-  const int64_t tile = xcd_tile(blockIdx.x, int64_t(gridDim.x));
+  const int64_t tile = tile_order(g, xcd_tile(blockIdx.x, int64_t(gridDim.x)));
   const int ex = g.tx + 1, ey = g.ty + 1, ez = g.tz + 1;
   const int nbox = ex * ey * ez;
   int o0, o1, o2;

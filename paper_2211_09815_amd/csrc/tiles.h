@@ -89,6 +89,24 @@ __device__ __forceinline__ void tile_origin(const TileGeo& g, int64_t tile, int&
   o2 = t2 * g.tz;
 }
 
+// Dispatch order of the tiles: groups of kOrderX x kOrderY columns of tiles
+// (x, y) are interleaved at every z, so the x and y neighbours of most tiles
+// run at about the same time on the same XCD and share its L2 (boxes overlap
+// by one cell plane, and particle cache lines straddle tile faces).
+// pos -> tile id; identity when the tile grid does not divide into groups.
+constexpr int kOrderX = 2, kOrderY = 2;
+__device__ __forceinline__ int64_t tile_order(const TileGeo& g, int64_t pos) {
+  if (g.ntx % kOrderX || g.nty % kOrderY) return pos;
+  constexpr int G = kOrderX * kOrderY;
+  const int64_t blk = pos / (G * g.ntz);
+  const int w = int(pos - blk * G * g.ntz);
+  const int t2 = w / G, d = w % G;
+  const int d0 = d / kOrderY, d1 = d % kOrderY;
+  const int hy = g.nty / kOrderY;
+  const int m0 = int(blk / hy), m1 = int(blk - int64_t(m0) * hy);
+  return (int64_t(kOrderX * m0 + d0) * g.nty + (kOrderY * m1 + d1)) * g.ntz + t2;
+}
+
 // contiguous particle chunk of this workgroup (consecutive chunks on one XCD)
 __device__ __forceinline__ void chunk_of(int64_t N, int64_t& start, int64_t& end) {
   const int64_t nb = gridDim.x;
