@@ -216,3 +216,42 @@ def test_adjoint_memory_is_flat_in_step_count():
         del sim
         torch.cuda.empty_cache()
     assert max(peaks) - min(peaks) == 0, peaks
+
+
+@pytest.mark.parametrize("mdt,sdt", [(torch.float32, torch.float64), (torch.float64, torch.float64),
+                                     (torch.float32, torch.float32)])
+def test_native_loops_match_step_calls(mdt, sdt):
+    # the native loops pm_run_fwd / pm_run_adj must leave exactly the state
+    # that the sequence of step calls leaves (theta_bar up to the order of
+    # its FP64 partial sums)
+    api = _api()
+    announce("native loops vs step calls %s/%s" % (mdt, sdt))
+    n, nm, box, steps = 16, 32, 64.0, 6
+    cfg = osim.SimConfig(n, nm, box, 1 / 16, 1.0, steps)
+    omega = inputs.white_noise(n, 0)
+    s0, p0 = osim.initial_state(omega, cfg)
+    coefs, dcoefs = ocos.step_coefficients_with_derivative(cfg.a_grid(), 0.3)
+    rows = np.concatenate([coefs, dcoefs], axis=1)
+    plan = api.Plan(nm, n, box=box, mesh_dtype=mdt, state_dtype=sdt)
+    res = []
+    for native in (True, False):
+        st = plan.new_state(dev(soa(s0), sdt), dev(soa(p0), sdt))
+        if native:
+            plan.run_fwd(st, rows, 0.45)
+        else:
+            plan.fwd_init(st, rows[0], 0.45)
+            for i in range(steps):
+                plan.step_fwd(st, rows[i], rows[i + 1] if i + 1 < steps else None, 0.45)
+        fwd = (host(st["s"]), host(st["p"]), host(st["acc"]))
+        adj = {"xi": dev(inputs.normal((3, n ** 3), 60, 0.01), mdt), "pi": dev(inputs.normal((3, n ** 3), 61, 0.01), mdt)}
+        tb = torch.zeros(2, dtype=torch.float64, device="cuda")
+        if native:
+            plan.run_adj(st, adj, rows, 0.45, tb)
+        else:
+            plan.adj_init(st, adj, rows[-1], 0.45, tb)
+            for i in range(steps - 1, -1, -1):
+                plan.step_adj(st, adj, rows[i], rows[i - 1] if i > 0 else None, 0.45, tb)
+        res.append(fwd + (host(st["s"]), host(st["p"]), host(adj["xi"]), host(adj["pi"]), host(tb)))
+    for a, b in zip(res[0][:-1], res[1][:-1]):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_allclose(res[0][-1], res[1][-1], rtol=1e-12)
