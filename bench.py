@@ -105,11 +105,11 @@ def cpu_baseline(seconds_hint=20.0):
     }
 
 
-def _setup_run(n, nm, box, nsteps, a0, mdt, sdt, seed=None):
+def _setup_run(n, nm, box, nsteps, a0, mdt, sdt, seed=None, checkpoint_steps=()):
     import torch
     from paper_2211_09815_amd import api, inputs
     from paper_2211_09815_amd.simulate import SimConfig, Simulation
-    sim = Simulation(SimConfig(n, nm, box, a0, 1.0, nsteps, mdt, sdt))
+    sim = Simulation(SimConfig(n, nm, box, a0, 1.0, nsteps, mdt, sdt, checkpoint_steps=tuple(checkpoint_steps)))
     cosmo = api.Cosmology()
     tabs = sim.tables(cosmo)
     npdt = "float32" if mdt == torch.float32 else "float64"
@@ -222,6 +222,60 @@ def study_precision(args):
             % (n, nm, box, nsteps, a0), "modes": res, "peak_memory_vs_steps": mem,
             "reversibility_metric": "recovered minus true 2LPT initial state after the reverse-time pass; "
                                     "rms over all particles and axes, in cells and relative to the std of s0 / p0"}
+
+
+def study_checkpoints(args):
+    """Piecewise reverse from forward checkpoints (Sec. 4.1): for FP32 state
+    and for FP32 mesh + FP64 state, the pass time, the checkpoint memory, the
+    reversibility of the recovered initial state and the gradient error
+    against the all-FP64 pass, with 0, 7, 21 and 63 evenly spaced
+    checkpoints."""
+    import torch
+    from paper_2211_09815_amd import inputs
+    n, nm, box, nsteps, a0 = WORKLOADS[args.workload]
+    sim, cosmo, tabs, omega_t = _setup_run(n, nm, box, nsteps, a0, torch.float64, torch.float64,
+                                           seed=inputs.SEED_TARGET)
+    sim.forward(omega_t, cosmo, tabs)
+    target64 = sim.plan.density(sim.s).clone()
+    del sim, omega_t
+    torch.cuda.empty_cache()
+    log("checkpoints: all-FP64 reference")
+    sim, cosmo, tabs, omega = _setup_run(n, nm, box, nsteps, a0, torch.float64, torch.float64)
+    _, g64, th64, _ = _timed_pass(sim, omega, cosmo, target64, tabs)
+    g64 = g64.float()
+    del sim, omega
+    torch.cuda.empty_cache()
+    res = {}
+    for sdt_name, sdt, counts in (("f32", torch.float32, (0, 7, 21, nsteps)), ("f64", torch.float64, (0, 7))):
+        for k in counts:
+            steps = [round((i + 1) * nsteps / k) for i in range(k)] if k else []
+            key = "f32-mesh/%s-state/%d-checkpoints" % (sdt_name, k)
+            log("checkpoints: " + key)
+            sim, cosmo, tabs, omega = _setup_run(n, nm, box, nsteps, a0, torch.float32, sdt, checkpoint_steps=steps)
+            coefs, ic = tabs
+            st0 = {"s": torch.zeros_like(sim.s), "p": torch.zeros_like(sim.p), "acc": None}
+            sim.plan.lpt(omega, cosmo, ic, st0)
+            target = target64.float()
+            _timed_pass(sim, omega, cosmo, target, tabs)  # warm-up
+            J, g, th, dt = _timed_pass(sim, omega, cosmo, target, tabs)
+            s0 = st0["s"].double()
+            ds = sim.s.double() - s0
+            res[key] = {
+                "checkpoint_steps": steps,
+                "checkpoint_memory_gb": 2 * k * sim.s.numel() * sim.s.element_size() / 1e9,
+                "ms_per_pass": 1000 * dt,
+                "particle_steps_per_s": n ** 3 * nsteps / dt,
+                "s0_rms_err_over_std": float(ds.pow(2).mean().sqrt() / s0.std()),
+                "grad_omega_rel_l2_vs_fp64": _rel_l2(g, g64),
+                "dJ_dtheta_rel_err_vs_fp64": [abs(float(a) - float(b)) / abs(float(b))
+                                              for a, b in zip(th.cpu(), th64.cpu())],
+            }
+            del sim, omega, st0, s0, ds, g, target
+            torch.cuda.empty_cache()
+    return {"study": "checkpoints", "workload": "%d^3 particles, %d^3 mesh, %.0f Mpc/h, %d steps a=%.5f..1"
+            % (n, nm, box, nsteps, a0), "runs": res,
+            "note": "checkpoint j holds (s_j, p_{j-1/2}); the reverse pass lands its drift on s_j and takes "
+                    "p_{j-1/2} after its kick; the forward pass is bitwise the same with or without them"}
 
 
 def study_force(args, reps=10):
@@ -349,11 +403,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-ref", action="store_true",
                     help="skip the all-FP64 reference pass used for the gradient rel-L2")
-    ap.add_argument("--study", choices=["precision", "force", "fd-theta"],
+    ap.add_argument("--study", choices=["precision", "force", "fd-theta", "checkpoints"],
                     help="print a study instead of the benchmark line: precision = FP32 / mixed / FP64 "
                          "reversibility, gradient error and memory vs steps; force = single force and VJP "
                          "per stage at 256^3 particles on a 512^3 mesh; fd-theta = dJ/dtheta against central "
-                         "differences")
+                         "differences; checkpoints = piecewise reverse from forward checkpoints")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -367,7 +421,8 @@ def main():
     from paper_2211_09815_amd.simulate import SimConfig, Simulation
     families = _lib.KERNEL_FAMILIES
     if args.study:
-        out = {"precision": study_precision, "force": study_force, "fd-theta": study_fd_theta}[args.study](args)
+        out = {"precision": study_precision, "force": study_force, "fd-theta": study_fd_theta,
+               "checkpoints": study_checkpoints}[args.study](args)
         print(json.dumps(out), flush=True)
         return
 

@@ -212,6 +212,38 @@ int pm_run_fwd(pm_plan plan, pm_state* st, const pm_step_coef* coefs, int n, dou
 int pm_run_adj(pm_plan plan, pm_state* st, pm_adj* adj, const pm_step_coef* coefs, int n,
                double coef, double* theta_bar, hipStream_t stream);
 
+/* ---- piecewise reverse from forward checkpoints (Sec. 4.1) ---------------- */
+/* Where the reverse-time integration drifts too far from the forward
+ * trajectory (long or strongly nonlinear runs, FP32 state), the backward
+ * evolution can be resumed piecewise from states saved during the forward
+ * pass.  Checkpoint j (1 <= j <= n) holds the state at which the reverse step
+ * j starts: s_j and p_{j-1/2}.
+ *   step[k]: host array, strictly increasing steps in [1, n];
+ *   s[k], p[k]: host arrays of device buffers [3][N_p] in the state dtype,
+ *   owned by the caller, written by pm_run_fwd_ckpt, read by pm_run_adj_ckpt.
+ * count == 0 (or ck == NULL) makes both calls the plain loops. */
+typedef struct {
+    int count;
+    const int* step;
+    void* const* s;
+    void* const* p;
+} pm_checkpoints;
+
+/* pm_run_fwd that also copies p_{j-1/2} (before step j) and s_j (after step
+ * j) into checkpoint j.  Extra traffic: two state copies per checkpoint. */
+int pm_run_fwd_ckpt(pm_plan plan, pm_state* st, const pm_step_coef* coefs, int n, double coef,
+                    const pm_checkpoints* ck, hipStream_t stream);
+
+/* pm_run_adj resuming from the checkpoints: the reverse step j + 1 lands its
+ * drift on the stored s_j (the force and its VJP are evaluated there; the
+ * theta term (xi . p) dD and pi += xi D are unchanged) and ends with p set to
+ * the stored p_{j-1/2}; a checkpoint at n sets p_{n-1/2} after pm_adj_init.
+ * xi and pi are integrated as in pm_run_adj.  With a checkpoint at every step
+ * the adjoint runs on the forward trajectory itself.  Errors: PM_EINVAL for
+ * unordered or out-of-range steps or NULL buffers (before any launch). */
+int pm_run_adj_ckpt(pm_plan plan, pm_state* st, pm_adj* adj, const pm_step_coef* coefs, int n,
+                    double coef, const pm_checkpoints* ck, double* theta_bar, hipStream_t stream);
+
 /* ---- a11: objective and its VJP (Sec. 5.2) ------------------------------- */
 /* delta = paint(x) N_c/N_p - 1; *J = (1/N_c) sum (delta - target)^2 (device
  * double, overwritten); disp_bar[k][n] = sum_cell dW/dx_k (2 (delta -

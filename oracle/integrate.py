@@ -15,6 +15,11 @@ Paper passages followed:
     to t_{i-1}, which re-integrates (x, p) backward together with (xi, pi) and
     caches alpha = pi . da/dx and zeta = pi . da/dtheta; the objective gradient
     with respect to theta accumulates the kick and drift factor derivatives.
+  * Sec. 4.1 (end): when the backward evolution drifts from the forward one,
+    it can be resumed piecewise from states saved during the forward pass.
+    Checkpoint j holds s_j and p_{j-1/2}, the values the reverse step j starts
+    from; the reverse pass takes s_j from it when its drift reaches t_j and
+    p_{j-1/2} when its kick does.
 
 theta here is Omega_m only (the step coefficients and the force coefficient
 1.5 Omega_m depend on nothing else); sigma8 enters through the initial
@@ -47,18 +52,22 @@ class ForceModel:
         return xbar, coef_bar * FORCE_COEF_PER_OMEGA_M, a
 
 
-def forward(q, s0, p0, coefs, F, store=True):
+def forward(q, s0, p0, coefs, F, store=True, checkpoints=None):
     """KDK forward (eq. KDFK).  Returns (s_n, p_n, a_n, traj) where traj holds
-    x_i (i = 0..n), p_{i-1/2} (i = 1..n) and a_i (i = 0..n) if store."""
+    x_i (i = 0..n), p_{i-1/2} (i = 1..n) and a_i (i = 0..n) if store.  If
+    `checkpoints` is a dict whose keys are steps j (1..n), each value is set to
+    (s_j, p_{j-1/2})."""
     s = np.array(s0, dtype=np.float64)
     p = np.array(p0, dtype=np.float64)
     a = F(q + s)
     traj = {"x": [q + s], "p_half": [], "a": [a]} if store else None
-    for Ka, D, Kb in coefs:
+    for i, (Ka, D, Kb) in enumerate(coefs, start=1):
         p = p + a * Ka
         if store:
             traj["p_half"].append(p.copy())
         s = s + p * D
+        if checkpoints is not None and i in checkpoints:
+            checkpoints[i] = (s.copy(), p.copy())
         a = F(q + s)
         p = p + a * Kb
         if store:
@@ -96,13 +105,15 @@ def adjoint_stored(traj, coefs, dcoefs, xbar_n, pbar_n, F):
     return xi, pi, th
 
 
-def adjoint_reverse(q, s_n, p_n, a_n, xi_n, pi_n, coefs, dcoefs, F):
+def adjoint_reverse(q, s_n, p_n, a_n, xi_n, pi_n, coefs, dcoefs, F, checkpoints=None):
     """Adjoint KDK with reverse-time integration (eq. KDFKO_adj, KDFKO_grad).
 
     (x, p) are re-integrated backward jointly with (xi, pi); a and the VJP
     caches alpha, zeta are recomputed at each x_{i-1}.  a_n comes from the
-    forward pass; alpha_n, zeta_n from one VJP at x_n.
-    Returns (s_0, p_0, xi_0, pi_0, dJ/dOmega_m from the steps)."""
+    forward pass; alpha_n, zeta_n from one VJP at x_n.  `checkpoints` ({j:
+    (s_j, p_{j-1/2})}, as filled by forward) resumes (x, p) from the saved
+    states.  Returns (s_0, p_0, xi_0, pi_0, dJ/dOmega_m from the steps)."""
+    ck = checkpoints or {}
     s = np.array(s_n, dtype=np.float64)
     p = np.array(p_n, dtype=np.float64)
     xi = np.array(xi_n, dtype=np.float64)
@@ -116,11 +127,15 @@ def adjoint_reverse(q, s_n, p_n, a_n, xi_n, pi_n, coefs, dcoefs, F):
         dKa, dD, dKb = dcoefs[i - 1]
         # K_i^{i-1/2}
         p = p - a * Kb
+        if i in ck:
+            p = np.array(ck[i][1], dtype=np.float64)
         xi = xi + alpha * Kb
         th += np.sum(pi * a) * dKb + zeta * Kb
         # D_i^{i-1}
         th += np.sum(xi * p) * dD
         s = s - p * D
+        if i - 1 in ck:
+            s = np.array(ck[i - 1][0], dtype=np.float64)
         pi = pi + xi * D
         # F_{i-1}
         alpha, zeta, a = F.vjp(q + s, pi)

@@ -101,19 +101,21 @@ class FixedThetaObjective:
         return J
 
 
-def value_and_grad(omega, cfg, target, mode="stored", final_state_out=None):
+def value_and_grad(omega, cfg, target, mode="stored", final_state_out=None, checkpoint_steps=()):
     """J and (dJ/domega, dJ/dOmega_m, dJ/dsigma8).
 
     mode = "stored": discrete adjoint along the stored trajectory (plain chain
     rule, Sec. 4.1); mode = "reverse": adjoint with reverse-time integration
-    (eq. KDFKO_adj).  If `final_state_out` is a dict, the final forward state
-    is stored in it as "s" and "p" ((N, 3) arrays)."""
+    (eq. KDFKO_adj), resumed from forward checkpoints at `checkpoint_steps`
+    (Sec. 4.1) if any.  If `final_state_out` is a dict, the final forward
+    state is stored in it as "s" and "p" ((N, 3) arrays)."""
     q = lattice(cfg)
     s0, p0 = initial_state(omega, cfg)
     om = cfg.cosmo.omega_m
     coefs, dcoefs = cosmology.step_coefficients_with_derivative(cfg.a_grid(), om)
     F = integrate.ForceModel(cfg.mesh_shape, cfg.n_particles, om)
-    s, p, a, traj = integrate.forward(q, s0, p0, coefs, F, store=(mode == "stored"))
+    ck = {int(j): None for j in checkpoint_steps}
+    s, p, a, traj = integrate.forward(q, s0, p0, coefs, F, store=(mode == "stored"), checkpoints=ck)
     if final_state_out is not None:
         final_state_out["s"], final_state_out["p"] = s.copy(), p.copy()
     J, xbar = objective.density_mse(q + s, target, cfg.n_particles)
@@ -121,7 +123,7 @@ def value_and_grad(omega, cfg, target, mode="stored", final_state_out=None):
     if mode == "stored":
         xi0, pi0, th = integrate.adjoint_stored(traj, coefs, dcoefs, xbar, pbar, F)
     else:
-        _, _, xi0, pi0, th = integrate.adjoint_reverse(q, s, p, a, xbar, pbar, coefs, dcoefs, F)
+        _, _, xi0, pi0, th = integrate.adjoint_reverse(q, s, p, a, xbar, pbar, coefs, dcoefs, F, checkpoints=ck)
     g_omega = lpt.lpt_vjp(omega, cfg.box, cfg.cosmo, cfg.a_start, cfg.r, xi0, pi0)
     ds, dp = lpt.lpt_jvp_omega_m(omega, cfg.box, cfg.cosmo, cfg.a_start, cfg.r)
     g_om = th + np.sum(xi0 * ds) + np.sum(pi0 * dp)

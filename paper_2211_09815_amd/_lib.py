@@ -67,6 +67,11 @@ class PmAdj(ctypes.Structure):
     _fields_ = [("xi", c_vp), ("pi", c_vp)]
 
 
+class PmCheckpoints(ctypes.Structure):
+    _fields_ = [("count", c_int), ("step", ctypes.POINTER(c_int)), ("s", ctypes.POINTER(c_vp)),
+                ("p", ctypes.POINTER(c_vp))]
+
+
 class PmCosmo(ctypes.Structure):
     _fields_ = [("omega_m", c_dbl), ("omega_b", c_dbl), ("h", c_dbl), ("n_s", c_dbl),
                 ("sigma8", c_dbl), ("t_cmb", c_dbl)]
@@ -96,6 +101,9 @@ _PROTOS = {
     "pm_step_adj": (c_int, [c_vp, P(PmState), P(PmAdj), P(PmStepCoef), P(PmStepCoef), c_dbl, c_vp, c_vp]),
     "pm_run_fwd": (c_int, [c_vp, P(PmState), P(PmStepCoef), c_int, c_dbl, c_vp]),
     "pm_run_adj": (c_int, [c_vp, P(PmState), P(PmAdj), P(PmStepCoef), c_int, c_dbl, c_vp, c_vp]),
+    "pm_run_fwd_ckpt": (c_int, [c_vp, P(PmState), P(PmStepCoef), c_int, c_dbl, P(PmCheckpoints), c_vp]),
+    "pm_run_adj_ckpt": (c_int, [c_vp, P(PmState), P(PmAdj), P(PmStepCoef), c_int, c_dbl, P(PmCheckpoints), c_vp,
+                                c_vp]),
     "pm_density_mse": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "pm_density": (c_int, [c_vp, c_vp, c_vp, c_vp]),
     "pm_tables": (c_int, [P(PmCosmo), P(c_dbl), c_int, P(PmStepCoef), P(PmIcCoef)]),

@@ -10,7 +10,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import PmAdj, PmConfig, PmCosmo, PmIcCoef, PmState, PmStepCoef, check, lib
+from ._lib import PmAdj, PmCheckpoints, PmConfig, PmCosmo, PmIcCoef, PmState, PmStepCoef, check, lib
 
 _TORCH_DT = {_lib.PM_F32: torch.float32, _lib.PM_F64: torch.float64}
 _CPLX_DT = {_lib.PM_F32: torch.complex64, _lib.PM_F64: torch.complex128}
@@ -257,6 +257,44 @@ class Plan:
         arr, n = self._coef_array(coefs)
         self._c(lib().pm_run_adj(self._h, ctypes.byref(self._st(state)), ctypes.byref(self._adj(adj)), arr, n,
                                  float(coef), _ptr(theta_bar), _stream()))
+
+    def new_checkpoints(self, steps):
+        """Buffers for forward checkpoints at the given steps (1..n): a dict
+        with "step" (sorted list), "s" and "p" (lists of [3, N_p] tensors)."""
+        steps = sorted(int(j) for j in steps)
+        n = self.n_particles
+        mk = lambda: torch.empty((3, n), dtype=self.sdt, device=self.device)  # noqa: E731
+        return {"step": steps, "s": [mk() for _ in steps], "p": [mk() for _ in steps]}
+
+    def _ck(self, ck):
+        if ck is None:
+            return None, ()
+        for t in list(ck["s"]) + list(ck["p"]):
+            self._t(t, self.sdt, 3 * self.n_particles, "checkpoint")
+        k = len(ck["step"])
+        steps = (ctypes.c_int * max(k, 1))(*ck["step"])
+        sp = (ctypes.c_void_p * max(k, 1))(*[t.data_ptr() for t in ck["s"]])
+        pp = (ctypes.c_void_p * max(k, 1))(*[t.data_ptr() for t in ck["p"]])
+        c = PmCheckpoints(k, ctypes.cast(steps, ctypes.POINTER(ctypes.c_int)),
+                          ctypes.cast(sp, ctypes.POINTER(ctypes.c_void_p)),
+                          ctypes.cast(pp, ctypes.POINTER(ctypes.c_void_p)))
+        return c, (steps, sp, pp)     # keep the arrays alive for the call
+
+    def run_fwd_ckpt(self, state, coefs, coef, checkpoints):
+        arr, n = self._coef_array(coefs)
+        c, keep = self._ck(checkpoints)
+        self._c(lib().pm_run_fwd_ckpt(self._h, ctypes.byref(self._st(state)), arr, n, float(coef),
+                                      ctypes.byref(c) if c is not None else None, _stream()))
+        del keep
+
+    def run_adj_ckpt(self, state, adj, coefs, coef, checkpoints, theta_bar):
+        self._t(theta_bar, torch.float64, 2, "theta_bar")
+        arr, n = self._coef_array(coefs)
+        c, keep = self._ck(checkpoints)
+        self._c(lib().pm_run_adj_ckpt(self._h, ctypes.byref(self._st(state)), ctypes.byref(self._adj(adj)), arr,
+                                      n, float(coef), ctypes.byref(c) if c is not None else None,
+                                      _ptr(theta_bar), _stream()))
+        del keep
 
     def density_mse(self, disp, target, want_grad=True):
         """(J device FP64 scalar, disp_bar or None)."""

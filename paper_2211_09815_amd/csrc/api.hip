@@ -174,6 +174,88 @@ int check_step(Plan* p, const pm_step_coef* c, const char* name) {
   return PM_OK;
 }
 
+size_t state_bytes(const Plan* p);
+
+int check_adj_args(Plan* p, const pm_state* stt, const pm_adj* adj, const pm_step_coef* cur,
+                   const pm_step_coef* prev, double coef, const double* theta_bar) {
+  if (!stt || !adj) return set_error(p, PM_EINVAL, "state or adjoint is NULL");
+  if (int rc = check_ptr(p, stt->s, "state.s")) return rc;
+  if (int rc = check_ptr(p, stt->p, "state.p")) return rc;
+  if (int rc = check_ptr(p, adj->xi, "adj.xi")) return rc;
+  if (int rc = check_ptr(p, adj->pi, "adj.pi")) return rc;
+  if (int rc = check_ptr(p, theta_bar, "theta_bar")) return rc;
+  if (int rc = check_step(p, cur, "cur")) return rc;
+  if (prev)
+    if (int rc = check_step(p, prev, "prev")) return rc;
+  return check_coef(p, coef);
+}
+
+// Reverse step i (eq. KDFKO_adj with merged kicks).  With s_set, the drift
+// lands on the stored positions s_{i-1} instead of s_i - p_{i-1/2} D_i; with
+// p_set, p_{i-3/2} is replaced by the stored momentum after the kick.
+int step_adj(Plan* p, pm_state* stt, pm_adj* adj, const pm_step_coef* cur, const pm_step_coef* prev, double coef,
+             double* theta_bar, const void* s_set, const void* p_set, hipStream_t st) {
+  PaintArgs pa{};
+  pa.s = stt->s;
+  pa.p = stt->p;
+  pa.xi = adj->xi;
+  pa.pi = adj->pi;
+  pa.unit = 1;
+  pa.nw = 3;
+  pa.mesh = p->mesh[0];
+  pa.D = cur->D;
+  pa.partials = p->partials;
+  pa.s_set = s_set;
+  if (int rc = paint_launch(p, s_set ? DRIFT_SET : DRIFT_ADJ, pa, st)) return rc;
+  if (int rc = vjp_fields_any(p, coef, st)) return rc;
+  const double K = cur->Ka + (prev ? prev->Kb : 0.0);
+  const double dK = cur->dKa + (prev ? prev->dKb : 0.0);
+  GatherArgs ga{};
+  ga.s = stt->s;
+  ga.mesh = p->mesh[0];
+  ga.nf = 4;
+  ga.p = stt->p;
+  ga.xi = adj->xi;
+  ga.cot = adj->pi;
+  ga.K = K;
+  ga.binned = true;
+  if (int rc = gather_launch(p, GATHER_KICK_ADJ, ga, st)) return rc;
+  // theta_bar[0] += (xi.p) dD  (drift partials)  +  (pi.a)(dK + K 1.5/coef)  (tile partials)
+  const double fd[4] = {cur->dD, 0.0, 0.0, 0.0};
+  if (int rc = reduce_partials(p, blocks_for_particles(p), fd, theta_bar, true, st)) return rc;
+  const double fk[4] = {0.0, dK + K * 1.5 / coef, 0.0, 0.0};
+  if (int rc = reduce_buffer(p, p->tile_partials, p->ntiles, fk, theta_bar, true, st)) return rc;
+  if (p_set) PM_HIP_CHECK(p, hipMemcpyAsync(stt->p, p_set, state_bytes(p), hipMemcpyDeviceToDevice, st));
+  return PM_OK;
+}
+
+size_t state_bytes(const Plan* p) {
+  return size_t(3) * size_t(p->nptcl) * (p->cfg.state_dtype == PM_F64 ? 8 : 4);
+}
+
+// checkpoint steps strictly increasing in [1, n], every buffer given
+int check_checkpoints(Plan* p, const pm_checkpoints* ck, int n) {
+  if (!ck) return PM_OK;
+  if (ck->count < 0) return set_error(p, PM_EINVAL, "checkpoint count must be >= 0");
+  if (ck->count == 0) return PM_OK;
+  if (!ck->step || !ck->s || !ck->p) return set_error(p, PM_EINVAL, "checkpoint arrays are NULL");
+  for (int k = 0; k < ck->count; ++k) {
+    const int j = ck->step[k];
+    if (j < 1 || j > n) return set_error(p, PM_EINVAL, "checkpoint step %d outside [1, %d]", j, n);
+    if (k > 0 && j <= ck->step[k - 1]) return set_error(p, PM_EINVAL, "checkpoint steps must increase");
+    if (!ck->s[k] || !ck->p[k]) return set_error(p, PM_EINVAL, "checkpoint %d has a NULL buffer", j);
+  }
+  return PM_OK;
+}
+
+// index of step j among the checkpoints, or -1
+int checkpoint_index(const pm_checkpoints* ck, int j) {
+  if (!ck) return -1;
+  for (int k = 0; k < ck->count; ++k)
+    if (ck->step[k] == j) return k;
+  return -1;
+}
+
 }  // namespace
 
 extern "C" {
@@ -542,46 +624,9 @@ int pm_adj_init(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* last,
 int pm_step_adj(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* cur, const pm_step_coef* prev,
                 double coef, double* theta_bar, hipStream_t st) {
   CHECK_PLAN(h);
-  if (!stt || !adj) return set_error(p, PM_EINVAL, "state or adjoint is NULL");
-  if (int rc = check_ptr(p, stt->s, "state.s")) return rc;
-  if (int rc = check_ptr(p, stt->p, "state.p")) return rc;
-  if (int rc = check_ptr(p, adj->xi, "adj.xi")) return rc;
-  if (int rc = check_ptr(p, adj->pi, "adj.pi")) return rc;
-  if (int rc = check_ptr(p, theta_bar, "theta_bar")) return rc;
-  if (int rc = check_step(p, cur, "cur")) return rc;
-  if (prev)
-    if (int rc = check_step(p, prev, "prev")) return rc;
-  if (int rc = check_coef(p, coef)) return rc;
+  if (int rc = check_adj_args(p, stt, adj, cur, prev, coef, theta_bar)) return rc;
   if (int rc = set_device(p)) return rc;
-  PaintArgs pa{};
-  pa.s = stt->s;
-  pa.p = stt->p;
-  pa.xi = adj->xi;
-  pa.pi = adj->pi;
-  pa.unit = 1;
-  pa.nw = 3;
-  pa.mesh = p->mesh[0];
-  pa.D = cur->D;
-  pa.partials = p->partials;
-  if (int rc = paint_launch(p, DRIFT_ADJ, pa, st)) return rc;
-  if (int rc = vjp_fields_any(p, coef, st)) return rc;
-  const double K = cur->Ka + (prev ? prev->Kb : 0.0);
-  const double dK = cur->dKa + (prev ? prev->dKb : 0.0);
-  GatherArgs ga{};
-  ga.s = stt->s;
-  ga.mesh = p->mesh[0];
-  ga.nf = 4;
-  ga.p = stt->p;
-  ga.xi = adj->xi;
-  ga.cot = adj->pi;
-  ga.K = K;
-  ga.binned = true;
-  if (int rc = gather_launch(p, GATHER_KICK_ADJ, ga, st)) return rc;
-  // theta_bar[0] += (xi.p) dD  (drift partials)  +  (pi.a)(dK + K 1.5/coef)  (tile partials)
-  const double fd[4] = {cur->dD, 0.0, 0.0, 0.0};
-  if (int rc = reduce_partials(p, blocks_for_particles(p), fd, theta_bar, true, st)) return rc;
-  const double fk[4] = {0.0, dK + K * 1.5 / coef, 0.0, 0.0};
-  return reduce_buffer(p, p->tile_partials, p->ntiles, fk, theta_bar, true, st);
+  return step_adj(p, stt, adj, cur, prev, coef, theta_bar, nullptr, nullptr, st);
 }
 
 int pm_run_fwd(pm_plan h, pm_state* stt, const pm_step_coef* coefs, int n, double coef, hipStream_t st) {
@@ -601,6 +646,42 @@ int pm_run_adj(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* coefs,
   for (int i = n - 1; i >= 0; --i)
     if (int rc = pm_step_adj(h, stt, adj, &coefs[i], i > 0 ? &coefs[i - 1] : nullptr, coef, theta_bar, st))
       return rc;
+  return PM_OK;
+}
+
+int pm_run_fwd_ckpt(pm_plan h, pm_state* stt, const pm_step_coef* coefs, int n, double coef,
+                    const pm_checkpoints* ck, hipStream_t st) {
+  CHECK_PLAN(h);
+  if (!coefs || n < 1) return set_error(p, PM_EINVAL, "need n >= 1 step coefficients");
+  if (int rc = check_checkpoints(p, ck, n)) return rc;
+  if (int rc = pm_fwd_init(h, stt, &coefs[0], coef, st)) return rc;
+  const size_t bytes = state_bytes(p);
+  for (int i = 0; i < n; ++i) {
+    const int k = checkpoint_index(ck, i + 1);
+    if (k >= 0) PM_HIP_CHECK(p, hipMemcpyAsync(ck->p[k], stt->p, bytes, hipMemcpyDeviceToDevice, st));
+    if (int rc = pm_step_fwd(h, stt, &coefs[i], i + 1 < n ? &coefs[i + 1] : nullptr, coef, st)) return rc;
+    if (k >= 0) PM_HIP_CHECK(p, hipMemcpyAsync(ck->s[k], stt->s, bytes, hipMemcpyDeviceToDevice, st));
+  }
+  return PM_OK;
+}
+
+int pm_run_adj_ckpt(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* coefs, int n, double coef,
+                    const pm_checkpoints* ck, double* theta_bar, hipStream_t st) {
+  CHECK_PLAN(h);
+  if (!coefs || n < 1) return set_error(p, PM_EINVAL, "need n >= 1 step coefficients");
+  if (int rc = check_checkpoints(p, ck, n)) return rc;
+  for (int i = 0; i < n; ++i)
+    if (int rc = check_step(p, &coefs[i], "coefs[i]")) return rc;
+  if (int rc = pm_adj_init(h, stt, adj, &coefs[n - 1], coef, theta_bar, st)) return rc;
+  const int kn = checkpoint_index(ck, n);
+  if (kn >= 0) PM_HIP_CHECK(p, hipMemcpyAsync(stt->p, ck->p[kn], state_bytes(p), hipMemcpyDeviceToDevice, st));
+  for (int i = n - 1; i >= 0; --i) {
+    // reverse step i + 1 ends at t_i: resume from checkpoint i if there is one
+    const int k = i >= 1 ? checkpoint_index(ck, i) : -1;
+    if (int rc = step_adj(p, stt, adj, &coefs[i], i > 0 ? &coefs[i - 1] : nullptr, coef, theta_bar,
+                          k >= 0 ? ck->s[k] : nullptr, k >= 0 ? ck->p[k] : nullptr, st))
+      return rc;
+  }
   return PM_OK;
 }
 

@@ -43,6 +43,7 @@ struct BinP {
   unsigned* counts;   // [ntiles]
   uint2* keys;        // [N] (tile, rank)
   double* partials;   // slot 0: xi.p (adjoint drift)
+  const S* s_set;     // DRIFT_SET: displacement after the drift
 };
 
 // Each thread takes U particles per round, all loads issued first.  Lanes of
@@ -69,9 +70,9 @@ __global__ __launch_bounds__(kThreads) void k_bin(BinP<S, T> a) {
       if (!valid[u]) continue;
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) {
-        sv[u][ax] = a.s[ax * g.N + n];
+        sv[u][ax] = (MODE == DRIFT_SET ? a.s_set : a.s)[ax * g.N + n];
         if (MODE != DRIFT_NONE) pv[u][ax] = a.p[ax * g.N + n];
-        if (MODE == DRIFT_ADJ) {
+        if (MODE == DRIFT_ADJ || MODE == DRIFT_SET) {
           xv[u][ax] = a.xi[ax * g.N + n];
           piv[u][ax] = a.pi[ax * g.N + n];
         }
@@ -88,11 +89,11 @@ __global__ __launch_bounds__(kThreads) void k_bin(BinP<S, T> a) {
           sv[u][ax] += pv[u][ax] * a.D;
           a.s[ax * g.N + n] = sv[u][ax];
         }
-      } else if (MODE == DRIFT_ADJ) {
+      } else if (MODE == DRIFT_ADJ || MODE == DRIFT_SET) {
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
           xp += double(xv[u][ax]) * double(pv[u][ax]);
-          sv[u][ax] -= pv[u][ax] * a.D;
+          if (MODE == DRIFT_ADJ) sv[u][ax] -= pv[u][ax] * a.D;
           a.s[ax * g.N + n] = sv[u][ax];
           a.pi[ax * g.N + n] = piv[u][ax] + T(xv[u][ax] * T(a.D));
         }
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(kThreads) void k_bin(BinP<S, T> a) {
       if (valid[u]) a.keys[n] = make_uint2(unsigned(tile[u]), b + within[u]);
     }
   }
-  if (MODE == DRIFT_ADJ) {
+  if (MODE == DRIFT_ADJ || MODE == DRIFT_SET) {
     const double t = block_sum_d(xp);
     if (threadIdx.x == 0) a.partials[blockIdx.x * 4 + 0] = t;
   }
@@ -462,16 +463,19 @@ int bin_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
   b.counts = p->bin_counts;
   b.keys = static_cast<uint2*>(p->bin_keys);
   b.partials = in.partials;
+  b.s_set = static_cast<const S*>(in.s_set);
   timing_begin(p, PM_K_BIN, st);
   if (mode == DRIFT_FWD) hipLaunchKernelGGL((k_bin<S, T, DRIFT_FWD>), dim3(pblocks), block, 0, st, b);
   else if (mode == DRIFT_ADJ) hipLaunchKernelGGL((k_bin<S, T, DRIFT_ADJ>), dim3(pblocks), block, 0, st, b);
+  else if (mode == DRIFT_SET) hipLaunchKernelGGL((k_bin<S, T, DRIFT_SET>), dim3(pblocks), block, 0, st, b);
   else hipLaunchKernelGGL((k_bin<S, T, DRIFT_NONE>), dim3(pblocks), block, 0, st, b);
   {
-    // s read (+ p read, s write; adjoint: xi read, pi read/write), key write
+    // s (or s_set) read (+ p read, s write; adjoint: xi read, pi read/write),
+    // key write
     const double N = double(g.N), sb = sizeof(S), mb = sizeof(T);
     double bytes = 3 * N * sb + 8 * N;
     if (mode == DRIFT_FWD) bytes += 6 * N * sb;
-    if (mode == DRIFT_ADJ) bytes += 6 * N * sb + 9 * N * mb;
+    if (mode == DRIFT_ADJ || mode == DRIFT_SET) bytes += 6 * N * sb + 9 * N * mb;
     timing_end(p, PM_K_BIN, st, bytes);
   }
   const int64_t nt = g.ntiles;
@@ -497,7 +501,7 @@ int paint_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
   if (int rc = bin_typed<S, T>(p, mode, in, st)) return rc;
   const S* s = static_cast<const S*>(in.s);
   // in the adjoint drift the weighted channels are the updated pi
-  const T* w = static_cast<const T*>(mode == DRIFT_ADJ ? in.pi : in.w);
+  const T* w = static_cast<const T*>(mode == DRIFT_ADJ || mode == DRIFT_SET ? in.pi : in.w);
   T* mesh = static_cast<T*>(in.mesh);
   T* halo = static_cast<T*>(p->bin_halo);
   const dim3 tg{unsigned(nt), 1, 1};

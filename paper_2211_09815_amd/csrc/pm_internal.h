@@ -165,7 +165,9 @@ int poisson_grad_spec(Plan* p, const FftShape& s, const cplx<T>* in, cplx<T>* ou
 // ---------------------------------------------------------------------------
 // particle kernels (particles.hip)
 // ---------------------------------------------------------------------------
-enum DriftMode { DRIFT_NONE = 0, DRIFT_FWD = 1, DRIFT_ADJ = 2 };
+// DRIFT_SET: the adjoint drift with the new positions taken from s_set (a
+// forward checkpoint) instead of s - p D
+enum DriftMode { DRIFT_NONE = 0, DRIFT_FWD = 1, DRIFT_ADJ = 2, DRIFT_SET = 3 };
 
 struct PaintArgs {
   const void* s;        // [3][N] state
@@ -179,6 +181,7 @@ struct PaintArgs {
   void* mesh;           // [nch][ncell]
   double D;             // drift coefficient
   double* partials;     // per-block partial sum of xi.p (adjoint drift)
+  const void* s_set;    // DRIFT_SET: [3][N] state dtype, positions to land on
 };
 int paint_launch(Plan* p, DriftMode mode, const PaintArgs& a, hipStream_t st);
 // tile binning only (drift + bins + per-tile lists), as done by paint_launch

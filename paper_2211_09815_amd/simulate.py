@@ -24,6 +24,9 @@ class SimConfig:
     mesh_dtype: torch.dtype = torch.float32
     state_dtype: torch.dtype = torch.float64
     lattice_offset: float = 0.0
+    # steps j (1..n_steps) whose forward state (s_j, p_{j-1/2}) is saved for
+    # the piecewise reverse pass (Sec. 4.1); empty: plain reverse integration
+    checkpoint_steps: tuple = ()
 
     @property
     def n_particles(self):
@@ -47,6 +50,7 @@ class Simulation:
         self.xi = torch.zeros((3, n), dtype=self.plan.mdt, device=dev)
         self.pi = torch.zeros((3, n), dtype=self.plan.mdt, device=dev)
         self.theta_bar = torch.zeros(2, dtype=torch.float64, device=dev)
+        self.checkpoints = self.plan.new_checkpoints(cfg.checkpoint_steps) if cfg.checkpoint_steps else None
 
     def state(self):
         return {"s": self.s, "p": self.p, "acc": self.acc}
@@ -62,7 +66,10 @@ class Simulation:
         coefs, ic = tables if tables is not None else self.tables(cosmo)
         st = self.state()
         self.plan.lpt(omega, cosmo, ic, st)
-        self.plan.run_fwd(st, coefs, 1.5 * cosmo.omega_m)
+        if self.checkpoints is None:
+            self.plan.run_fwd(st, coefs, 1.5 * cosmo.omega_m)
+        else:
+            self.plan.run_fwd_ckpt(st, coefs, 1.5 * cosmo.omega_m, self.checkpoints)
         return coefs, ic
 
     def final_density(self, omega, cosmo):
@@ -76,7 +83,11 @@ class Simulation:
         self.xi.copy_(xbar)
         self.pi.zero_()
         self.theta_bar.zero_()
-        self.plan.run_adj(self.state(), self.adj(), coefs, 1.5 * cosmo.omega_m, self.theta_bar)
+        if self.checkpoints is None:
+            self.plan.run_adj(self.state(), self.adj(), coefs, 1.5 * cosmo.omega_m, self.theta_bar)
+        else:
+            self.plan.run_adj_ckpt(self.state(), self.adj(), coefs, 1.5 * cosmo.omega_m, self.checkpoints,
+                                   self.theta_bar)
         g_omega = self.plan.lpt_vjp(omega, cosmo, ic, self.adj(), self.theta_bar)
         return J, g_omega, self.theta_bar.clone()
 

@@ -255,3 +255,139 @@ def test_native_loops_match_step_calls(mdt, sdt):
     for a, b in zip(res[0][:-1], res[1][:-1]):
         np.testing.assert_array_equal(a, b)
     np.testing.assert_allclose(res[0][-1], res[1][-1], rtol=1e-12)
+
+
+# ---- piecewise reverse from forward checkpoints (Sec. 4.1) --------------------
+
+def test_piecewise_reverse_fp64_vs_oracle():
+    # FP64 GPU pass resumed from checkpoints at steps 2, 5, 9, 10 against the
+    # oracle's reverse pass with the same checkpoints and its stored-trajectory
+    # gradient
+    from paper_2211_09815_amd.simulate import SimConfig, Simulation
+    api = _api()
+    announce("piecewise reverse FP64 32^3/64^3 10 steps")
+    n, nm, box, steps, a0, ck = 32, 64, 128.0, 10, 1 / 16, (2, 5, 9, 10)
+    ocfg = osim.SimConfig(n, nm, box, a0, 1.0, steps)
+    omega = inputs.white_noise(n, inputs.SEED_RUN)
+    target = osim.final_density(inputs.white_noise(n, inputs.SEED_TARGET), ocfg)
+    J_ref, g_ref, t_ref = osim.value_and_grad(omega, ocfg, target, mode="reverse", checkpoint_steps=ck)
+    J_st, g_st, t_st = osim.value_and_grad(omega, ocfg, target, mode="stored")
+    sim = Simulation(SimConfig(n, nm, box, a0, 1.0, steps, torch.float64, torch.float64, checkpoint_steps=ck))
+    J, g, t = (host(x) for x in sim.value_and_grad(dev(omega, torch.float64), api.Cosmology(),
+                                                  dev(target, torch.float64)))
+    assert J[0] == pytest.approx(J_ref, rel=1e-10)
+    assert rel_l2(g, g_ref) < 1e-8
+    np.testing.assert_allclose(t, t_ref, rtol=1e-8)
+    assert rel_l2(g, g_st) < 1e-8
+    np.testing.assert_allclose(t, t_st, rtol=1e-8)
+    # the checkpoints hold the oracle's forward states (s_j, p_{j-1/2})
+    q = osim.lattice(ocfg)
+    s0, p0 = osim.initial_state(omega, ocfg)
+    coefs = ocos.step_coefficients(ocfg.a_grid(), 0.3)
+    F = oint.ForceModel(ocfg.mesh_shape, ocfg.n_particles, 0.3)
+    ock = {j: None for j in ck}
+    oint.forward(q, s0, p0, coefs, F, store=False, checkpoints=ock)
+    for k, j in enumerate(ck):
+        assert rel_l2(aos(host(sim.checkpoints["s"][k])), ock[j][0]) < 1e-11
+        assert rel_l2(aos(host(sim.checkpoints["p"][k])), ock[j][1]) < 1e-11
+
+
+def _ck_pass(plan, rows, s0, p0, sdt, mdt, ck, xi_n, pi_n, wipe_p=False):
+    n3 = s0.shape[0]
+    st = plan.new_state(dev(soa(s0), sdt), dev(soa(p0), sdt))
+    plan.run_fwd_ckpt(st, rows, 0.45, ck)
+    fwd = (host(st["s"]), host(st["p"]))
+    if wipe_p:
+        st["p"].zero_()
+    adj = {"xi": dev(xi_n, mdt), "pi": dev(pi_n, mdt)}
+    tb = torch.zeros(2, dtype=torch.float64, device="cuda")
+    plan.run_adj_ckpt(st, adj, rows, 0.45, ck, tb)
+    assert adj["xi"].shape == (3, n3)
+    return fwd, (host(st["s"]), host(st["p"]), host(adj["xi"]), host(adj["pi"]), host(tb))
+
+
+def test_checkpoint_at_last_step_replaces_final_momentum():
+    # with a checkpoint at step n the reverse pass takes p_{n-1/2} from it: a
+    # wiped final momentum changes nothing, bit for bit
+    api = _api()
+    announce("checkpoint at the last step, mixed 16^3/32^3 6 steps")
+    n, nm, box, steps = 16, 32, 64.0, 6
+    cfg = osim.SimConfig(n, nm, box, 1 / 16, 1.0, steps)
+    s0, p0 = osim.initial_state(inputs.white_noise(n, 0), cfg)
+    coefs, dcoefs = ocos.step_coefficients_with_derivative(cfg.a_grid(), 0.3)
+    rows = np.concatenate([coefs, dcoefs], axis=1)
+    plan = api.Plan(nm, n, box=box, mesh_dtype=torch.float32, state_dtype=torch.float64)
+    xi_n = inputs.normal((3, n ** 3), 60, 0.01)
+    pi_n = inputs.normal((3, n ** 3), 61, 0.01)
+    ck = plan.new_checkpoints((3, steps))
+    f1, r1 = _ck_pass(plan, rows, s0, p0, torch.float64, torch.float32, ck, xi_n, pi_n)
+    f2, r2 = _ck_pass(plan, rows, s0, p0, torch.float64, torch.float32, ck, xi_n, pi_n, wipe_p=True)
+    for a, b in zip(f1 + r1[:4], f2 + r2[:4]):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_allclose(r1[4], r2[4], rtol=1e-12)     # theta_bar: FP64 partial sums in any order
+    # the checkpointed forward loop leaves the state of the plain loop
+    st = plan.new_state(dev(soa(s0), torch.float64), dev(soa(p0), torch.float64))
+    plan.run_fwd(st, rows, 0.45)
+    np.testing.assert_array_equal(host(st["s"]), f1[0])
+    np.testing.assert_array_equal(host(st["p"]), f1[1])
+    # no checkpoints: the loops equal pm_run_fwd / pm_run_adj
+    empty = plan.new_checkpoints(())
+    f3, r3 = _ck_pass(plan, rows, s0, p0, torch.float64, torch.float32, empty, xi_n, pi_n)
+    adj = {"xi": dev(xi_n, torch.float32), "pi": dev(pi_n, torch.float32)}
+    tb = torch.zeros(2, dtype=torch.float64, device="cuda")
+    plan.run_adj(st, adj, rows, 0.45, tb)
+    for a, b in zip(r3[:4], (host(st["s"]), host(st["p"]), host(adj["xi"]), host(adj["pi"]))):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_allclose(r3[4], host(tb), rtol=1e-12)
+
+
+def test_checkpoints_reject_bad_steps():
+    api = _api()
+    from paper_2211_09815_amd._lib import PM_EINVAL, PmError
+    n, nm, steps = 8, 16, 4
+    plan = api.Plan(nm, n, box=32.0, mesh_dtype=torch.float32, state_dtype=torch.float64)
+    rows = np.tile(np.array([[0.1, 0.1, 0.1, 0.0, 0.0, 0.0]]), (steps, 1))
+    st = plan.new_state(torch.zeros((3, n ** 3), dtype=torch.float64, device="cuda"),
+                        torch.zeros((3, n ** 3), dtype=torch.float64, device="cuda"))
+    for bad in ((3, 2), (0,), (5,), (2, 2)):
+        ck = plan.new_checkpoints(())
+        ck["step"] = list(bad)
+        ck["s"] = [torch.zeros((3, n ** 3), dtype=torch.float64, device="cuda") for _ in bad]
+        ck["p"] = [torch.zeros((3, n ** 3), dtype=torch.float64, device="cuda") for _ in bad]
+        with pytest.raises(PmError) as e:
+            plan.run_fwd_ckpt(st, rows, 0.45, ck)
+        assert e.value.code == PM_EINVAL
+
+
+def test_checkpoints_reduce_the_reversal_error_of_fp32_state():
+    # FP32 state in a strongly nonlinear box (1 Mpc/h particle spacing, 40
+    # steps from a = 1/64): the forward pass is the same with or without
+    # checkpoints (deterministic paint), so with a checkpoint at every step
+    # the adjoint runs on the forward trajectory itself, and sparser
+    # checkpoints fall between that and the plain reverse-time pass
+    api = _api()
+    n, nm, box, steps = 32, 32, 32.0, 40
+    announce("checkpoint spacing vs reversal error, FP32 state %d^3 %d steps" % (n, steps))
+    cfg = osim.SimConfig(n, nm, box, 1 / 64, 1.0, steps)
+    s0, p0 = osim.initial_state(inputs.white_noise(n, 0), cfg)
+    coefs, dcoefs = ocos.step_coefficients_with_derivative(cfg.a_grid(), 0.3)
+    rows = np.concatenate([coefs, dcoefs], axis=1)
+    plan = api.Plan(nm, n, box=box, mesh_dtype=torch.float32, state_dtype=torch.float32)
+    xi_n = inputs.normal((3, n ** 3), 62, 0.01)
+    pi_n = np.zeros((3, n ** 3))
+    res = {}
+    for name, ck_steps in (("all", range(1, steps + 1)), ("every4", range(4, steps + 1, 4)), ("none", ())):
+        ck = plan.new_checkpoints(ck_steps)
+        f, r = _ck_pass(plan, rows, s0, p0, torch.float32, torch.float32, ck, xi_n, pi_n)
+        res[name] = (f, r)
+    for a, b in zip(res["all"][0], res["none"][0]):
+        np.testing.assert_array_equal(a, b)
+    g_all = res["all"][1][2]
+    e4 = rel_l2(res["every4"][1][2], g_all)
+    e0 = rel_l2(res["none"][1][2], g_all)
+    s_true = soa(s0)
+    rev = {k: np.sqrt(np.mean((v[1][0] - s_true) ** 2)) / s_true.std() for k, v in res.items()}
+    print("xi_0 rel-L2 vs every-step checkpoints: every 4: %.3g, none: %.3g; s_0 recovery %s" % (e4, e0, rev))
+    assert e0 > 0
+    assert e4 < e0
+    assert rev["all"] <= rev["every4"] <= rev["none"]

@@ -83,6 +83,58 @@ def test_reverse_time_adjoint_matches_stored_trajectory():
     np.testing.assert_allclose(t1, t2, rtol=1e-8)
 
 
+def test_checkpoints_hold_the_states_of_the_stored_trajectory():
+    # checkpoint j is (s_j, p_{j-1/2}): the positions after step j and the
+    # momentum its drift used
+    cfg, omega = _small_run(steps=5)
+    q = simulate.lattice(cfg)
+    s0, p0 = simulate.initial_state(omega, cfg)
+    coefs = C.step_coefficients(cfg.a_grid(), cfg.cosmo.omega_m)
+    F = integrate.ForceModel(cfg.mesh_shape, cfg.n_particles, cfg.cosmo.omega_m)
+    ck = {1: None, 3: None, 5: None}
+    integrate.forward(q, s0, p0, coefs, F, store=True, checkpoints=ck)
+    _, _, _, traj = integrate.forward(q, s0, p0, coefs, F, store=True)
+    for j, (s_j, p_j) in ck.items():
+        np.testing.assert_array_equal(q + s_j, traj["x"][j])
+        np.testing.assert_array_equal(p_j, traj["p_half"][j - 1])
+
+
+@pytest.mark.parametrize("steps_ck", [(2,), (1, 3, 5), (1, 2, 3, 4, 5)])
+def test_piecewise_reverse_matches_stored_trajectory(steps_ck):
+    # resuming (x, p) from checkpoints leaves the gradient of the discrete
+    # map unchanged; a checkpoint restored one step early or late would move
+    # the positions by a whole drift and fail this by orders of magnitude
+    cfg, omega = _small_run(steps=5)
+    target = simulate.final_density(inputs.white_noise(cfg.n_ptcl, 1), cfg)
+    J1, g1, t1 = simulate.value_and_grad(omega, cfg, target, mode="stored")
+    J2, g2, t2 = simulate.value_and_grad(omega, cfg, target, mode="reverse", checkpoint_steps=steps_ck)
+    assert J1 == J2
+    assert np.linalg.norm(g1 - g2) / np.linalg.norm(g1) < 1e-8
+    np.testing.assert_allclose(t1, t2, rtol=1e-8)
+
+
+def test_checkpoint_at_last_step_replaces_the_reconstructed_momentum():
+    # with a checkpoint at step n the reverse pass takes p_{n-1/2} from it, so
+    # a wrong final momentum has no effect at all; without it, it does
+    cfg, omega = _small_run(steps=4)
+    q = simulate.lattice(cfg)
+    s0, p0 = simulate.initial_state(omega, cfg)
+    om = cfg.cosmo.omega_m
+    coefs, dcoefs = C.step_coefficients_with_derivative(cfg.a_grid(), om)
+    F = integrate.ForceModel(cfg.mesh_shape, cfg.n_particles, om)
+    ck = {4: None}
+    s, p, a, _ = integrate.forward(q, s0, p0, coefs, F, store=False, checkpoints=ck)
+    xi = inputs.normal(s.shape, 70)
+    pi = inputs.normal(s.shape, 71, 0.1)
+    wrong = p + inputs.normal(p.shape, 72)
+    good = integrate.adjoint_reverse(q, s, p, a, xi, pi, coefs, dcoefs, F, checkpoints=ck)
+    bad = integrate.adjoint_reverse(q, s, wrong, a, xi, pi, coefs, dcoefs, F, checkpoints=ck)
+    for u, v in zip(good, bad):
+        np.testing.assert_array_equal(u, v)
+    plain = integrate.adjoint_reverse(q, s, wrong, a, xi, pi, coefs, dcoefs, F)
+    assert np.linalg.norm(plain[2] - good[2]) > 1e-3 * np.linalg.norm(good[2])
+
+
 @pytest.mark.slow
 def test_end_to_end_gradient_brute_force_fd():
     # every one of the 8^3 white-noise entries and both theta components
