@@ -224,9 +224,9 @@ constexpr int kPaintThreads = 512;  // threads per tile workgroup of the paint
 
 // One workgroup per tile; weights: channel 0 unit mass if UNIT, then w[c].
 // Particles are taken in chunks of P per thread whose loads are all issued
-// before any is used.  A tile whose particles fit in one chunk (the common
-// case) takes the per-channel bound max|w| from the registers; larger tiles
-// read their weights once more for it.
+// before any is used.  A tile whose particles fit in one chunk takes the
+// per-channel bound max|w| from the registers; larger tiles (the common case
+// with three or more channels) read their weights once more for it.
 template <typename S, typename T, int NCH, bool UNIT>
 __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const S* __restrict__ s,
                                                           const T* __restrict__ w, const unsigned* __restrict__ offs,
@@ -236,7 +236,9 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
   constexpr int NWR = NW > 0 ? NW : 1;
   constexpr bool F32 = sizeof(T) == 4;
   constexpr int kHead = F32 ? 51 : 61;         // bits of headroom of the fixed point
-  constexpr int P = 2048 / kPaintThreads;
+  // particles per thread per chunk; one with three or more channels, which
+  // brings the register use under the three workgroups per CU that LDS allows
+  constexpr int P = (NCH >= 3 ? 512 : 2048) / kPaintThreads;
   constexpr unsigned CHUNK = P * kPaintThreads;
   constexpr unsigned NONE = 0xffffffffu;
   __shared__ unsigned long long box[NCH * kBoxMax];

@@ -43,7 +43,9 @@ constexpr int kGatherThreads = 512;  // threads per tile workgroup of the gather
 
 template <typename S, typename T, int MODE, int NF>
 __global__ __launch_bounds__(kGatherThreads) void k_gather_tiles(GatherP<S, T> a) {
-  constexpr int P = 1024 / kGatherThreads;     // particles per thread per chunk
+  // particles per thread per chunk: one for the adjoint kick, whose register
+  // use would otherwise hold the CU to two workgroups
+  constexpr int P = (MODE == GATHER_KICK_ADJ ? 512 : 1024) / kGatherThreads;
   constexpr unsigned CHUNK = P * kGatherThreads;
   constexpr unsigned NONE = 0xffffffffu;
   constexpr bool KICKF = MODE == GATHER_KICK_FWD, KICKA = MODE == GATHER_KICK_ADJ;
