@@ -138,12 +138,14 @@ cplx<T>* spec_ptr(Plan* p, int i) { return static_cast<cplx<T>*>(p->spec[i]); }
 // coefficient of the fused Poisson multiplier: coef * N_c / N_p (delta = rho N_c/N_p - 1)
 double mass_coef(const Plan* p, double coef) { return coef * double(p->ncell) / double(p->nptcl); }
 
+// Both follow a paint made with defer_z: the R2C adds the paint's z faces.
 template <typename T>
 int force_fields(Plan* p, double coef, hipStream_t st) {
   // mesh0 holds the painted mass; leaves g_0..2 in mesh0..2
   T* reals[3] = {mesh_ptr<T>(p, 0), mesh_ptr<T>(p, 1), mesh_ptr<T>(p, 2)};
   cplx<T>* specs[3] = {spec_ptr<T>(p, 0), spec_ptr<T>(p, 1), spec_ptr<T>(p, 2)};
-  return fft_spectral_op<T>(p, mesh_shape(p), SPEC_GRAD3, reals, specs, T(mass_coef(p, coef)), st);
+  const ZFold zf = paint_zfold(p);
+  return fft_spectral_op<T>(p, mesh_shape(p), SPEC_GRAD3, reals, specs, T(mass_coef(p, coef)), &zf, st);
 }
 
 template <typename T>
@@ -151,13 +153,19 @@ int vjp_fields(Plan* p, double coef, hipStream_t st) {
   // mesh0..3 hold [rho, gbar_x, gbar_y, gbar_z]; leaves [g_x, g_y, g_z, rhobar]
   T* reals[4] = {mesh_ptr<T>(p, 0), mesh_ptr<T>(p, 1), mesh_ptr<T>(p, 2), mesh_ptr<T>(p, 3)};
   cplx<T>* specs[4] = {spec_ptr<T>(p, 0), spec_ptr<T>(p, 1), spec_ptr<T>(p, 2), spec_ptr<T>(p, 3)};
-  return fft_spectral_op<T>(p, mesh_shape(p), SPEC_ADJ4, reals, specs, T(mass_coef(p, coef)), st);
+  const ZFold zf = paint_zfold(p);
+  return fft_spectral_op<T>(p, mesh_shape(p), SPEC_ADJ4, reals, specs, T(mass_coef(p, coef)), &zf, st);
 }
 
-int force_fields_any(Plan* p, double coef, hipStream_t st) {
+// paint (with the z faces deferred) and the force or VJP fields
+int paint_force_fields(Plan* p, DriftMode mode, PaintArgs pa, double coef, hipStream_t st) {
+  pa.defer_z = true;
+  if (int rc = paint_launch(p, mode, pa, st)) return rc;
   return p->cfg.mesh_dtype == PM_F64 ? force_fields<double>(p, coef, st) : force_fields<float>(p, coef, st);
 }
-int vjp_fields_any(Plan* p, double coef, hipStream_t st) {
+int paint_vjp_fields(Plan* p, DriftMode mode, PaintArgs pa, double coef, hipStream_t st) {
+  pa.defer_z = true;
+  if (int rc = paint_launch(p, mode, pa, st)) return rc;
   return p->cfg.mesh_dtype == PM_F64 ? vjp_fields<double>(p, coef, st) : vjp_fields<float>(p, coef, st);
 }
 
@@ -206,8 +214,7 @@ int step_adj(Plan* p, pm_state* stt, pm_adj* adj, const pm_step_coef* cur, const
   pa.D = cur->D;
   pa.partials = p->partials;
   pa.s_set = s_set;
-  if (int rc = paint_launch(p, s_set ? DRIFT_SET : DRIFT_ADJ, pa, st)) return rc;
-  if (int rc = vjp_fields_any(p, coef, st)) return rc;
+  if (int rc = paint_vjp_fields(p, s_set ? DRIFT_SET : DRIFT_ADJ, pa, coef, st)) return rc;
   const double K = cur->Ka + (prev ? prev->Kb : 0.0);
   const double dK = cur->dKa + (prev ? prev->dKb : 0.0);
   GatherArgs ga{};
@@ -490,8 +497,7 @@ int pm_force(pm_plan h, const void* disp, double coef, void* acc, hipStream_t st
   pa.s = disp;
   pa.unit = 1;
   pa.mesh = p->mesh[0];
-  if (int rc = paint_launch(p, DRIFT_NONE, pa, st)) return rc;
-  if (int rc = force_fields_any(p, coef, st)) return rc;
+  if (int rc = paint_force_fields(p, DRIFT_NONE, pa, coef, st)) return rc;
   GatherArgs ga{};
   ga.s = disp;
   ga.mesh = p->mesh[0];
@@ -516,8 +522,7 @@ int pm_force_vjp(pm_plan h, const void* disp, const void* acc_bar, double coef, 
   pa.w = acc_bar;
   pa.nw = 3;
   pa.mesh = p->mesh[0];
-  if (int rc = paint_launch(p, DRIFT_NONE, pa, st)) return rc;
-  if (int rc = vjp_fields_any(p, coef, st)) return rc;
+  if (int rc = paint_vjp_fields(p, DRIFT_NONE, pa, coef, st)) return rc;
   GatherArgs ga{};
   ga.s = disp;
   ga.mesh = p->mesh[0];
@@ -543,8 +548,7 @@ int pm_fwd_init(pm_plan h, pm_state* stt, const pm_step_coef* first, double coef
   pa.s = stt->s;
   pa.unit = 1;
   pa.mesh = p->mesh[0];
-  if (int rc = paint_launch(p, DRIFT_NONE, pa, st)) return rc;
-  if (int rc = force_fields_any(p, coef, st)) return rc;
+  if (int rc = paint_force_fields(p, DRIFT_NONE, pa, coef, st)) return rc;
   GatherArgs ga{};
   ga.s = stt->s;
   ga.mesh = p->mesh[0];
@@ -572,8 +576,7 @@ int pm_step_fwd(pm_plan h, pm_state* stt, const pm_step_coef* cur, const pm_step
   pa.unit = 1;
   pa.mesh = p->mesh[0];
   pa.D = cur->D;
-  if (int rc = paint_launch(p, DRIFT_FWD, pa, st)) return rc;
-  if (int rc = force_fields_any(p, coef, st)) return rc;
+  if (int rc = paint_force_fields(p, DRIFT_FWD, pa, coef, st)) return rc;
   GatherArgs ga{};
   ga.s = stt->s;
   ga.mesh = p->mesh[0];
@@ -603,8 +606,7 @@ int pm_adj_init(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* last,
   pa.w = adj->pi;
   pa.nw = 3;
   pa.mesh = p->mesh[0];
-  if (int rc = paint_launch(p, DRIFT_NONE, pa, st)) return rc;
-  if (int rc = vjp_fields_any(p, coef, st)) return rc;
+  if (int rc = paint_vjp_fields(p, DRIFT_NONE, pa, coef, st)) return rc;
   GatherArgs ga{};
   ga.s = stt->s;
   ga.mesh = p->mesh[0];

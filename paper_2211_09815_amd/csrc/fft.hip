@@ -46,7 +46,7 @@ int fft_r2c_3d(Plan* p, const FftShape& s, const T* in, cplx<T>* out, int batch,
                int64_t out_stride, hipStream_t st) {
   const Ptrs4 i4 = strided<T>(in, in_stride, batch);
   const Ptrs4 o4 = strided<cplx<T>>(out, out_stride, batch);
-  int rc = fftk::r2c_z_pass<T>(p, s, i4, o4, batch, st);
+  int rc = fftk::r2c_z_pass<T>(p, s, i4, o4, batch, nullptr, st);
   if (!rc) rc = y_pass<T>(p, s, o4, batch, false, st);
   if (!rc) rc = x_pass<T>(p, s, o4, batch, false, st);
   return rc;
@@ -65,12 +65,12 @@ int fft_c2r_3d(Plan* p, const FftShape& s, cplx<T>* in, T* out, int batch, int64
 
 template <typename T>
 int fft_spectral_op(Plan* p, const FftShape& s, SpecOp op, T* const* reals, cplx<T>* const* specs, T coef,
-                    hipStream_t st) {
+                    const ZFold* zf, hipStream_t st) {
   const int nin = op == SPEC_GRAD3 ? 1 : 4;
   const int nout = op == SPEC_GRAD3 ? 3 : 4;
   const Ptrs4 rin = fftk::ptrs(reals, nin);
   const Ptrs4 spec_in = fftk::ptrs(specs, nin);
-  int rc = fftk::r2c_z_pass<T>(p, s, rin, spec_in, nin, st);
+  int rc = fftk::r2c_z_pass<T>(p, s, rin, spec_in, nin, zf, st);
   if (!rc) rc = y_pass<T>(p, s, spec_in, nin, false, st);
   if (rc) return rc;
   // outputs in place: GRAD3 g_j -> specs[j]; ADJ4 g_0 -> specs[0],
@@ -98,8 +98,8 @@ template int fft_c2r_3d<float>(Plan*, const FftShape&, Cx<float>*, float*, int, 
 template int fft_c2r_3d<double>(Plan*, const FftShape&, Cx<double>*, double*, int, int64_t, int64_t, double,
                                 hipStream_t);
 template int fft_spectral_op<float>(Plan*, const FftShape&, SpecOp, float* const*, Cx<float>* const*, float,
-                                    hipStream_t);
+                                    const ZFold*, hipStream_t);
 template int fft_spectral_op<double>(Plan*, const FftShape&, SpecOp, double* const*, Cx<double>* const*, double,
-                                     hipStream_t);
+                                     const ZFold*, hipStream_t);
 
 }  // namespace pmx

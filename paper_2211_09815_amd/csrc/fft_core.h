@@ -242,7 +242,8 @@ int lines_pass(Plan* p, const Ptrs4& arrs, int batch, bool inv, int M, int64_t l
                int64_t ostride, int64_t nouter, hipStream_t st);
 // z passes between real lines of n2 and half-spectrum lines of n2/2 + 1
 template <typename T>
-int r2c_z_pass(Plan* p, const FftShape& s, const Ptrs4& in, const Ptrs4& out, int batch, hipStream_t st);
+int r2c_z_pass(Plan* p, const FftShape& s, const Ptrs4& in, const Ptrs4& out, int batch, const ZFold* zf,
+               hipStream_t st);
 template <typename T>
 int c2r_z_pass(Plan* p, const FftShape& s, const Ptrs4& in, const Ptrs4& out, int batch, T scale,
                hipStream_t st);

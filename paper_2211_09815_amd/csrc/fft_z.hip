@@ -9,10 +9,11 @@ namespace {
 
 // real -> complex.  z[n] = x[2n] + i x[2n+1];  Z = FFT_M(z);  with
 // Zc = conj(Z[M-k]):  X[k] = (Z + Zc)/2 - i exp(-2 pi i k/N) (Z - Zc)/2,
-// k = 0..M.
-template <typename T, int LOGM>
+// k = 0..M.  FOLD: x[z] += the paint's z-face halo value of the tile below,
+// for every z on a tile boundary (z = 2n is even there).
+template <typename T, int LOGM, bool FOLD>
 __global__ __launch_bounds__(kFT, 4) void k_fft_r2c_z(Ptrs4 ins, Ptrs4 outs, int64_t nlines,
-                                                      const cplx<T>* __restrict__ tw) {
+                                                      const cplx<T>* __restrict__ tw, ZFold zf) {
   using C = cplx<T>;
   using R = T;
   constexpr int EPT = Cfg<T>::EPT;
@@ -34,6 +35,33 @@ __global__ __launch_bounds__(kFT, 4) void k_fft_r2c_z(Ptrs4 ins, Ptrs4 outs, int
     for (int i = 0; i < EPT; ++i) {
       const int f = tid + i * kFT;
       v[i] = ((f >> LOGM) < lines_here) ? src[f] : cmk<C>(0, 0);
+    }
+    if constexpr (FOLD) {
+      // the z faces these lines need, entry t * W + l for line l and tile
+      // boundary z = t tz, staged in LDS after the data with reads that run
+      // along y (the fastest index of a face)
+      T* zb = reinterpret_cast<T*>(lds + M * PITCH);
+      const T* halo = static_cast<const T*>(zf.halo) + int64_t(blockIdx.y) * zf.ntiles * zf.hc;
+      const int nt = (2 * M) >> zf.ltz;
+      for (int j = tid; j < nt * W; j += kFT) {
+        const int l = j & (W - 1), t = j >> LOGW;
+        T h = T(0);
+        if (l < lines_here) {
+          const int64_t line = l0 + l;
+          const int x = int(line >> zf.ln1), y = int(line & ((int64_t(1) << zf.ln1) - 1));
+          const int tb = (t - 1) & (zf.ntz - 1);
+          const int64_t below = (int64_t(x >> zf.ltx) * zf.nty + (y >> zf.lty)) * zf.ntz + tb;
+          h = halo[below * zf.hc + zf.face + ((x & ((1 << zf.ltx) - 1)) << zf.lty) + (y & ((1 << zf.lty) - 1))];
+        }
+        zb[j] = h;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int f = tid + i * kFT;
+        const int z = 2 * (f & (M - 1));
+        if ((z & ((1 << zf.ltz) - 1)) == 0) v[i].x += zb[((z >> zf.ltz) << LOGW) + (f >> LOGM)];
+      }
     }
     load_twiddles<LOGL>(tws, tw);
 #pragma unroll
@@ -127,7 +155,8 @@ int64_t z_tiles(const FftShape& s, int logM) {
 }  // namespace
 
 template <typename T>
-int r2c_z_pass(Plan* p, const FftShape& s, const Ptrs4& in, const Ptrs4& out, int batch, hipStream_t st) {
+int r2c_z_pass(Plan* p, const FftShape& s, const Ptrs4& in, const Ptrs4& out, int batch, const ZFold* zf,
+               hipStream_t st) {
   const int nh = s.n2 / 2 + 1;
   const int logM = ilog2(s.n2 / 2);
   const int64_t nlines = int64_t(s.n0) * s.n1;
@@ -135,15 +164,27 @@ int r2c_z_pass(Plan* p, const FftShape& s, const Ptrs4& in, const Ptrs4& out, in
   const size_t lds = lds_bytes<T>(logM, logM + 1);
   const cplx<T>* tw = static_cast<const cplx<T>*>(p->tw);
   if (logM < 1 || logM > 9) return set_error(p, PM_EUNSUPPORTED, "FFT length %d is not supported", s.n2);
+  const bool fold = zf && zf->halo;
+  const ZFold zfv = fold ? *zf : ZFold{};
+  // the fold stages one value per line and tile boundary after the data
+  const size_t lds_fold = fold ? lds + (size_t(1) << (tile_log2<T>() - logM)) * (s.n2 >> zfv.ltz) * sizeof(T) : lds;
   timing_begin(p, PM_K_FFT_R2C_Z, st);
   (void)with_log2<1, 9>(logM, [&](auto L) {
     constexpr int LOGM = decltype(L)::value;
-    allow_lds(p, k_fft_r2c_z<T, LOGM>, lds);
-    hipLaunchKernelGGL((k_fft_r2c_z<T, LOGM>), grid, dim3(kFT), lds, st, in, out, nlines, tw);
+    if (fold) {
+      allow_lds(p, k_fft_r2c_z<T, LOGM, true>, lds_fold);
+      hipLaunchKernelGGL((k_fft_r2c_z<T, LOGM, true>), grid, dim3(kFT), lds_fold, st, in, out, nlines, tw, zfv);
+    } else {
+      allow_lds(p, k_fft_r2c_z<T, LOGM, false>, lds);
+      hipLaunchKernelGGL((k_fft_r2c_z<T, LOGM, false>), grid, dim3(kFT), lds, st, in, out, nlines, tw, zfv);
+    }
     return PM_OK;
   });
+  // lines read and half spectra written (+ one halo value per tile boundary)
+  const double fold_bytes = fold ? double(s.n2 >> zf->ltz) * sizeof(T) : 0.0;
   timing_end(p, PM_K_FFT_R2C_Z, st,
-             double(batch) * double(nlines) * (double(s.n2) * sizeof(T) + double(nh) * sizeof(cplx<T>)));
+             double(batch) * double(nlines) *
+                 (double(s.n2) * sizeof(T) + double(nh) * sizeof(cplx<T>) + fold_bytes));
   PM_HIP_CHECK(p, hipGetLastError());
   return PM_OK;
 }
@@ -170,8 +211,8 @@ int c2r_z_pass(Plan* p, const FftShape& s, const Ptrs4& in, const Ptrs4& out, in
   return PM_OK;
 }
 
-template int r2c_z_pass<float>(Plan*, const FftShape&, const Ptrs4&, const Ptrs4&, int, hipStream_t);
-template int r2c_z_pass<double>(Plan*, const FftShape&, const Ptrs4&, const Ptrs4&, int, hipStream_t);
+template int r2c_z_pass<float>(Plan*, const FftShape&, const Ptrs4&, const Ptrs4&, int, const ZFold*, hipStream_t);
+template int r2c_z_pass<double>(Plan*, const FftShape&, const Ptrs4&, const Ptrs4&, int, const ZFold*, hipStream_t);
 template int c2r_z_pass<float>(Plan*, const FftShape&, const Ptrs4&, const Ptrs4&, int, float, hipStream_t);
 template int c2r_z_pass<double>(Plan*, const FftShape&, const Ptrs4&, const Ptrs4&, int, double, hipStream_t);
 

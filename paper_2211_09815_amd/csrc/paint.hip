@@ -409,8 +409,10 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
 }
 
 // core cells on the lower faces of each tile gather the halo faces of the
-// lower neighbours d in {0,1}^3 \ {0} (wrapped), for every channel
-template <typename T, int NCH>
+// lower neighbours d in {0,1}^3 \ {0} (wrapped), for every channel.  DEFER:
+// the z face of the tile below (d = (0,0,1), the only contribution to the
+// bottom-plane cells off the x and y faces) is left to the next R2C
+template <typename T, int NCH, bool DEFER>
 __global__ __launch_bounds__(kThreads) void k_halo_add(TileGeo g, T* __restrict__ mesh, const T* __restrict__ halo) {
   const int64_t tile = xcd_tile(blockIdx.x, int64_t(gridDim.x));
   const int t2 = int(tile % g.ntz);
@@ -420,7 +422,7 @@ __global__ __launch_bounds__(kThreads) void k_halo_add(TileGeo g, T* __restrict_
   const int ez = g.tz + 1, ey = g.ty + 1;
   const int fx = ey * ez, fy = g.tx * ez;
   const int nA = g.ty * g.tz, nB = (g.tx - 1) * g.tz, nC = (g.tx - 1) * (g.ty - 1);
-  const int nb = nA + nB + nC;
+  const int nb = nA + nB + (DEFER ? 0 : nC);
   for (int i = threadIdx.x; i < nb; i += kThreads) {
     int lx, ly, lz;
     if (i < nA) { lx = 0; ly = i / g.tz; lz = i % g.tz; }
@@ -433,6 +435,7 @@ __global__ __launch_bounds__(kThreads) void k_halo_add(TileGeo g, T* __restrict_
     for (int d = 1; d < 8; ++d) {
       const int dx = d >> 2, dy = (d >> 1) & 1, dz = d & 1;
       if ((dx && lx) || (dy && ly) || (dz && lz)) continue;
+      if (DEFER && d == 1) continue;
       const int u0 = (t0 - dx + g.ntx) % g.ntx, u1 = (t1 - dy + g.nty) % g.nty, u2 = (t2 - dz + g.ntz) % g.ntz;
       const int64_t u = (int64_t(u0) * g.nty + u1) * g.ntz + u2;
       const int e1 = dy ? g.ty : ly, e2 = dz ? g.tz : lz;
@@ -512,9 +515,12 @@ int paint_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
   const double halo_bytes = double(nch) * double(nt) * g.hc * mb;
   // tiles: list + s + weights read, core and halo faces written
   const double tile_bytes = 4 * N + 3 * N * sb + double(nch - in.unit) * N * mb + core_bytes + halo_bytes;
-  // halo: halo faces read, the lower-face core cells read and written
-  const double lower = double(g.ty * g.tz + (g.tx - 1) * g.tz + (g.tx - 1) * (g.ty - 1)) / (g.tx * g.ty * g.tz);
-  const double hadd_bytes = halo_bytes + 2.0 * lower * core_bytes;
+  // halo: halo faces read (but the z faces when deferred), the lower-face
+  // core cells read and written
+  const int zc = g.tx * g.ty;
+  const int nlow = g.ty * g.tz + (g.tx - 1) * g.tz + (in.defer_z ? 0 : (g.tx - 1) * (g.ty - 1));
+  const double lower = double(nlow) / (g.tx * g.ty * g.tz);
+  const double hadd_bytes = halo_bytes * (in.defer_z ? double(g.hc - zc) / g.hc : 1.0) + 2.0 * lower * core_bytes;
 #define PM_TILES(NCH, UNIT)                                                                                \
   timing_begin(p, PM_K_PAINT_TILES, st);                                                                   \
   hipLaunchKernelGGL((k_paint_tiles<S, T, NCH, UNIT>), tg, dim3(kPaintThreads), 0, st, g, s, w, p->bin_offs,    \
@@ -522,7 +528,8 @@ int paint_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
                      mesh, halo);                                                                          \
   timing_end(p, PM_K_PAINT_TILES, st, tile_bytes);                                                         \
   timing_begin(p, PM_K_HALO, st);                                                                          \
-  hipLaunchKernelGGL((k_halo_add<T, NCH>), tg, block, 0, st, g, mesh, halo);                               \
+  if (in.defer_z) hipLaunchKernelGGL((k_halo_add<T, NCH, true>), tg, block, 0, st, g, mesh, halo);         \
+  else hipLaunchKernelGGL((k_halo_add<T, NCH, false>), tg, block, 0, st, g, mesh, halo);                   \
   timing_end(p, PM_K_HALO, st, hadd_bytes)
   if (in.unit) {
     switch (nch) {
@@ -559,6 +566,22 @@ int paint_launch(Plan* p, DriftMode mode, const PaintArgs& a, hipStream_t st) {
   if (m64) return paint_typed<double, double>(p, mode, a, st);
   if (s64) return paint_typed<double, float>(p, mode, a, st);
   return paint_typed<float, float>(p, mode, a, st);
+}
+
+ZFold paint_zfold(const Plan* p) {
+  const TileGeo g = tile_geo(p);
+  ZFold z{};
+  z.halo = p->bin_halo;
+  z.ntiles = g.ntiles;
+  z.hc = g.hc;
+  z.face = (g.ty + 1) * (g.tz + 1) + g.tx * (g.tz + 1);   // after the x and y faces
+  z.ln1 = ilog2(g.n1);
+  z.ltx = g.ltx;
+  z.lty = g.lty;
+  z.ltz = g.ltz;
+  z.nty = g.nty;
+  z.ntz = g.ntz;
+  return z;
 }
 
 void tile_dims(const int n[3], int tile[3], int64_t& ntiles, int& halo_cells) {

@@ -143,6 +143,20 @@ enum SpecOp {
   SPEC_ADJ4 = 2,      // out_0..2 = T_j * in0, out_3 = -sum_j T_j in_{1+j}
 };
 
+// The z faces of the tiled paint's halo (the cells above a tile's top plane,
+// which belong to the bottom plane of the tile above) can be left out of the
+// halo fold and added instead by the first z pass of the R2C that reads the
+// painted mesh: there every such cell is one value of a line already in
+// registers, while the fold would read and write a whole cache line for it.
+struct ZFold {
+  const void* halo;     // [nch][ntiles][hc] mesh dtype (channel = batch index); null: no fold
+  int64_t ntiles;
+  int hc, face;         // halo cells per tile; index of the z face within them
+  int ln1;              // log2 of the mesh's y size
+  int ltx, lty, ltz;    // log2 of the tile dims
+  int nty, ntz;         // tiles along y and z
+};
+
 template <typename T>
 int fft_r2c_3d(Plan* p, const FftShape& s, const T* in, cplx<T>* out, int batch,
                int64_t in_stride, int64_t out_stride, hipStream_t st);
@@ -153,10 +167,11 @@ int fft_c2r_3d(Plan* p, const FftShape& s, cplx<T>* in, T* out, int batch,
 // real fields -> spectral multipliers -> real fields, in place:
 //   GRAD3: reals[0] -> reals[0..2] = g_0..2;
 //   ADJ4:  reals[0..3] = [rho, gbar_0..2] -> [g_0..2, rhobar].
-// specs[0..3] are half-spectrum scratch buffers (clobbered).
+// specs[0..3] are half-spectrum scratch buffers (clobbered).  zf (may be
+// null): z faces of the paint that produced reals, still to be added.
 template <typename T>
 int fft_spectral_op(Plan* p, const FftShape& s, SpecOp op, T* const* reals, cplx<T>* const* specs,
-                    T coef, hipStream_t st);
+                    T coef, const ZFold* zf, hipStream_t st);
 // elementwise spectral multiplies used by the standalone Poisson call
 template <typename T>
 int poisson_grad_spec(Plan* p, const FftShape& s, const cplx<T>* in, cplx<T>* out, T coef,
@@ -182,12 +197,15 @@ struct PaintArgs {
   double D;             // drift coefficient
   double* partials;     // per-block partial sum of xi.p (adjoint drift)
   const void* s_set;    // DRIFT_SET: [3][N] state dtype, positions to land on
+  bool defer_z;         // leave the z faces of the halo to the next R2C (paint_zfold)
 };
 int paint_launch(Plan* p, DriftMode mode, const PaintArgs& a, hipStream_t st);
 // tile binning only (drift + bins + per-tile lists), as done by paint_launch
 int bin_launch(Plan* p, DriftMode mode, const PaintArgs& a, hipStream_t st);
 // tile shape of the binned paint for a mesh
 void tile_dims(const int n[3], int tile[3], int64_t& ntiles, int& halo_cells);
+// the z faces a paint with defer_z left in the plan's halo buffer
+ZFold paint_zfold(const Plan* p);
 
 enum GatherMode {
   GATHER_PLAIN = 0,     // out[c] = readout(mesh[c])
