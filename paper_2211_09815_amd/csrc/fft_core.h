@@ -225,6 +225,123 @@ __device__ __forceinline__ void fft_lds(C* buf, const C* tws) {
   fft_stages<EPT, INV, LOGM, LOGW, LOGL, 0>(buf, tws);
 }
 
+// ---------------------------------------------------------------------------
+// Transforms whose first stage starts from registers and whose last stage
+// ends in registers.  With S stages, stage s of radix 2^bits(s) (larger
+// radices first; REV reverses the order) takes thread t's butterflies
+// b < EPT / R at g = t + b kFT: column c = g mod W, butterfly j = g / W, rows
+// j + r M/R (r < R) in and, for the last stage, rows j + r M/R out (output
+// index = frequency).  So a load into the first stage's registers and a store
+// from the last stage's are row runs of W adjacent columns, and the last
+// stage of a transform hands its registers straight to the first stage of a
+// transform whose first radix equals that last radix (REV).  Only the S - 1
+// exchanges between stages go through LDS.
+// ---------------------------------------------------------------------------
+template <int LOGM, int LRMAX, bool REV>
+struct RegPlan {
+  static constexpr int S = (LOGM + LRMAX - 1) / LRMAX;
+  static constexpr int fwd_bits(int s) {
+    int done = 0;
+    for (int i = 0;; ++i) {
+      const int left = S - i;
+      const int b = (LOGM - done + left - 1) / left;
+      if (i == s) return b;
+      done += b;
+    }
+  }
+  static constexpr int bits(int s) { return REV ? fwd_bits(S - 1 - s) : fwd_bits(s); }
+  static constexpr int ns_log2(int s) {   // log2 of the sub-transform length entering stage s
+    int n = 0;
+    for (int i = 0; i < s; ++i) n += bits(i);
+    return n;
+  }
+};
+
+template <typename C, int EPT, int LOGM, int LRMAX, bool REV, bool LAST>
+struct RegStage {
+  using P = RegPlan<LOGM, LRMAX, REV>;
+  static constexpr int LR = P::bits(LAST ? P::S - 1 : 0);
+  static constexpr int R = 1 << LR;
+  static constexpr int B = EPT / R;
+};
+
+// rows of the thread's registers for the first (or last) stage: v[b][r] is
+// element (row_of(b, r), col_of(b)) of the tile
+template <int LR, int LOGM, int LOGW>
+__device__ __forceinline__ int reg_col(int tid, int b) {
+  return (tid + b * kFT) & ((1 << LOGW) - 1);
+}
+template <int LR, int LOGM, int LOGW>
+__device__ __forceinline__ int reg_row(int tid, int b, int r) {
+  return ((tid + b * kFT) >> LOGW) + (r << (LOGM - LR));
+}
+
+// first stage from registers: DFT of each butterfly, results to LDS in the
+// Stockham order of the next stage (the caller makes sure no thread still
+// reads buf).  Ends with a barrier.  With a single stage nothing is written.
+template <int EPT, bool INV, int LOGM, int LOGW, int LRMAX, bool REV, typename C, int B, int R>
+__device__ __forceinline__ void reg_first_stage(C (&v)[B][R], C* buf) {
+  using P = RegPlan<LOGM, LRMAX, REV>;
+  constexpr int LR = P::bits(0);
+  static_assert((1 << LR) == R && B * R == EPT, "register shape");
+  constexpr int PITCH = (1 << LOGW) + 1;
+#pragma unroll
+  for (int b = 0; b < B; ++b) dft<R, INV>(v[b]);
+  if constexpr (P::S > 1) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int g = tid + b * kFT;
+      const int c = g & ((1 << LOGW) - 1), j = g >> LOGW;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[((j << LR) + r) * PITCH + c] = v[b][r];
+    }
+    __syncthreads();
+  }
+}
+
+// stages 1 .. S-2 through LDS (each ends with a barrier)
+template <int EPT, bool INV, int LOGM, int LOGW, int LOGL, int LRMAX, bool REV, int s, typename C>
+__device__ __forceinline__ void reg_middle_stages(C* buf, const C* tws) {
+  using P = RegPlan<LOGM, LRMAX, REV>;
+  if constexpr (s < P::S - 1) {
+    fft_stage<P::bits(s), EPT, INV, LOGM, LOGW, P::ns_log2(s), LOGL>(buf, tws);
+    reg_middle_stages<EPT, INV, LOGM, LOGW, LOGL, LRMAX, REV, s + 1>(buf, tws);
+  }
+}
+
+// last stage into registers: v[b][r] = output row reg_row(b, r) of column
+// reg_col(b).  Reads buf (no barrier at the end: the caller adds one before
+// buf is written again).  With a single stage v already holds the result.
+template <int EPT, bool INV, int LOGM, int LOGW, int LOGL, int LRMAX, bool REV, typename C, int B, int R>
+__device__ __forceinline__ void reg_last_stage(const C* buf, const C* tws, C (&v)[B][R]) {
+  using P = RegPlan<LOGM, LRMAX, REV>;
+  if constexpr (P::S > 1) {
+    constexpr int LR = P::bits(P::S - 1);
+    static_assert((1 << LR) == R && B * R == EPT, "register shape");
+    constexpr int PITCH = (1 << LOGW) + 1;
+    constexpr int NBF = (1 << LOGM) >> LR;           // = the sub-transform length Ns here
+    constexpr int TWSH = LOGL - LOGM;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int g = tid + b * kFT;
+      const int c = g & ((1 << LOGW) - 1), j = g >> LOGW;
+      const C* src = buf + j * PITCH + c;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = src[r * NBF * PITCH];
+      const int kt = j << TWSH;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        C w = tws[kt * r];
+        if (INV) w.y = -w.y;
+        v[b][r] = cmul(v[b][r], w);
+      }
+      dft<R, INV>(v[b]);
+    }
+  }
+}
+
 // copy exp(-2 pi i m / 2^LOGL), m < 2^LOGL, from the 4096-entry table to LDS
 template <int LOGL, typename C>
 __device__ __forceinline__ void load_twiddles(C* tws, const C* __restrict__ tw) {

@@ -51,10 +51,19 @@ __global__ __launch_bounds__(kFT, 4) void k_fft_x_fused(Ptrs4 ins, Ptrs4 outs, i
                                                         const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
   constexpr int EPT = Cfg<T>::EPT;
+  constexpr int LRMAX = EPT >= 16 ? 4 : 3;
   constexpr int M = 1 << LOGM;  // = n0
   constexpr int LOGW = tile_log2<T>() - LOGM;
   constexpr int W = 1 << LOGW;
-  constexpr int PITCH = W + 1;
+  constexpr int S = RegPlan<LOGM, LRMAX, false>::S;
+  // forward stages larger radix first, inverse stages in the reverse order,
+  // so the forward's last stage and the inverse's first share one register
+  // layout: the multipliers are applied in registers between them
+  using FF = RegStage<C, EPT, LOGM, LRMAX, false, false>;
+  using FL = RegStage<C, EPT, LOGM, LRMAX, false, true>;
+  using IF = RegStage<C, EPT, LOGM, LRMAX, true, false>;
+  using IL = RegStage<C, EPT, LOGM, LRMAX, true, true>;
+  static_assert(FL::LR == IF::LR, "forward last and inverse first radix");
   // when W <= kFT all elements of a thread lie in one column
   constexpr bool ONE_COL = W <= kFT;
   C* tws = reinterpret_cast<C*>(fft_smem);
@@ -63,114 +72,201 @@ __global__ __launch_bounds__(kFT, 4) void k_fft_x_fused(Ptrs4 ins, Ptrs4 outs, i
   const int64_t ls = ncols;
   const int64_t c0 = xcd_tile(blockIdx.x, int64_t(gridDim.x)) << LOGW;
   const T two_pi = T(6.283185307179586476925286766559);
-  const KCol<T> k0 = kcol<T>(c0 + (int(threadIdx.x) & (W - 1)), n1, n2, nh);
-  auto kc = [&](int c) { return ONE_COL ? k0 : kcol<T>(c0 + c, n1, n2, nh); };
+  const int col0 = int(threadIdx.x) & (W - 1);
+  const KCol<T> kk0 = kcol<T>(c0 + col0, n1, n2, nh);
+  auto colof = [&](int tid, int b) { return ONE_COL ? col0 : (tid + b * kFT) & (W - 1); };
+  auto kkof = [&](int tid, int b) { return ONE_COL ? kk0 : kcol<T>(c0 + colof(tid, b), n1, n2, nh); };
+  // kx and its Nyquist flag of output row reg_row(b, r) of the forward's last stage
   auto kxj = [&](int j, T& kx, bool& nx) {
     const int fx = j < (M >> 1) ? j : j - M;
     kx = two_pi * T(fx) / T(M);
     nx = (2 * j == M);
   };
-  auto load_forward = [&](const void* src_v) {
+  // ky, kz (zero on their Nyquist planes) of butterfly b's column
+  auto kyz = [&](int tid, int b, T& ky, T& kz) {
+    const KCol<T> kk = kkof(tid, b);
+    ky = kk.ny ? T(0) : kk.ky;
+    kz = kk.nz ? T(0) : kk.kz;
+  };
+  // g = coef / k^2 at the forward's last-stage element (b, r), and its kx
+  // (zero on the Nyquist plane)
+  auto gk = [&](int tid, int b, int r, T& g, T& kxn) {
+    const KCol<T> kk = kkof(tid, b);
+    T kx;
+    bool nx;
+    kxj(reg_row<FL::LR, LOGM, LOGW>(tid, b, r), kx, nx);
+    // explicit fused multiply-adds: the force of the Poisson path and of the
+    // VJP path must round identically (exact time reversal), whatever the
+    // compiler would contract in either kernel
+    const T k2 = fma(kx, kx, fma(kk.ky, kk.ky, kk.kz * kk.kz));
+    g = k2 > T(0) ? coef / k2 : T(0);
+    kxn = nx ? T(0) : kx;
+  };
+
+  // forward FFT along x of one input into X (frequency rows)
+  auto forward = [&](const void* src_v, C (&X)[FL::B][FL::R], bool lds_busy) {
     const C* src = static_cast<const C*>(src_v) + c0;
-    // ADJ4 carries EPT accumulators through this phase: load in two halves
-    constexpr int NH = OP == SPEC_ADJ4 ? 2 : 1;
-    constexpr int EH = EPT / NH;
+    const int tid = fresh_tid();
+    C v[FF::B][FF::R];
 #pragma unroll
-    for (int h = 0; h < NH; ++h) {
-      const int tid = fresh_tid();
-      C v[EH];
+    for (int b = 0; b < FF::B; ++b) {
+      const int col = colof(tid, b);
 #pragma unroll
-      for (int i = 0; i < EH; ++i) {
-        const int f = tid + (h * EH + i) * kFT;
-        const int c = f & (W - 1), j = f >> LOGW;
-        v[i] = (c0 + c < ncols) ? src[int64_t(j) * ls + c] : cmk<C>(0, 0);
-      }
-      if (h == 0) __syncthreads();  // earlier readers of lds are done
+      for (int r = 0; r < FF::R; ++r)
+        v[b][r] = c0 + col < ncols ? src[int64_t(reg_row<FF::LR, LOGM, LOGW>(tid, b, r)) * ls + col] : cmk<C>(0, 0);
+    }
+    if (lds_busy) __syncthreads();   // earlier readers of lds are done
+    reg_first_stage<EPT, false, LOGM, LOGW, LRMAX, false>(v, lds);
+    if constexpr (S == 1) {
 #pragma unroll
-      for (int i = 0; i < EH; ++i) {
-        const int f = tid + (h * EH + i) * kFT;
-        lds[(f >> LOGW) * PITCH + (f & (W - 1))] = v[i];
+      for (int b = 0; b < FL::B; ++b)
+#pragma unroll
+        for (int r = 0; r < FL::R; ++r) X[b][r] = v[b][r];
+    } else {
+      reg_middle_stages<EPT, false, LOGM, LOGW, LOGM, LRMAX, false, 1>(lds, tws);
+      reg_last_stage<EPT, false, LOGM, LOGW, LOGM, LRMAX, false>(lds, tws, X);
+    }
+  };
+  // inverse FFT along x of Y (frequency rows, the forward's last layout);
+  // stores it to dst_a, or with yz set, ky times it to dst_a and kz times it
+  // to dst_b
+  auto store_rows = [&](int tid, const auto& u, int lr, void* dst_a, void* dst_b, auto yz) {
+    constexpr int NB = sizeof(u) / sizeof(u[0]);
+    constexpr int NR = sizeof(u[0]) / sizeof(C);
+    C* da = static_cast<C*>(dst_a) + c0;
+    C* db = static_cast<C*>(dst_b) + c0;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int col = colof(tid, b);
+      if (c0 + col >= ncols) continue;
+      T ky = T(1), kz = T(1);
+      if constexpr (!std::is_same_v<decltype(yz), std::nullptr_t>) yz(tid, b, ky, kz);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int64_t at = int64_t(((tid + b * kFT) >> LOGW) + (r << (LOGM - lr))) * ls + col;
+        if constexpr (std::is_same_v<decltype(yz), std::nullptr_t>) {
+          da[at] = u[b][r];
+        } else {
+          da[at] = cmk<C>(ky * u[b][r].x, ky * u[b][r].y);
+          db[at] = cmk<C>(kz * u[b][r].x, kz * u[b][r].y);
+        }
       }
     }
-    fft_lds<EPT, false, LOGM, LOGW, LOGM>(lds, tws);
   };
-  auto inverse_store = [&](void* dst_v) {
-    fft_lds<EPT, true, LOGM, LOGW, LOGM>(lds, tws);
-    C* dst = static_cast<C*>(dst_v) + c0;
+  auto inverse_store = [&](C (&Y)[IF::B][IF::R], void* dst_a, void* dst_b, auto yz) {
+    __syncthreads();   // earlier readers of lds are done
+    reg_first_stage<EPT, true, LOGM, LOGW, LRMAX, true>(Y, lds);
     const int tid = fresh_tid();
+    if constexpr (S == 1) {
+      store_rows(tid, Y, IF::LR, dst_a, dst_b, yz);
+    } else {
+      reg_middle_stages<EPT, true, LOGM, LOGW, LOGM, LRMAX, true, 1>(lds, tws);
+      C u[IL::B][IL::R];
+      reg_last_stage<EPT, true, LOGM, LOGW, LOGM, LRMAX, true>(lds, tws, u);
+      store_rows(tid, u, IL::LR, dst_a, dst_b, yz);
+    }
+  };
+  // forward FFT along x of ky in_a + kz in_b (ky, kz of each column)
+  auto forward_yz = [&](const void* src_a, const void* src_b, C (&X)[FL::B][FL::R]) {
+    const C* sa = static_cast<const C*>(src_a) + c0;
+    const C* sb = static_cast<const C*>(src_b) + c0;
+    const int tid = fresh_tid();
+    C v[FF::B][FF::R];
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int f = tid + i * kFT;
-      const int c = f & (W - 1), j = f >> LOGW;
-      if (c0 + c < ncols) dst[int64_t(j) * ls + c] = lds[j * PITCH + c];
+    for (int b = 0; b < FF::B; ++b) {
+      const int col = colof(tid, b);
+      T ky, kz;
+      kyz(tid, b, ky, kz);
+#pragma unroll
+      for (int r = 0; r < FF::R; ++r) {
+        const int64_t at = int64_t(reg_row<FF::LR, LOGM, LOGW>(tid, b, r)) * ls + col;
+        v[b][r] = cmk<C>(0, 0);
+        if (c0 + col < ncols) {
+          const C a = sa[at], e = sb[at];
+          v[b][r] = cmk<C>(ky * a.x + kz * e.x, ky * a.y + kz * e.y);
+        }
+      }
+    }
+    __syncthreads();   // earlier readers of lds are done
+    reg_first_stage<EPT, false, LOGM, LOGW, LRMAX, false>(v, lds);
+    if constexpr (S == 1) {
+#pragma unroll
+      for (int b = 0; b < FL::B; ++b)
+#pragma unroll
+        for (int r = 0; r < FL::R; ++r) X[b][r] = v[b][r];
+    } else {
+      reg_middle_stages<EPT, false, LOGM, LOGW, LOGM, LRMAX, false, 1>(lds, tws);
+      reg_last_stage<EPT, false, LOGM, LOGW, LOGM, LRMAX, false>(lds, tws, X);
     }
   };
 
   load_twiddles<LOGM>(tws, tw);
+  bool lds_busy = false;
   if constexpr (OP == SPEC_ADJ4) {
-    C acc[EPT];
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) acc[i] = cmk<C>(0, 0);
-#pragma unroll 1
-    for (int q = 0; q < 3; ++q) {
-      load_forward(ins.p[1 + q]);
+    // s = kx in_1 + ky in_2 + kz in_3: ky and kz are constant along x, so
+    // in_2 and in_3 are combined before their one forward transform
+    C acc[FL::B][FL::R];
+    forward(ins.p[1], acc, false);
+    lds_busy = true;
+    {
       const int tid = fresh_tid();
 #pragma unroll
-      for (int i = 0; i < EPT; ++i) {
-        const int f = tid + i * kFT;
-        const int c = f & (W - 1), j = f >> LOGW;
-        const KCol<T> kk = kc(c);
-        T kx;
-        bool nx;
-        kxj(j, kx, nx);
-        const T kq = q == 0 ? (nx ? T(0) : kx) : q == 1 ? (kk.ny ? T(0) : kk.ky) : (kk.nz ? T(0) : kk.kz);
-        const C x = lds[j * PITCH + c];
-        acc[i] = cmk<C>(acc[i].x + kq * x.x, acc[i].y + kq * x.y);
+      for (int b = 0; b < FL::B; ++b)
+#pragma unroll
+        for (int r = 0; r < FL::R; ++r) {
+          T g, kxn;
+          gk(tid, b, r, g, kxn);
+          acc[b][r] = cmk<C>(kxn * acc[b][r].x, kxn * acc[b][r].y);
+        }
+    }
+    {
+      C X[FL::B][FL::R];
+      forward_yz(ins.p[2], ins.p[3], X);
+#pragma unroll
+      for (int b = 0; b < FL::B; ++b)
+#pragma unroll
+        for (int r = 0; r < FL::R; ++r) acc[b][r] = cadd(acc[b][r], X[b][r]);
+    }
+    const int tid = fresh_tid();
+#pragma unroll
+    for (int b = 0; b < FL::B; ++b)
+#pragma unroll
+      for (int r = 0; r < FL::R; ++r) {
+        T g, kxn;
+        gk(tid, b, r, g, kxn);
+        // -i g s
+        acc[b][r] = cmk<C>(acc[b][r].y * g, -acc[b][r].x * g);
       }
-    }
-    __syncthreads();
+    inverse_store(acc, outs.p[3], nullptr, nullptr);
+  }
+  // out_0 = IFFT(i g kx X);  out_1, out_2 = ky, kz times IFFT(i g X)
+  C X[FL::B][FL::R];
+  forward(ins.p[0], X, lds_busy);
+  {
+    const int tid = fresh_tid();
+    C Y[IF::B][IF::R];
+#pragma unroll
+    for (int b = 0; b < FL::B; ++b)
+#pragma unroll
+      for (int r = 0; r < FL::R; ++r) {
+        T g, kxn;
+        gk(tid, b, r, g, kxn);
+        g *= kxn;
+        Y[b][r] = cmk<C>(-X[b][r].y * g, X[b][r].x * g);
+      }
+    inverse_store(Y, outs.p[0], nullptr, nullptr);
+  }
+  {
     const int tid = fresh_tid();
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int f = tid + i * kFT;
-      const int c = f & (W - 1), j = f >> LOGW;
-      const KCol<T> kk = kc(c);
-      T kx;
-      bool nx;
-      kxj(j, kx, nx);
-      const T k2 = kx * kx + kk.ky * kk.ky + kk.kz * kk.kz;
-      const T g = k2 > T(0) ? coef / k2 : T(0);
-      // -i g s, s = sum_j k_j in_{1+j}
-      lds[j * PITCH + c] = cmk<C>(acc[i].y * g, -acc[i].x * g);
-    }
-    inverse_store(outs.p[3]);
-  }
-  C reg[EPT];
-  load_forward(ins.p[0]);
+    for (int b = 0; b < FL::B; ++b)
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int f = int(threadIdx.x) + i * kFT;
-    reg[i] = lds[(f >> LOGW) * PITCH + (f & (W - 1))];
-  }
-#pragma unroll 1
-  for (int comp = 0; comp < 3; ++comp) {
-    __syncthreads();
-    const int tid = fresh_tid();
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int f = tid + i * kFT;
-      const int c = f & (W - 1), j = f >> LOGW;
-      const KCol<T> kk = kc(c);
-      T kx;
-      bool nx;
-      kxj(j, kx, nx);
-      const T k2 = kx * kx + kk.ky * kk.ky + kk.kz * kk.kz;
-      const T kj = comp == 0 ? (nx ? T(0) : kx) : comp == 1 ? (kk.ny ? T(0) : kk.ky) : (kk.nz ? T(0) : kk.kz);
-      const T g = k2 > T(0) ? kj * coef / k2 : T(0);
-      // i g in
-      lds[j * PITCH + c] = cmk<C>(-reg[i].y * g, reg[i].x * g);
-    }
-    inverse_store(outs.p[comp]);
+      for (int r = 0; r < FL::R; ++r) {
+        T g, kxn;
+        gk(tid, b, r, g, kxn);
+        X[b][r] = cmk<C>(-X[b][r].y * g, X[b][r].x * g);
+      }
+    inverse_store(X, outs.p[1], outs.p[2], kyz);
   }
 }
 

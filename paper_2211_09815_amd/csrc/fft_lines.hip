@@ -15,12 +15,13 @@ __global__ __launch_bounds__(kFT, 4) void k_fft_lines(Ptrs4 arrs, int64_t ls, in
                                                       const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
   constexpr int EPT = Cfg<T>::EPT;
-  constexpr int M = 1 << LOGM;
+  constexpr int LRMAX = EPT >= 16 ? 4 : 3;
   constexpr int LOGW = tile_log2<T>() - LOGM;
   constexpr int W = 1 << LOGW;
-  constexpr int PITCH = W + 1;
+  using F = RegStage<C, EPT, LOGM, LRMAX, false, false>;
+  using L = RegStage<C, EPT, LOGM, LRMAX, false, true>;
   C* tws = reinterpret_cast<C*>(fft_smem);
-  C* lds = tws + M;
+  C* lds = tws + (1 << LOGM);
   const int64_t ncb = (ncols + W - 1) >> LOGW;
   const int64_t tile = xcd_tile(blockIdx.x, int64_t(gridDim.x));
   const int64_t o = tile / ncb;
@@ -28,27 +29,37 @@ __global__ __launch_bounds__(kFT, 4) void k_fft_lines(Ptrs4 arrs, int64_t ls, in
   C* base = static_cast<C*>(arrs.p[blockIdx.y]) + o * ostride + c0;
   const int tid = threadIdx.x;
   {
-    // all loads in flight before the first LDS store
-    C v[EPT];
+    // the first stage's operands straight from HBM, all loads in flight
+    C v[F::B][F::R];
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int f = tid + i * kFT;
-      const int c = f & (W - 1), j = f >> LOGW;
-      v[i] = (c0 + c < ncols) ? base[j * ls + c] : cmk<C>(0, 0);
+    for (int b = 0; b < F::B; ++b) {
+      const int c = reg_col<F::LR, LOGM, LOGW>(tid, b);
+#pragma unroll
+      for (int r = 0; r < F::R; ++r)
+        v[b][r] = (c0 + c < ncols) ? base[reg_row<F::LR, LOGM, LOGW>(tid, b, r) * ls + c] : cmk<C>(0, 0);
     }
     load_twiddles<LOGM>(tws, tw);
+    reg_first_stage<EPT, INV, LOGM, LOGW, LRMAX, false>(v, lds);
+    if constexpr (RegPlan<LOGM, LRMAX, false>::S == 1) {
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int f = tid + i * kFT;
-      lds[(f >> LOGW) * PITCH + (f & (W - 1))] = v[i];
+      for (int b = 0; b < F::B; ++b) {
+        const int c = reg_col<F::LR, LOGM, LOGW>(tid, b);
+        if (c0 + c < ncols)
+#pragma unroll
+          for (int r = 0; r < F::R; ++r) base[reg_row<F::LR, LOGM, LOGW>(tid, b, r) * ls + c] = v[b][r];
+      }
+      return;
     }
   }
-  fft_lds<EPT, INV, LOGM, LOGW, LOGM>(lds, tws);
+  reg_middle_stages<EPT, INV, LOGM, LOGW, LOGM, LRMAX, false, 1>(lds, tws);
+  C u[L::B][L::R];
+  reg_last_stage<EPT, INV, LOGM, LOGW, LOGM, LRMAX, false>(lds, tws, u);
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int f = tid + i * kFT;
-    const int c = f & (W - 1), j = f >> LOGW;
-    if (c0 + c < ncols) base[j * ls + c] = lds[j * PITCH + c];
+  for (int b = 0; b < L::B; ++b) {
+    const int c = reg_col<L::LR, LOGM, LOGW>(tid, b);
+    if (c0 + c < ncols)
+#pragma unroll
+      for (int r = 0; r < L::R; ++r) base[reg_row<L::LR, LOGM, LOGW>(tid, b, r) * ls + c] = u[b][r];
   }
 }
 

@@ -157,6 +157,22 @@ def test_force_vjp_vs_oracle(mesh, ptcl, scale, mdt):
     assert abs(host(cbar)[0] - cb_ref) < tol * abs(cb_ref)
 
 
+@pytest.mark.parametrize("mesh,ptcl,scale", FORCE_CASES)
+@pytest.mark.parametrize("mdt", [torch.float32, torch.float64])
+def test_force_of_vjp_path_is_bitwise_the_force(mesh, ptcl, scale, mdt):
+    # the reverse-time pass recomputes each step's force through the VJP
+    # path; time reversal is exact only if it equals the forward force bit
+    # for bit
+    announce("force vs VJP-path force mesh=%s ptcl=%s %s" % (mesh, ptcl, mdt))
+    plan = _plan(mesh, ptcl, mdt, torch.float64)
+    r = [mesh[a] / ptcl[a] for a in range(3)]
+    q, s = _particles(ptcl, r, 57, scale)
+    s_dev = dev(soa(s), torch.float64)
+    a = host(plan.force(s_dev, 0.45))
+    _, _, acc = plan.force_vjp(s_dev, dev(inputs.normal((3, len(q)), 58), mdt), 0.45)
+    np.testing.assert_array_equal(host(acc), a)
+
+
 def test_force_vjp_dot_product_identity():
     # <abar, J v> = <J^T abar, v> with J v from central differences of the
     # library's own force (FP64 mode)
