@@ -58,6 +58,8 @@ __global__ __launch_bounds__(kThreads) void k_bin(BinP<S, T> a) {
   chunk_of(g.N, start, end);
   const int lane = threadIdx.x & 63;
   double xp = 0.0;
+  double pm[3] = {0.0, 0.0, 0.0};   // max |pi| after the adjoint drift
+  auto fold = [](double m, double a) { return (a > m || a != a) ? a : m; };
   for (int64_t base = start; base < end; base += U * kThreads) {
     S sv[U][3], pv[U][3];
     T xv[U][3], piv[U][3];
@@ -95,7 +97,9 @@ __global__ __launch_bounds__(kThreads) void k_bin(BinP<S, T> a) {
           xp += double(xv[u][ax]) * double(pv[u][ax]);
           if (MODE == DRIFT_ADJ) sv[u][ax] -= pv[u][ax] * a.D;
           a.s[ax * g.N + n] = sv[u][ax];
-          a.pi[ax * g.N + n] = piv[u][ax] + T(xv[u][ax] * T(a.D));
+          const T pn = piv[u][ax] + T(xv[u][ax] * T(a.D));
+          a.pi[ax * g.N + n] = pn;
+          pm[ax] = fold(pm[ax], fabs(double(pn)));
         }
       }
       double q[3];
@@ -140,6 +144,11 @@ __global__ __launch_bounds__(kThreads) void k_bin(BinP<S, T> a) {
   if (MODE == DRIFT_ADJ || MODE == DRIFT_SET) {
     const double t = block_sum_d(xp);
     if (threadIdx.x == 0) a.partials[blockIdx.x * 4 + 0] = t;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const double m = block_max_d(pm[ax]);
+      if (threadIdx.x == 0) a.partials[blockIdx.x * 4 + 1 + ax] = m;
+    }
   }
 }
 
@@ -220,6 +229,19 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint2* keys, const u
   }
 }
 
+// out[c] = max over blocks of part[b*4 + 1 + c], c < 3 (NaN if any is NaN):
+// the largest |pi| of each channel after the adjoint drift
+__global__ __launch_bounds__(kThreads) void k_wmax(const double* part, int nblocks, double* out) {
+  auto fold = [](double m, double a) { return (a > m || a != a) ? a : m; };
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double m = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kThreads) m = fold(m, part[b * 4 + 1 + c]);
+    const double t = block_max_d(m);
+    if (threadIdx.x == 0) out[c] = t;
+  }
+}
+
 constexpr int kPaintThreads = 512;  // threads per tile workgroup of the paint
 
 // One workgroup per tile; weights: channel 0 unit mass if UNIT, then w[c].
@@ -231,7 +253,7 @@ template <typename S, typename T, int NCH, bool UNIT>
 __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const S* __restrict__ s,
                                                           const T* __restrict__ w, const unsigned* __restrict__ offs,
                                                           const unsigned* __restrict__ list, T* __restrict__ mesh,
-                                                          T* __restrict__ halo) {
+                                                          T* __restrict__ halo, const double* __restrict__ wglob) {
   constexpr int NW = NCH - (UNIT ? 1 : 0);   // weighted channels
   constexpr int NWR = NW > 0 ? NW : 1;
   constexpr bool F32 = sizeof(T) == 4;
@@ -335,6 +357,11 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
         if (nn[k] != NONE)
 #pragma unroll
           for (int c = 0; c < NW; ++c) fold(c + (UNIT ? 1 : 0), fabs(double(ws[k][c])));
+    } else if (wglob) {
+      // a larger tile with the weights' global maxima at hand uses them
+      // instead of reading its weights twice
+#pragma unroll
+      for (int c = 0; c < NW; ++c) fold(c + (UNIT ? 1 : 0), wglob[c]);
     } else {
       for (unsigned i = beg + tid; i < fin; i += kPaintThreads) {
         const unsigned n = list[i];
@@ -505,8 +532,15 @@ int paint_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
   const int64_t nt = g.ntiles;
   if (int rc = bin_typed<S, T>(p, mode, in, st)) return rc;
   const S* s = static_cast<const S*>(in.s);
-  // in the adjoint drift the weighted channels are the updated pi
-  const T* w = static_cast<const T*>(mode == DRIFT_ADJ || mode == DRIFT_SET ? in.pi : in.w);
+  // in the adjoint drift the weighted channels are the updated pi, whose
+  // per-channel maxima the drift left in the block partials
+  const bool adj = mode == DRIFT_ADJ || mode == DRIFT_SET;
+  const T* w = static_cast<const T*>(adj ? in.pi : in.w);
+  const double* wglob = nullptr;
+  if (adj && in.nw == 3) {
+    hipLaunchKernelGGL(k_wmax, dim3(1), block, 0, st, in.partials, blocks_for_particles(p), p->scalars);
+    wglob = p->scalars;
+  }
   T* mesh = static_cast<T*>(in.mesh);
   T* halo = static_cast<T*>(p->bin_halo);
   const dim3 tg{unsigned(nt), 1, 1};
@@ -524,8 +558,7 @@ int paint_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
 #define PM_TILES(NCH, UNIT)                                                                                \
   timing_begin(p, PM_K_PAINT_TILES, st);                                                                   \
   hipLaunchKernelGGL((k_paint_tiles<S, T, NCH, UNIT>), tg, dim3(kPaintThreads), 0, st, g, s, w, p->bin_offs,    \
-                     p->bin_list,                                                                          \
-                     mesh, halo);                                                                          \
+                     p->bin_list, mesh, halo, wglob);                                                      \
   timing_end(p, PM_K_PAINT_TILES, st, tile_bytes);                                                         \
   timing_begin(p, PM_K_HALO, st);                                                                          \
   if (in.defer_z) hipLaunchKernelGGL((k_halo_add<T, NCH, true>), tg, block, 0, st, g, mesh, halo);         \

@@ -131,4 +131,22 @@ __device__ __forceinline__ double block_sum_d(double v) {
   return t;
 }
 
+// largest of v over a workgroup of NT threads, NaN if any v is NaN; the
+// result is valid in thread 0
+template <int NT = kThreads>
+__device__ __forceinline__ double block_max_d(double v) {
+  __shared__ double wm[NT / 64];
+  auto fold = [](double m, double a) { return (a > m || a != a) ? a : m; };
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fold(v, __shfl_down(v, off, 64));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) wm[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < NT / 64; ++w) t = fold(t, wm[w]);
+  return t;
+}
+
 }  // namespace pmx

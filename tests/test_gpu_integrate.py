@@ -67,10 +67,14 @@ def test_forward_steps_vs_oracle(mdt, sdt, tol):
     assert rel_l2(host(st2["s"]), host(st["s"])) < (1e-14 if mdt == torch.float64 else 1e-6)
 
 
+# the second shape puts 8192 particles in each of the mesh's two tiles, so the
+# adjoint paint takes its multi-chunk path (fixed-point bound from the
+# drift's global maxima of |pi|)
+@pytest.mark.parametrize("n,nm", [(16, 32), (32, 16)])
 @pytest.mark.parametrize("mdt,sdt,tol", [(torch.float64, torch.float64, 1e-9), (torch.float32, torch.float64, 1e-4)])
-def test_adjoint_steps_vs_oracle(mdt, sdt, tol):
-    announce("adjoint steps %s/%s" % (mdt, sdt))
-    api, cfg, omega, plan = _setup(16, 32, 64.0, 5, mdt=mdt, sdt=sdt)
+def test_adjoint_steps_vs_oracle(n, nm, mdt, sdt, tol):
+    announce("adjoint steps %d^3/%d^3 %s/%s" % (n, nm, mdt, sdt))
+    api, cfg, omega, plan = _setup(n, nm, 64.0, 5, mdt=mdt, sdt=sdt)
     q = osim.lattice(cfg)
     s0, p0 = osim.initial_state(omega, cfg)
     coefs, dcoefs = ocos.step_coefficients_with_derivative(cfg.a_grid(), 0.3)
