@@ -91,7 +91,7 @@ Sizes sizes_of(const pm_config* c) {
   s.spec_bytes = size_t(4) * s.nspec * 2 * s.rb;
   s.tw_bytes = size_t(kTwiddleSize) * 2 * s.rb;
   s.part_bytes = size_t(kMaxPartials) * 4 * sizeof(double);
-  s.scal_bytes = 16 * sizeof(double);
+  s.scal_bytes = size_t(kScalars) * sizeof(double);
   int tile[3];
   tile_dims(c->mesh, tile, s.ntiles, s.halo_cells);
   s.nptcl = int64_t(c->ptcl[0]) * c->ptcl[1] * c->ptcl[2];

@@ -217,20 +217,30 @@ __global__ __launch_bounds__(kThreads) void k_contrast(T* mesh, int64_t ncell, d
     mesh[i] = T(double(mesh[i]) * ratio - 1.0);
 }
 
-// out[0] (+)= sum_k f[k] * sum_b part[b*4 + k]; summed in a fixed order
-// (slots whose factor is zero are skipped, so stale slots never contribute)
+// out[0] (+)= sum_k f[k] * sum_b part[b*4 + k], summed in a fixed order in
+// two levels: workgroup w of kReduceBlocks sums the slots of a contiguous
+// range of b into stage[w], then one workgroup sums stage (slots whose factor
+// is zero are skipped, so stale slots never contribute)
 __global__ __launch_bounds__(kThreads) void k_reduce(const double* part, int64_t nblocks, double f0, double f1,
-                                                     double f2, double f3, double* out, int accumulate) {
+                                                     double f2, double f3, double* stage) {
   const double f[4] = {f0, f1, f2, f3};
+  const int64_t per = (nblocks + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = int64_t(blockIdx.x) * per;
+  const int64_t b1 = b0 + per < nblocks ? b0 + per : nblocks;
   double v = 0.0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (f[k] == 0.0) continue;
     double s = 0.0;
-    for (int64_t b = threadIdx.x; b < nblocks; b += kThreads) s += part[b * 4 + k];
+    for (int64_t b = b0 + threadIdx.x; b < b1; b += kThreads) s += part[b * 4 + k];
     v += f[k] * s;
   }
   const double t = block_sum(v);
+  if (threadIdx.x == 0) stage[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kThreads) void k_reduce_stage(const double* stage, int n, double* out, int accumulate) {
+  const double t = block_sum(threadIdx.x < n ? stage[threadIdx.x] : 0.0);
   if (threadIdx.x == 0) out[0] = accumulate ? out[0] + t : t;
 }
 
@@ -339,8 +349,11 @@ int reduce_partials(Plan* p, int nblocks, const double* f, double* out, bool acc
 
 int reduce_buffer(Plan* p, const double* buf, int64_t nblocks, const double* f, double* out, bool accumulate,
                   hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, st, buf, nblocks, f[0], f[1], f[2], f[3], out,
-                     accumulate ? 1 : 0);
+  static_assert(kReduceBlocks <= kThreads, "one thread per staged sum");
+  double* stage = p->scalars + 16;
+  hipLaunchKernelGGL(k_reduce, dim3(kReduceBlocks), dim3(kThreads), 0, st, buf, nblocks, f[0], f[1], f[2], f[3],
+                     stage);
+  hipLaunchKernelGGL(k_reduce_stage, dim3(1), dim3(kThreads), 0, st, stage, kReduceBlocks, out, accumulate ? 1 : 0);
   PM_HIP_CHECK(p, hipGetLastError());
   return PM_OK;
 }

@@ -15,6 +15,8 @@ constexpr int kThreads = 256;        // threads per workgroup for all kernels
 constexpr int kTwiddleLog2 = 12;     // twiddle table exp(-2 pi i m / 4096)
 constexpr int kTwiddleSize = 1 << kTwiddleLog2;
 constexpr int kMaxPartials = 4096;   // per-block partial sums for reductions
+constexpr int kReduceBlocks = 128;   // first level of the two-level reductions
+constexpr int kScalars = 16 + kReduceBlocks;   // device scalars: [0, 16) named, then reduction staging
 
 // ---------------------------------------------------------------------------
 // complex helpers
@@ -76,7 +78,7 @@ struct Plan {
   void* spec[4] = {nullptr, nullptr, nullptr, nullptr};   // half spectra [nspec]
   void* tw = nullptr;                                      // twiddles (mesh dtype complex)
   double* partials = nullptr;                              // [kMaxPartials * 4]
-  double* scalars = nullptr;                               // [16] device scalars
+  double* scalars = nullptr;                               // [kScalars] device scalars
   // paint binning (paint.hip): tiles of tile[0] x tile[1] x tile[2] cells
   int tile[3] = {8, 8, 32};
   int64_t ntiles = 0;
