@@ -31,7 +31,8 @@
  *    adjoint variables (xi, pi, alpha) have cfg.mesh_dtype.
  *  - Ownership: the caller owns every pointer argument; all pointers except
  *    host-struct arguments are DEVICE pointers on the plan's device.  The
- *    plan owns only its scratch (meshes, spectra, twiddles, reduction space),
+ *    plan owns only its scratch (meshes, spectra, twiddles, reduction space,
+ *    one [3][N_p] mesh-dtype array for the native adjoint loop),
  *    allocated once in pm_plan_create, plus the 2LPT lattice scratch that
  *    the first pm_lpt / pm_lpt_vjp call allocates; pm_workspace_bytes
  *    reports both.  The other calls allocate nothing.
@@ -206,7 +207,11 @@ int pm_step_adj(pm_plan plan, pm_state* st, pm_adj* adj, const pm_step_coef* cur
 
 /* Whole loops (native drivers of the two calls above).  coefs: host array of
  * n steps.  pm_run_fwd = pm_fwd_init + n x pm_step_fwd;  pm_run_adj =
- * pm_adj_init + n x pm_step_adj (reverse order). */
+ * pm_adj_init + n x pm_step_adj (reverse order), with bitwise the same
+ * result.  With st->acc given, the loops use it as scratch: each gather
+ * stores a there and leaves its kick to the next step's drift (the plan's
+ * workspace holds alpha for the adjoint).  After pm_run_fwd, acc holds a_n
+ * as after the step calls; after pm_run_adj its contents are unspecified. */
 int pm_run_fwd(pm_plan plan, pm_state* st, const pm_step_coef* coefs, int n, double coef,
                hipStream_t stream);
 int pm_run_adj(pm_plan plan, pm_state* st, pm_adj* adj, const pm_step_coef* coefs, int n,

@@ -78,8 +78,10 @@ struct Sizes {
   int64_t ncell, nspec, nptcl, ntiles;
   int halo_cells;
   size_t rb;
-  size_t mesh_bytes, spec_bytes, tw_bytes, part_bytes, scal_bytes, bin_bytes;
-  size_t total() const { return mesh_bytes + spec_bytes + tw_bytes + part_bytes + scal_bytes + bin_bytes; }
+  size_t mesh_bytes, spec_bytes, tw_bytes, part_bytes, scal_bytes, bin_bytes, kick_bytes;
+  size_t total() const {
+    return mesh_bytes + spec_bytes + tw_bytes + part_bytes + scal_bytes + bin_bytes + kick_bytes;
+  }
 };
 
 Sizes sizes_of(const pm_config* c) {
@@ -92,6 +94,8 @@ Sizes sizes_of(const pm_config* c) {
   s.tw_bytes = size_t(kTwiddleSize) * 2 * s.rb;
   s.part_bytes = size_t(kMaxPartials) * 4 * sizeof(double);
   s.scal_bytes = size_t(kScalars) * sizeof(double);
+  // alpha of the adjoint kick a native loop leaves pending: [3][N] mesh dtype
+  s.kick_bytes = size_t(3) * size_t(int64_t(c->ptcl[0]) * c->ptcl[1] * c->ptcl[2]) * s.rb;
   int tile[3];
   tile_dims(c->mesh, tile, s.ntiles, s.halo_cells);
   s.nptcl = int64_t(c->ptcl[0]) * c->ptcl[1] * c->ptcl[2];
@@ -331,13 +335,15 @@ int pm_plan_create(const pm_config* cfg, pm_plan* out) {
       hipMalloc(&bb, s.bin_bytes) != hipSuccess ||
       hipMalloc(&p->tw, s.tw_bytes) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&p->partials), s.part_bytes) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&p->scalars), s.scal_bytes) != hipSuccess) {
+      hipMalloc(reinterpret_cast<void**>(&p->scalars), s.scal_bytes) != hipSuccess ||
+      hipMalloc(&p->kick_al, s.kick_bytes) != hipSuccess) {
     if (mb) (void)hipFree(mb);
     if (sb) (void)hipFree(sb);
     if (bb) (void)hipFree(bb);
     if (p->tw) (void)hipFree(p->tw);
     if (p->partials) (void)hipFree(p->partials);
     if (p->scalars) (void)hipFree(p->scalars);
+    if (p->kick_al) (void)hipFree(p->kick_al);
     (void)hipGetLastError();
     delete p;
     return set_error(nullptr, PM_ENOMEM, "could not allocate %zu bytes of plan scratch", s.total());
@@ -391,6 +397,7 @@ int pm_plan_create(const pm_config* cfg, pm_plan* out) {
     (void)hipFree(p->tw);
     (void)hipFree(p->partials);
     (void)hipFree(p->scalars);
+    (void)hipFree(p->kick_al);
     delete p;
     return set_error(nullptr, PM_EDEVICE, "plan initialisation failed");
   }
@@ -408,6 +415,7 @@ int pm_plan_destroy(pm_plan h) {
   (void)hipFree(p->tw);
   (void)hipFree(p->partials);
   (void)hipFree(p->scalars);
+  (void)hipFree(p->kick_al);
   for (void* q : p->lreal) if (q) (void)hipFree(q);
   for (void* q : p->lspec) if (q) (void)hipFree(q);
   for (auto& f : p->timing.fam)
@@ -632,39 +640,77 @@ int pm_step_adj(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* cur, 
 }
 
 int pm_run_fwd(pm_plan h, pm_state* stt, const pm_step_coef* coefs, int n, double coef, hipStream_t st) {
-  CHECK_PLAN(h);
-  if (!coefs || n < 1) return set_error(p, PM_EINVAL, "need n >= 1 step coefficients");
-  if (int rc = pm_fwd_init(h, stt, &coefs[0], coef, st)) return rc;
-  for (int i = 0; i < n; ++i)
-    if (int rc = pm_step_fwd(h, stt, &coefs[i], i + 1 < n ? &coefs[i + 1] : nullptr, coef, st)) return rc;
-  return PM_OK;
+  return pm_run_fwd_ckpt(h, stt, coefs, n, coef, nullptr, st);
 }
 
 int pm_run_adj(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* coefs, int n, double coef,
                double* theta_bar, hipStream_t st) {
-  CHECK_PLAN(h);
-  if (!coefs || n < 1) return set_error(p, PM_EINVAL, "need n >= 1 step coefficients");
-  if (int rc = pm_adj_init(h, stt, adj, &coefs[n - 1], coef, theta_bar, st)) return rc;
-  for (int i = n - 1; i >= 0; --i)
-    if (int rc = pm_step_adj(h, stt, adj, &coefs[i], i > 0 ? &coefs[i - 1] : nullptr, coef, theta_bar, st))
-      return rc;
-  return PM_OK;
+  return pm_run_adj_ckpt(h, stt, adj, coefs, n, coef, nullptr, theta_bar, st);
 }
 
+// The native loops.  With st->acc given, every kick is left pending: the
+// gather only stores a (and alpha) in lattice order, and the next step's
+// drift, which reads and writes p (and xi) in lattice order anyway, applies
+// the kick before it moves the particles; the last one is applied at the end.
+// Kicks and drifts use the same fused multiply-adds in both places, so the
+// result is bitwise that of the step calls.  Without st->acc the loops are the
+// step calls.
 int pm_run_fwd_ckpt(pm_plan h, pm_state* stt, const pm_step_coef* coefs, int n, double coef,
                     const pm_checkpoints* ck, hipStream_t st) {
   CHECK_PLAN(h);
   if (!coefs || n < 1) return set_error(p, PM_EINVAL, "need n >= 1 step coefficients");
   if (int rc = check_checkpoints(p, ck, n)) return rc;
-  if (int rc = pm_fwd_init(h, stt, &coefs[0], coef, st)) return rc;
   const size_t bytes = state_bytes(p);
-  for (int i = 0; i < n; ++i) {
-    const int k = checkpoint_index(ck, i + 1);
-    if (k >= 0) PM_HIP_CHECK(p, hipMemcpyAsync(ck->p[k], stt->p, bytes, hipMemcpyDeviceToDevice, st));
-    if (int rc = pm_step_fwd(h, stt, &coefs[i], i + 1 < n ? &coefs[i + 1] : nullptr, coef, st)) return rc;
-    if (k >= 0) PM_HIP_CHECK(p, hipMemcpyAsync(ck->s[k], stt->s, bytes, hipMemcpyDeviceToDevice, st));
+  if (!stt || !stt->acc) {
+    if (int rc = pm_fwd_init(h, stt, &coefs[0], coef, st)) return rc;
+    for (int i = 0; i < n; ++i) {
+      const int k = checkpoint_index(ck, i + 1);
+      if (k >= 0) PM_HIP_CHECK(p, hipMemcpyAsync(ck->p[k], stt->p, bytes, hipMemcpyDeviceToDevice, st));
+      if (int rc = pm_step_fwd(h, stt, &coefs[i], i + 1 < n ? &coefs[i + 1] : nullptr, coef, st)) return rc;
+      if (k >= 0) PM_HIP_CHECK(p, hipMemcpyAsync(ck->s[k], stt->s, bytes, hipMemcpyDeviceToDevice, st));
+    }
+    return PM_OK;
   }
-  return PM_OK;
+  if (int rc = check_ptr(p, stt->s, "state.s")) return rc;
+  if (int rc = check_ptr(p, stt->p, "state.p")) return rc;
+  for (int i = 0; i < n; ++i)
+    if (int rc = check_step(p, &coefs[i], "coefs[i]")) return rc;
+  if (int rc = check_coef(p, coef)) return rc;
+  if (int rc = set_device(p)) return rc;
+  // a_0 = F(x_0); the kick p_0 + a_0 Ka_1 is left pending
+  PaintArgs pa{};
+  pa.s = stt->s;
+  pa.unit = 1;
+  pa.mesh = p->mesh[0];
+  if (int rc = paint_force_fields(p, DRIFT_NONE, pa, coef, st)) return rc;
+  GatherArgs ga{};
+  ga.s = stt->s;
+  ga.mesh = p->mesh[0];
+  ga.nf = 3;
+  ga.out = stt->acc;
+  ga.binned = true;
+  if (int rc = gather_launch(p, GATHER_PLAIN, ga, st)) return rc;
+  double Kp = coefs[0].Ka;
+  for (int i = 0; i < n; ++i) {
+    PaintArgs pb{};
+    pb.s = stt->s;
+    pb.p = stt->p;
+    pb.unit = 1;
+    pb.mesh = p->mesh[0];
+    pb.D = coefs[i].D;
+    pb.kick_a = stt->acc;
+    pb.Kp = Kp;
+    if (int rc = paint_force_fields(p, DRIFT_FWD, pb, coef, st)) return rc;
+    // the drift has applied the kick and moved the particles: (s_{i+1}, p_{i+1/2})
+    const int k = checkpoint_index(ck, i + 1);
+    if (k >= 0) {
+      PM_HIP_CHECK(p, hipMemcpyAsync(ck->p[k], stt->p, bytes, hipMemcpyDeviceToDevice, st));
+      PM_HIP_CHECK(p, hipMemcpyAsync(ck->s[k], stt->s, bytes, hipMemcpyDeviceToDevice, st));
+    }
+    if (int rc = gather_launch(p, GATHER_PLAIN, ga, st)) return rc;   // a_{i+1}
+    Kp = coefs[i].Kb + (i + 1 < n ? coefs[i + 1].Ka : 0.0);
+  }
+  return kick_flush(p, stt->p, stt->acc, Kp, false, nullptr, nullptr, 0.0, st);
 }
 
 int pm_run_adj_ckpt(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* coefs, int n, double coef,
@@ -677,13 +723,64 @@ int pm_run_adj_ckpt(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* c
   if (int rc = pm_adj_init(h, stt, adj, &coefs[n - 1], coef, theta_bar, st)) return rc;
   const int kn = checkpoint_index(ck, n);
   if (kn >= 0) PM_HIP_CHECK(p, hipMemcpyAsync(stt->p, ck->p[kn], state_bytes(p), hipMemcpyDeviceToDevice, st));
+  const bool defer = stt->acc != nullptr;
+  bool pending = false;
+  double Kp = 0.0, Kx = 0.0;
   for (int i = n - 1; i >= 0; --i) {
     // reverse step i + 1 ends at t_i: resume from checkpoint i if there is one
     const int k = i >= 1 ? checkpoint_index(ck, i) : -1;
-    if (int rc = step_adj(p, stt, adj, &coefs[i], i > 0 ? &coefs[i - 1] : nullptr, coef, theta_bar,
-                          k >= 0 ? ck->s[k] : nullptr, k >= 0 ? ck->p[k] : nullptr, st))
-      return rc;
+    const void* s_set = k >= 0 ? ck->s[k] : nullptr;
+    const void* p_set = k >= 0 ? ck->p[k] : nullptr;
+    const pm_step_coef* cur = &coefs[i];
+    const pm_step_coef* prev = i > 0 ? &coefs[i - 1] : nullptr;
+    if (!defer) {
+      if (int rc = step_adj(p, stt, adj, cur, prev, coef, theta_bar, s_set, p_set, st)) return rc;
+      continue;
+    }
+    PaintArgs pa{};
+    pa.s = stt->s;
+    pa.p = stt->p;
+    pa.xi = adj->xi;
+    pa.pi = adj->pi;
+    pa.unit = 1;
+    pa.nw = 3;
+    pa.mesh = p->mesh[0];
+    pa.D = cur->D;
+    pa.partials = p->partials;
+    pa.s_set = s_set;
+    if (pending) {
+      pa.kick_a = stt->acc;
+      pa.kick_al = p->kick_al;
+      pa.Kp = Kp;
+      pa.Kx = Kx;
+    }
+    if (int rc = paint_vjp_fields(p, s_set ? DRIFT_SET : DRIFT_ADJ, pa, coef, st)) return rc;
+    const double K = cur->Ka + (prev ? prev->Kb : 0.0);
+    const double dK = cur->dKa + (prev ? prev->dKb : 0.0);
+    // a and alpha at x_i, pi.a partials; the kick p -= a K, xi += alpha K is left pending
+    GatherArgs ga{};
+    ga.s = stt->s;
+    ga.mesh = p->mesh[0];
+    ga.nf = 4;
+    ga.out = p->kick_al;
+    ga.acc = stt->acc;
+    ga.cot = adj->pi;
+    ga.binned = true;
+    if (int rc = gather_launch(p, GATHER_VJP, ga, st)) return rc;
+    const double fd[4] = {cur->dD, 0.0, 0.0, 0.0};
+    if (int rc = reduce_partials(p, blocks_for_particles(p), fd, theta_bar, true, st)) return rc;
+    const double fk[4] = {0.0, dK + K * 1.5 / coef, 0.0, 0.0};
+    if (int rc = reduce_buffer(p, p->tile_partials, p->ntiles, fk, theta_bar, true, st)) return rc;
+    pending = true;
+    Kp = K;
+    Kx = K;
+    if (p_set) {
+      // the stored momentum already holds this kick
+      PM_HIP_CHECK(p, hipMemcpyAsync(stt->p, p_set, state_bytes(p), hipMemcpyDeviceToDevice, st));
+      Kp = 0.0;
+    }
   }
+  if (defer && pending) return kick_flush(p, stt->p, stt->acc, Kp, true, adj->xi, p->kick_al, Kx, st);
   return PM_OK;
 }
 

@@ -36,22 +36,30 @@ template <typename S, typename T>
 struct BinP {
   TileGeo g;
   S* s;
-  const S* p;
-  const T* xi;
+  S* p;
+  T* xi;
   T* pi;
   S D;
   unsigned* counts;   // [ntiles]
   uint2* keys;        // [N] (tile, rank)
   double* partials;   // slot 0: xi.p (adjoint drift)
   const S* s_set;     // DRIFT_SET: displacement after the drift
+  // KICK: the kick the previous step's gather left pending, applied before
+  // the drift: p += a Kp (forward) or p -= a Kp, xi += alpha Kx (adjoint)
+  const T* ka;
+  const T* kal;
+  S Kp;
+  T Kx;
 };
 
 // Each thread takes U particles per round, all loads issued first.  Lanes of
 // a wavefront that share a tile form a group; the group leaders then issue
 // their count atomics together (one instruction, one round trip), and every
 // lane takes its rank from its leader's result.
-template <typename S, typename T, int MODE>
+template <typename S, typename T, int MODE, bool KICK>
 __global__ __launch_bounds__(kThreads) void k_bin(BinP<S, T> a) {
+  static_assert(!KICK || MODE != DRIFT_NONE, "a pending kick comes with a drift");
+  constexpr bool ADJ = MODE == DRIFT_ADJ || MODE == DRIFT_SET;
   constexpr int U = 4;
   const TileGeo& g = a.g;
   int64_t start, end;
@@ -62,7 +70,7 @@ __global__ __launch_bounds__(kThreads) void k_bin(BinP<S, T> a) {
   auto fold = [](double m, double a) { return (a > m || a != a) ? a : m; };
   for (int64_t base = start; base < end; base += U * kThreads) {
     S sv[U][3], pv[U][3];
-    T xv[U][3], piv[U][3];
+    T xv[U][3], piv[U][3], kav[U][KICK ? 3 : 1], kalv[U][KICK && ADJ ? 3 : 1];
     bool valid[U];
     int tile[U];
 #pragma unroll
@@ -74,10 +82,12 @@ __global__ __launch_bounds__(kThreads) void k_bin(BinP<S, T> a) {
       for (int ax = 0; ax < 3; ++ax) {
         sv[u][ax] = (MODE == DRIFT_SET ? a.s_set : a.s)[ax * g.N + n];
         if (MODE != DRIFT_NONE) pv[u][ax] = a.p[ax * g.N + n];
-        if (MODE == DRIFT_ADJ || MODE == DRIFT_SET) {
+        if (ADJ) {
           xv[u][ax] = a.xi[ax * g.N + n];
           piv[u][ax] = a.pi[ax * g.N + n];
         }
+        if (KICK) kav[u][ax] = a.ka[ax * g.N + n];
+        if (KICK && ADJ) kalv[u][ax] = a.kal[ax * g.N + n];
       }
     }
 #pragma unroll
@@ -85,19 +95,31 @@ __global__ __launch_bounds__(kThreads) void k_bin(BinP<S, T> a) {
       tile[u] = 0;
       if (!valid[u]) continue;
       const int64_t n = base + threadIdx.x + u * kThreads;
+      if constexpr (KICK) {
+        // the same fused multiply-adds as the gather's immediate kicks
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          pv[u][ax] = fma(ADJ ? -S(kav[u][ax]) : S(kav[u][ax]), a.Kp, pv[u][ax]);
+          a.p[ax * g.N + n] = pv[u][ax];
+          if (ADJ) {
+            xv[u][ax] = fma(kalv[u][ax], a.Kx, xv[u][ax]);
+            a.xi[ax * g.N + n] = xv[u][ax];
+          }
+        }
+      }
       if (MODE == DRIFT_FWD) {
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-          sv[u][ax] += pv[u][ax] * a.D;
+          sv[u][ax] = fma(pv[u][ax], a.D, sv[u][ax]);
           a.s[ax * g.N + n] = sv[u][ax];
         }
       } else if (MODE == DRIFT_ADJ || MODE == DRIFT_SET) {
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
           xp += double(xv[u][ax]) * double(pv[u][ax]);
-          if (MODE == DRIFT_ADJ) sv[u][ax] -= pv[u][ax] * a.D;
+          if (MODE == DRIFT_ADJ) sv[u][ax] = fma(-pv[u][ax], a.D, sv[u][ax]);
           a.s[ax * g.N + n] = sv[u][ax];
-          const T pn = piv[u][ax] + T(xv[u][ax] * T(a.D));
+          const T pn = fma(xv[u][ax], T(a.D), piv[u][ax]);
           a.pi[ax * g.N + n] = pn;
           pm[ax] = fold(pm[ax], fabs(double(pn)));
         }
@@ -488,26 +510,35 @@ int bin_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
   BinP<S, T> b;
   b.g = g;
   b.s = static_cast<S*>(const_cast<void*>(in.s));
-  b.p = static_cast<const S*>(in.p);
-  b.xi = static_cast<const T*>(in.xi);
+  b.p = static_cast<S*>(const_cast<void*>(in.p));
+  b.xi = static_cast<T*>(const_cast<void*>(in.xi));
   b.pi = static_cast<T*>(in.pi);
   b.D = S(in.D);
   b.counts = p->bin_counts;
   b.keys = static_cast<uint2*>(p->bin_keys);
   b.partials = in.partials;
   b.s_set = static_cast<const S*>(in.s_set);
+  b.ka = static_cast<const T*>(in.kick_a);
+  b.kal = static_cast<const T*>(in.kick_al);
+  b.Kp = S(in.Kp);
+  b.Kx = T(in.Kx);
+  const bool kick = in.kick_a != nullptr;
+  const bool adj = mode == DRIFT_ADJ || mode == DRIFT_SET;
   timing_begin(p, PM_K_BIN, st);
-  if (mode == DRIFT_FWD) hipLaunchKernelGGL((k_bin<S, T, DRIFT_FWD>), dim3(pblocks), block, 0, st, b);
-  else if (mode == DRIFT_ADJ) hipLaunchKernelGGL((k_bin<S, T, DRIFT_ADJ>), dim3(pblocks), block, 0, st, b);
-  else if (mode == DRIFT_SET) hipLaunchKernelGGL((k_bin<S, T, DRIFT_SET>), dim3(pblocks), block, 0, st, b);
-  else hipLaunchKernelGGL((k_bin<S, T, DRIFT_NONE>), dim3(pblocks), block, 0, st, b);
+#define PM_BIN(MODE, KICK) hipLaunchKernelGGL((k_bin<S, T, MODE, KICK>), dim3(pblocks), block, 0, st, b)
+  if (mode == DRIFT_FWD) { if (kick) PM_BIN(DRIFT_FWD, true); else PM_BIN(DRIFT_FWD, false); }
+  else if (mode == DRIFT_ADJ) { if (kick) PM_BIN(DRIFT_ADJ, true); else PM_BIN(DRIFT_ADJ, false); }
+  else if (mode == DRIFT_SET) { if (kick) PM_BIN(DRIFT_SET, true); else PM_BIN(DRIFT_SET, false); }
+  else PM_BIN(DRIFT_NONE, false);
+#undef PM_BIN
   {
     // s (or s_set) read (+ p read, s write; adjoint: xi read, pi read/write),
-    // key write
+    // key write; a pending kick reads a (and alpha) and writes p (and xi)
     const double N = double(g.N), sb = sizeof(S), mb = sizeof(T);
     double bytes = 3 * N * sb + 8 * N;
     if (mode == DRIFT_FWD) bytes += 6 * N * sb;
-    if (mode == DRIFT_ADJ || mode == DRIFT_SET) bytes += 6 * N * sb + 9 * N * mb;
+    if (adj) bytes += 6 * N * sb + 9 * N * mb;
+    if (kick) bytes += 3 * N * (mb + sb) + (adj ? 6 * N * mb : 0.0);
     timing_end(p, PM_K_BIN, st, bytes);
   }
   const int64_t nt = g.ntiles;

@@ -155,7 +155,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_tiles(GatherP<S, T> a
         } else if (KICKF) {
 #pragma unroll
           for (int ax = 0; ax < 3; ++ax) {
-            a.p[ax * g.N + n] = ps[k][ax] + S(v[ax]) * a.K;
+            // fused multiply-add, as a drift applying this kick later does
+            a.p[ax * g.N + n] = fma(S(v[ax]), a.K, ps[k][ax]);
             if (a.acc) a.acc[ax * g.N + n] = v[ax];
           }
         } else if (MODE == GATHER_VJP) {
@@ -173,8 +174,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_tiles(GatherP<S, T> a
 #pragma unroll
           for (int ax = 0; ax < 3; ++ax) {
             ca += double(cot[ax]) * double(v[ax]);
-            a.p[ax * g.N + n] = ps[k][ax] - S(v[ax]) * a.K;
-            a.xi[ax * g.N + n] = xis[k][ax] + dv[ax] * T(a.K);
+            a.p[ax * g.N + n] = fma(-S(v[ax]), a.K, ps[k][ax]);
+            a.xi[ax * g.N + n] = fma(dv[ax], T(a.K), xis[k][ax]);
             if (a.acc) a.acc[ax * g.N + n] = v[ax];
           }
         } else if (MODE == GATHER_MSE) {
@@ -294,6 +295,43 @@ int gather_typed(Plan* p, GatherMode mode, const GatherArgs& in, hipStream_t st)
 }
 
 }  // namespace
+
+// p += a Kp (or -=, adjoint) and xi += alpha Kx: a kick left pending by the
+// last gather of a native loop, with the fused multiply-adds of the drift
+template <typename S, typename T, bool ADJ>
+__global__ __launch_bounds__(kThreads) void k_kick_flush(S* __restrict__ p, const T* __restrict__ a, S Kp,
+                                                         T* __restrict__ xi, const T* __restrict__ al, T Kx,
+                                                         int64_t n3) {
+  const int64_t stride = int64_t(gridDim.x) * kThreads;
+  for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n3; i += stride) {
+    p[i] = fma(ADJ ? -S(a[i]) : S(a[i]), Kp, p[i]);
+    if (ADJ) xi[i] = fma(al[i], Kx, xi[i]);
+  }
+}
+
+template <typename S, typename T>
+void kick_flush_typed(Plan* p, void* ps, const void* a, double Kp, bool adjoint, void* xi, const void* al,
+                      double Kx, hipStream_t st) {
+  const int64_t n3 = 3 * p->nptcl;
+  const int64_t need = (n3 + kThreads - 1) / kThreads;
+  const int blocks = int(need < 4096 ? need : 4096);
+  if (adjoint)
+    hipLaunchKernelGGL((k_kick_flush<S, T, true>), dim3(blocks), dim3(kThreads), 0, st, static_cast<S*>(ps),
+                       static_cast<const T*>(a), S(Kp), static_cast<T*>(xi), static_cast<const T*>(al), T(Kx), n3);
+  else
+    hipLaunchKernelGGL((k_kick_flush<S, T, false>), dim3(blocks), dim3(kThreads), 0, st, static_cast<S*>(ps),
+                       static_cast<const T*>(a), S(Kp), static_cast<T*>(xi), static_cast<const T*>(al), T(Kx), n3);
+}
+
+int kick_flush(Plan* p, void* ps, const void* a, double Kp, bool adjoint, void* xi, const void* al, double Kx,
+               hipStream_t st) {
+  const bool s64 = p->cfg.state_dtype == PM_F64, m64 = p->cfg.mesh_dtype == PM_F64;
+  if (m64) kick_flush_typed<double, double>(p, ps, a, Kp, adjoint, xi, al, Kx, st);
+  else if (s64) kick_flush_typed<double, float>(p, ps, a, Kp, adjoint, xi, al, Kx, st);
+  else kick_flush_typed<float, float>(p, ps, a, Kp, adjoint, xi, al, Kx, st);
+  PM_HIP_CHECK(p, hipGetLastError());
+  return PM_OK;
+}
 
 int blocks_for_particles(const Plan* p) {
   const int64_t need = (p->nptcl + kThreads - 1) / kThreads;

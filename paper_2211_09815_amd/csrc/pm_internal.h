@@ -79,6 +79,7 @@ struct Plan {
   void* tw = nullptr;                                      // twiddles (mesh dtype complex)
   double* partials = nullptr;                              // [kMaxPartials * 4]
   double* scalars = nullptr;                               // [kScalars] device scalars
+  void* kick_al = nullptr;                                 // [3][N] mesh dtype, pending alpha
   // paint binning (paint.hip): tiles of tile[0] x tile[1] x tile[2] cells
   int tile[3] = {8, 8, 32};
   int64_t ntiles = 0;
@@ -200,7 +201,16 @@ struct PaintArgs {
   double* partials;     // per-block partial sum of xi.p (adjoint drift)
   const void* s_set;    // DRIFT_SET: [3][N] state dtype, positions to land on
   bool defer_z;         // leave the z faces of the halo to the next R2C (paint_zfold)
+  // kick left pending by the previous gather, applied by the drift before it
+  // moves the particles: p += a Kp (forward), p -= a Kp and xi += alpha Kx
+  // (adjoint); kick_a null: none
+  const void* kick_a;   // [3][N] mesh dtype a
+  const void* kick_al;  // [3][N] mesh dtype alpha (adjoint)
+  double Kp, Kx;
 };
+// apply a pending kick without a drift (the end of a native loop)
+int kick_flush(Plan* p, void* pstate, const void* a, double Kp, bool adjoint, void* xi, const void* al, double Kx,
+               hipStream_t st);
 int paint_launch(Plan* p, DriftMode mode, const PaintArgs& a, hipStream_t st);
 // tile binning only (drift + bins + per-tile lists), as done by paint_launch
 int bin_launch(Plan* p, DriftMode mode, const PaintArgs& a, hipStream_t st);
