@@ -133,6 +133,26 @@ def _rel_l2(a, b):
                  / torch.linalg.vector_norm(b.double().reshape(-1)))
 
 
+def copy_bandwidth(gib=2, reps=5):
+    """Best device-to-device copy rate (read + write bytes / time) of a
+    `gib` GiB buffer: the practical HBM ceiling next to the published peak."""
+    import torch
+    x = torch.empty((gib << 30) // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    best = 0.0
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        e1.synchronize()
+        best = max(best, 2.0 * x.numel() * 4 / 1e9 / (e0.elapsed_time(e1) / 1e3))
+    del x, y
+    torch.cuda.empty_cache()
+    return best
+
+
 def fp64_reference(args, target64, g_mixed, th_mixed):
     """One all-FP64 pass on the same workload (same white noise and target):
     its throughput and the relative L2 error of the benchmarked gradients."""
@@ -492,6 +512,8 @@ def main():
     gn = float(torch.linalg.vector_norm(g.double()).cpu())
     ok = math.isfinite(Jv) and all(math.isfinite(x) for x in thv) and math.isfinite(gn)
     log("J %.6e  |dJ/domega| %.6e  dJ/dtheta %s  finite %s" % (Jv, gn, thv, ok))
+    copy_gbs = copy_bandwidth()
+    log("device copy: %.0f GB/s" % copy_gbs)
     ref = None
     if not args.no_fp64_ref and (args.mesh_dtype, args.state_dtype) != ("f64", "f64"):
         g_keep, th_keep = g.double().clone(), th.clone()
@@ -536,6 +558,8 @@ def main():
             "launches": klaunch,
             "avg_launch_ms": kms / klaunch if klaunch else None,
             "algorithmic_bytes_per_launch": kbytes / klaunch if klaunch else None,
+            "device_copy_GBps": copy_gbs,
+            "frac_of_copy": (achieved / copy_gbs) if achieved else None,
         },
         "kernels": kernels,
         "result": {"J": Jv, "dJ_dtheta": thv, "grad_omega_norm": gn, "finite": ok},
