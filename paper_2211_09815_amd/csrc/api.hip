@@ -99,8 +99,8 @@ Sizes sizes_of(const pm_config* c) {
   int tile[3];
   tile_dims(c->mesh, tile, s.ntiles, s.halo_cells);
   s.nptcl = int64_t(c->ptcl[0]) * c->ptcl[1] * c->ptcl[2];
-  // keys, per-tile partials, halo faces, list, counts, offsets, block sums
-  s.bin_bytes = size_t(s.nptcl) * 8 + size_t(s.ntiles) * 4 * sizeof(double) +
+  // CIC records (FP32 meshes), keys, per-tile partials, halo faces, list, counts, offsets, block sums
+  s.bin_bytes = (s.rb == 4 ? size_t(s.nptcl) * 16 : 0) + size_t(s.nptcl) * 8 + size_t(s.ntiles) * 4 * sizeof(double) +
                 size_t(4) * s.ntiles * s.halo_cells * s.rb + size_t(s.nptcl) * 4 + size_t(s.ntiles) * 4 +
                 size_t(s.ntiles + 1) * 4 + size_t(4 * kThreads) * 4;
   return s;
@@ -354,7 +354,11 @@ int pm_plan_create(const pm_config* cfg, pm_plan* out) {
   }
   {
     char* q = static_cast<char*>(bb);
-    p->bin_keys = q;  // 8-byte aligned first
+    if (s.rb == 4) {
+      p->bin_rec = q;  // 16-byte aligned first
+      q += size_t(s.nptcl) * 16;
+    }
+    p->bin_keys = q;  // 8-byte aligned
     q += size_t(s.nptcl) * 8;
     p->tile_partials = reinterpret_cast<double*>(q);
     q += size_t(s.ntiles) * 4 * sizeof(double);
@@ -411,7 +415,7 @@ int pm_plan_destroy(pm_plan h) {
   (void)hipDeviceSynchronize();
   (void)hipFree(p->mesh[0]);
   (void)hipFree(p->spec[0]);
-  (void)hipFree(p->bin_keys);
+  (void)hipFree(p->bin_rec ? p->bin_rec : p->bin_keys);   // the start of the binning buffer
   (void)hipFree(p->tw);
   (void)hipFree(p->partials);
   (void)hipFree(p->scalars);

@@ -50,6 +50,7 @@ struct BinP {
   const T* kal;
   S Kp;
   T Kx;
+  float4* rec;        // FP32 meshes: per-particle CIC record (see tiles.h)
 };
 
 // Each thread takes U particles per round, all loads issued first.  Lanes of
@@ -126,10 +127,15 @@ __global__ __launch_bounds__(kThreads) void k_bin(BinP<S, T> a) {
       }
       double q[3];
       lattice_pos(g, n, q);
-      const int b0 = int(int64_t(floor(q[0] + double(sv[u][0]))) & (g.n0 - 1));
-      const int b1 = int(int64_t(floor(q[1] + double(sv[u][1]))) & (g.n1 - 1));
-      const int b2 = int(int64_t(floor(q[2] + double(sv[u][2]))) & (g.n2 - 1));
+      const double x0 = q[0] + double(sv[u][0]), x1 = q[1] + double(sv[u][1]), x2 = q[2] + double(sv[u][2]);
+      const double f0 = floor(x0), f1 = floor(x1), f2 = floor(x2);
+      const int b0 = int(int64_t(f0) & (g.n0 - 1));
+      const int b1 = int(int64_t(f1) & (g.n1 - 1));
+      const int b2 = int(int64_t(f2) & (g.n2 - 1));
       tile[u] = ((b0 >> g.ltx) * g.nty + (b1 >> g.lty)) * g.ntz + (b2 >> g.ltz);
+      if constexpr (kUseRec<T>)
+        a.rec[n] = make_float4(__uint_as_float(pack_cell(b0, b1, b2)), float(x0 - f0), float(x1 - f1),
+                               float(x2 - f2));
     }
     int leader[U];
     unsigned within[U], gsize[U], baseidx[U];
@@ -275,7 +281,8 @@ template <typename S, typename T, int NCH, bool UNIT>
 __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const S* __restrict__ s,
                                                           const T* __restrict__ w, const unsigned* __restrict__ offs,
                                                           const unsigned* __restrict__ list, T* __restrict__ mesh,
-                                                          T* __restrict__ halo, const double* __restrict__ wglob) {
+                                                          T* __restrict__ halo, const double* __restrict__ wglob,
+                                                          const float4* __restrict__ rec) {
   constexpr int NW = NCH - (UNIT ? 1 : 0);   // weighted channels
   constexpr int NWR = NW > 0 ? NW : 1;
   constexpr bool F32 = sizeof(T) == 4;
@@ -296,8 +303,10 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
   const unsigned beg = offs[tile], fin = offs[tile + 1];
   const int tid = threadIdx.x;
 
+  constexpr bool REC = kUseRec<T>;
   unsigned nn[P];
-  S xs[P][3];
+  S xs[P][REC ? 1 : 3];
+  float4 rs[P];
   T ws[P][NWR];
   auto load = [&](unsigned c0) {
 #pragma unroll
@@ -308,8 +317,12 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
 #pragma unroll
     for (int k = 0; k < P; ++k) {
       if (nn[k] == NONE) continue;
+      if constexpr (REC) {
+        rs[k] = rec[nn[k]];
+      } else {
 #pragma unroll
-      for (int ax = 0; ax < 3; ++ax) xs[k][ax] = s[ax * g.N + nn[k]];
+        for (int ax = 0; ax < 3; ++ax) xs[k][ax] = s[ax * g.N + nn[k]];
+      }
 #pragma unroll
       for (int c = 0; c < NW; ++c) ws[k][c] = w[c * g.N + nn[k]];
     }
@@ -321,15 +334,24 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
 #pragma unroll
     for (int k = 0; k < P; ++k) {
       if (nn[k] == NONE) continue;
-      double q[3];
-      lattice_pos(g, nn[k], q);
-      const double x0 = q[0] + double(xs[k][0]), x1 = q[1] + double(xs[k][1]), x2 = q[2] + double(xs[k][2]);
-      const double f0 = floor(x0), f1 = floor(x1), f2 = floor(x2);
-      // local base node inside the tile (the particle was binned by it)
-      const int l0 = int(int64_t(f0) & (g.n0 - 1)) - o0;
-      const int l1 = int(int64_t(f1) & (g.n1 - 1)) - o1;
-      const int l2 = int(int64_t(f2) & (g.n2 - 1)) - o2;
-      const T d0 = T(x0 - f0), d1 = T(x1 - f1), d2 = T(x2 - f2);
+      // local base node inside the tile (the particle was binned by it) and
+      // the in-cell fractions
+      int l0, l1, l2;
+      T d0, d1, d2;
+      if constexpr (REC) {
+        unpack_rec(rs[k], o0, o1, o2, l0, l1, l2, d0, d1, d2);
+      } else {
+        double q[3];
+        lattice_pos(g, nn[k], q);
+        const double x0 = q[0] + double(xs[k][0]), x1 = q[1] + double(xs[k][1]), x2 = q[2] + double(xs[k][2]);
+        const double f0 = floor(x0), f1 = floor(x1), f2 = floor(x2);
+        l0 = int(int64_t(f0) & (g.n0 - 1)) - o0;
+        l1 = int(int64_t(f1) & (g.n1 - 1)) - o1;
+        l2 = int(int64_t(f2) & (g.n2 - 1)) - o2;
+        d0 = T(x0 - f0);
+        d1 = T(x1 - f1);
+        d2 = T(x2 - f2);
+      }
       const T wx[2] = {T(1) - d0, d0}, wy[2] = {T(1) - d1, d1}, wz[2] = {T(1) - d2, d2};
       double wc[NCH];
 #pragma unroll
@@ -522,6 +544,7 @@ int bin_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
   b.kal = static_cast<const T*>(in.kick_al);
   b.Kp = S(in.Kp);
   b.Kx = T(in.Kx);
+  b.rec = static_cast<float4*>(p->bin_rec);
   const bool kick = in.kick_a != nullptr;
   const bool adj = mode == DRIFT_ADJ || mode == DRIFT_SET;
   timing_begin(p, PM_K_BIN, st);
@@ -589,7 +612,7 @@ int paint_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
 #define PM_TILES(NCH, UNIT)                                                                                \
   timing_begin(p, PM_K_PAINT_TILES, st);                                                                   \
   hipLaunchKernelGGL((k_paint_tiles<S, T, NCH, UNIT>), tg, dim3(kPaintThreads), 0, st, g, s, w, p->bin_offs,    \
-                     p->bin_list, mesh, halo, wglob);                                                      \
+                     p->bin_list, mesh, halo, wglob, static_cast<const float4*>(p->bin_rec));              \
   timing_end(p, PM_K_PAINT_TILES, st, tile_bytes);                                                         \
   timing_begin(p, PM_K_HALO, st);                                                                          \
   if (in.defer_z) hipLaunchKernelGGL((k_halo_add<T, NCH, true>), tg, block, 0, st, g, mesh, halo);         \

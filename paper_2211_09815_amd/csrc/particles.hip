@@ -8,7 +8,9 @@
 // particles from LDS, so the random part of the access pattern never reaches
 // HBM or L2.  Positions are formed in FP64 from the exact lattice coordinate
 // and the stored displacement, then the in-cell fraction is rounded to the
-// mesh type.  Reductions that feed gradients (pi.a, (delta - target)^2) are
+// mesh type; with FP32 meshes the binning has stored exactly those values per
+// particle (base node and fractions, 16 bytes), and the gather reads that
+// record instead of the displacement.  Reductions that feed gradients (pi.a, (delta - target)^2) are
 // written as per-workgroup FP64 partial sums and combined in a fixed order,
 // so they are deterministic.
 #include "tiles.h"
@@ -37,15 +39,16 @@ struct GatherP {
   const unsigned* offs;
   const unsigned* list;
   double* partials;  // per tile, slot 1: sum cot.a
+  const float4* rec; // FP32 meshes: the binning's CIC records
 };
 
 constexpr int kGatherThreads = 512;  // threads per tile workgroup of the gather
 
 template <typename S, typename T, int MODE, int NF>
 __global__ __launch_bounds__(kGatherThreads) void k_gather_tiles(GatherP<S, T> a) {
-  // particles per thread per chunk: one for the adjoint kick, whose register
+  // particles per thread per chunk: one for the adjoint modes, whose register
   // use would otherwise hold the CU to two workgroups
-  constexpr int P = (MODE == GATHER_KICK_ADJ ? 512 : 1024) / kGatherThreads;
+  constexpr int P = (MODE == GATHER_KICK_ADJ || MODE == GATHER_VJP ? 512 : 1024) / kGatherThreads;
   constexpr unsigned CHUNK = P * kGatherThreads;
   constexpr unsigned NONE = 0xffffffffu;
   constexpr bool KICKF = MODE == GATHER_KICK_FWD, KICKA = MODE == GATHER_KICK_ADJ;
@@ -62,8 +65,10 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_tiles(GatherP<S, T> a
   double ca = 0.0;
   if (fin > beg) {
     // particle chunk: all loads issued before any is used
+    constexpr bool REC = kUseRec<T>;
     unsigned nn[P];
-    S xs[P][3], ps[P][KICKF || KICKA ? 3 : 1];
+    S xs[P][REC ? 1 : 3], ps[P][KICKF || KICKA ? 3 : 1];
+    float4 rs[P];
     T cs[P][COT ? 3 : 1], xis[P][KICKA ? 3 : 1];
     auto load = [&](unsigned c0) {
 #pragma unroll
@@ -75,9 +80,10 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_tiles(GatherP<S, T> a
       for (int k = 0; k < P; ++k) {
         if (nn[k] == NONE) continue;
         const int64_t n = nn[k];
+        if constexpr (REC) rs[k] = a.rec[n];
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-          xs[k][ax] = a.s[ax * g.N + n];
+          if (!REC) xs[k][ax] = a.s[ax * g.N + n];
           if (KICKF || KICKA) ps[k][ax] = a.p[ax * g.N + n];
           if (COT) cs[k][ax] = a.cot[ax * g.N + n];
           if (KICKA) xis[k][ax] = a.xi[ax * g.N + n];
@@ -105,14 +111,22 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_tiles(GatherP<S, T> a
       for (int k = 0; k < P; ++k) {
         if (nn[k] == NONE) continue;
         const int64_t n = nn[k];
-        double q[3];
-        lattice_pos(g, n, q);
-        const double x0 = q[0] + double(xs[k][0]), x1 = q[1] + double(xs[k][1]), x2 = q[2] + double(xs[k][2]);
-        const double f0 = floor(x0), f1 = floor(x1), f2 = floor(x2);
-        const int l0 = int(int64_t(f0) & (g.n0 - 1)) - o0;
-        const int l1 = int(int64_t(f1) & (g.n1 - 1)) - o1;
-        const int l2 = int(int64_t(f2) & (g.n2 - 1)) - o2;
-        const T d0 = T(x0 - f0), d1 = T(x1 - f1), d2 = T(x2 - f2);
+        int l0, l1, l2;
+        T d0, d1, d2;
+        if constexpr (REC) {
+          unpack_rec(rs[k], o0, o1, o2, l0, l1, l2, d0, d1, d2);
+        } else {
+          double q[3];
+          lattice_pos(g, n, q);
+          const double x0 = q[0] + double(xs[k][0]), x1 = q[1] + double(xs[k][1]), x2 = q[2] + double(xs[k][2]);
+          const double f0 = floor(x0), f1 = floor(x1), f2 = floor(x2);
+          l0 = int(int64_t(f0) & (g.n0 - 1)) - o0;
+          l1 = int(int64_t(f1) & (g.n1 - 1)) - o1;
+          l2 = int(int64_t(f2) & (g.n2 - 1)) - o2;
+          d0 = T(x0 - f0);
+          d1 = T(x1 - f1);
+          d2 = T(x2 - f2);
+        }
         const T wx[2] = {T(1) - d0, d0}, wy[2] = {T(1) - d1, d1}, wz[2] = {T(1) - d2, d2};
         T v[NF];
 #pragma unroll
@@ -261,6 +275,7 @@ int gather_typed(Plan* p, GatherMode mode, const GatherArgs& in, hipStream_t st)
   a.offs = p->bin_offs;
   a.list = p->bin_list;
   a.partials = p->tile_partials;
+  a.rec = static_cast<const float4*>(p->bin_rec);
   const dim3 grid(unsigned(p->ntiles)), block(kGatherThreads);
   timing_begin(p, PM_K_GATHER, st);
 #define PM_GATHER(MODE, NF) hipLaunchKernelGGL((k_gather_tiles<S, T, MODE, NF>), grid, block, 0, st, a)

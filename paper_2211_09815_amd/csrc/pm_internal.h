@@ -88,6 +88,7 @@ struct Plan {
   unsigned* bin_offs = nullptr;     // [ntiles + 1]
   unsigned* bin_bsum = nullptr;     // [4 * kThreads]
   void* bin_keys = nullptr;         // [N] (tile, rank)
+  void* bin_rec = nullptr;          // [N] float4 CIC records (FP32 meshes), else null
   unsigned* bin_list = nullptr;     // [N]
   void* bin_halo = nullptr;         // [4][ntiles][halo_cells] mesh dtype
   double* tile_partials = nullptr;  // [ntiles][4] per-tile reduction slots

@@ -78,6 +78,29 @@ __device__ __forceinline__ void lattice_pos(const TileGeo& g, int64_t n, double 
 // the high word of r m is exact in that range
 __device__ __forceinline__ int fdiv_small(int r, unsigned m) { return int(__umulhi(unsigned(r), m)); }
 
+// Per-particle CIC record, written by the binning for FP32 meshes and read
+// by the paint and the gather instead of the displacement: the base node
+// (floor of the FP64 position, wrapped; 10 bits per axis, meshes up to 1024)
+// and the in-cell fractions rounded to float, i.e. exactly the values those
+// kernels would form from the FP64 position themselves.
+template <typename T> constexpr bool kUseRec = sizeof(T) == 4;
+
+__device__ __forceinline__ unsigned pack_cell(int b0, int b1, int b2) {
+  return (unsigned(b0) << 20) | (unsigned(b1) << 10) | unsigned(b2);
+}
+
+template <typename T>
+__device__ __forceinline__ void unpack_rec(const float4 r, int o0, int o1, int o2, int& l0, int& l1, int& l2, T& d0,
+                                           T& d1, T& d2) {
+  const unsigned c = __float_as_uint(r.x);
+  l0 = int(c >> 20) - o0;
+  l1 = int((c >> 10) & 1023u) - o1;
+  l2 = int(c & 1023u) - o2;
+  d0 = T(r.y);
+  d1 = T(r.z);
+  d2 = T(r.w);
+}
+
 // tile coordinates and origin cell of a tile index
 __device__ __forceinline__ void tile_origin(const TileGeo& g, int64_t tile, int& o0, int& o1, int& o2) {
   const int t2 = int(tile % g.ntz);
