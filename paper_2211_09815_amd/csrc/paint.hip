@@ -249,11 +249,24 @@ __global__ __launch_bounds__(kThreads) void k_scan_add(unsigned* offs, const uns
 
 __global__ __launch_bounds__(kThreads) void k_scatter(const uint2* keys, const unsigned* offs, unsigned* list,
                                                       int64_t N) {
+  constexpr int U = 4;   // keys per thread per round, all loads issued first
   int64_t start, end;
   chunk_of(N, start, end);
-  for (int64_t n = start + threadIdx.x; n < end; n += kThreads) {
-    const uint2 k = keys[n];
-    list[offs[k.x] + k.y] = unsigned(n);
+  for (int64_t base = start + threadIdx.x; base < end; base += U * kThreads) {
+    uint2 k[U];
+    unsigned o[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t n = base + u * kThreads;
+      k[u] = n < end ? keys[n] : make_uint2(0u, 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) o[u] = base + u * kThreads < end ? offs[k[u].x] : 0u;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t n = base + u * kThreads;
+      if (n < end) list[o[u] + k[u].y] = unsigned(n);
+    }
   }
 }
 
