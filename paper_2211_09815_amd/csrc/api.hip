@@ -293,12 +293,16 @@ size_t pm_workspace_bytes(const pm_config* cfg) {
   std::string why;
   if (validate_cfg(cfg, why) != PM_OK) return 0;
   size_t total = sizes_of(cfg).total();
-  // 2LPT lattice scratch (16 real fields, 3 half spectra), allocated by the
-  // first pm_lpt / pm_lpt_vjp call on a cubic lattice
+  // 2LPT lattice scratch (16 real fields, 3 half spectra; 12 real fields when
+  // the lattice has the mesh's shape and shares the plan's meshes and
+  // spectra), allocated by the first pm_lpt / pm_lpt_vjp call on a cubic
+  // lattice
   const int64_t n = cfg->ptcl[0];
   if (cfg->ptcl[1] == n && cfg->ptcl[2] == n) {
     const size_t rb = cfg->mesh_dtype == PM_F64 ? 8 : 4;
-    total += size_t(16) * n * n * n * rb + size_t(3) * n * n * (n / 2 + 1) * 2 * rb;
+    const bool shared = cfg->mesh[0] == n && cfg->mesh[1] == n && cfg->mesh[2] == n;
+    total += shared ? size_t(12) * n * n * n * rb
+                    : size_t(16) * n * n * n * rb + size_t(3) * n * n * (n / 2 + 1) * 2 * rb;
   }
   return total;
 }

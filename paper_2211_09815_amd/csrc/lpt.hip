@@ -227,18 +227,26 @@ int check_lattice(Plan* p) {
   return PM_OK;
 }
 
-// lattice scratch: 16 real fields and 3 half spectra
+// lattice scratch: 16 real fields and 3 half spectra.  Kernels take the
+// groups s1 (fields 0..2), H (3..8), s2 (10..12) and s1bar (13..15) as one
+// base pointer each, so every group must be contiguous.  When the lattice has
+// the mesh's shape, the plan's 4 meshes and first 3 spectra (idle outside the
+// steps; nothing of the 2LPT calls outlives them) hold s1 and S (field 9) and
+// the spectra, and only 12 real fields (H, s2, s1bar) are allocated.
+bool lattice_is_mesh(const Plan* p) { return p->np[0] == p->n[0] && p->np[1] == p->n[1] && p->np[2] == p->n[2]; }
+
 int ensure_lattice(Plan* p) {
   if (p->lpt_ready) return PM_OK;
   const int64_t n = p->np[0];
   const int64_t N = n * n * n;
   const int64_t ns = n * n * (n / 2 + 1);
   const size_t rb = p->real_bytes;
-  if (hipMalloc(&p->lreal[0], size_t(16) * N * rb) != hipSuccess) {
+  const bool shared = lattice_is_mesh(p);
+  if (hipMalloc(&p->lreal[0], size_t(shared ? 12 : 16) * N * rb) != hipSuccess) {
     (void)hipGetLastError();
     return set_error(p, PM_ENOMEM, "could not allocate 2LPT lattice fields");
   }
-  if (hipMalloc(&p->lspec[0], size_t(3) * ns * 2 * rb) != hipSuccess) {
+  if (!shared && hipMalloc(&p->lspec[0], size_t(3) * ns * 2 * rb) != hipSuccess) {
     (void)hipGetLastError();
     (void)hipFree(p->lreal[0]);
     p->lreal[0] = nullptr;
@@ -252,8 +260,18 @@ template <typename T>
 struct Lat {
   int n;
   int64_t N, ns;
-  T* real(Plan* p, int i) const { return static_cast<T*>(p->lreal[0]) + int64_t(i) * N; }
-  Cx<T>* spec(Plan* p, int i) const { return static_cast<Cx<T>*>(p->lspec[0]) + int64_t(i) * ns; }
+  T* real(Plan* p, int i) const {
+    if (lattice_is_mesh(p)) {
+      if (i < 3) return static_cast<T*>(p->mesh[i]);
+      if (i == 9) return static_cast<T*>(p->mesh[3]);
+      return static_cast<T*>(p->lreal[0]) + int64_t(i < 9 ? i - 3 : i - 4) * N;
+    }
+    return static_cast<T*>(p->lreal[0]) + int64_t(i) * N;
+  }
+  Cx<T>* spec(Plan* p, int i) const {
+    if (lattice_is_mesh(p)) return static_cast<Cx<T>*>(p->spec[i]);
+    return static_cast<Cx<T>*>(p->lspec[0]) + int64_t(i) * ns;
+  }
 };
 
 AmpP amp_params(const Plan* p, const pm_cosmo* c, const pm_ic_coef* ic) {

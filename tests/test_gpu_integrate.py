@@ -98,9 +98,10 @@ def test_adjoint_steps_vs_oracle(n, nm, mdt, sdt, tol):
 
 
 @pytest.mark.parametrize("mdt,sdt,tol", [(torch.float64, torch.float64, 1e-11), (torch.float32, torch.float64, 1e-5)])
-def test_lpt_vs_oracle(mdt, sdt, tol):
-    announce("lpt %s/%s" % (mdt, sdt))
-    api, cfg, omega, plan = _setup(32, 64, 128.0, 1, mdt=mdt, sdt=sdt)
+@pytest.mark.parametrize("n,nm", [(32, 64), (32, 32)])   # the second shares the plan's meshes as scratch
+def test_lpt_vs_oracle(n, nm, mdt, sdt, tol):
+    announce("lpt %d^3/%d^3 %s/%s" % (n, nm, mdt, sdt))
+    api, cfg, omega, plan = _setup(n, nm, 4.0 * n, 1, mdt=mdt, sdt=sdt)
     cos = api.Cosmology()
     _, ic = api.tables(cos, cfg.a_grid())
     st = plan.new_state(torch.zeros((3, cfg.n_particles), dtype=sdt, device="cuda"),
@@ -111,10 +112,11 @@ def test_lpt_vs_oracle(mdt, sdt, tol):
     assert rel_l2(aos(host(st["p"])), p_ref) < tol
 
 
+@pytest.mark.parametrize("n,nm", [(16, 32), (16, 16)])   # the second shares the plan's meshes as scratch
 @pytest.mark.parametrize("mdt,tol", [(torch.float64, 1e-10), (torch.float32, 2e-5)])
-def test_lpt_vjp_vs_oracle(mdt, tol):
-    announce("lpt_vjp %s" % mdt)
-    api, cfg, omega, plan = _setup(16, 32, 64.0, 1, mdt=mdt)
+def test_lpt_vjp_vs_oracle(n, nm, mdt, tol):
+    announce("lpt_vjp %d^3/%d^3 %s" % (n, nm, mdt))
+    api, cfg, omega, plan = _setup(n, nm, 4.0 * n, 1, mdt=mdt)
     cos = api.Cosmology()
     _, ic = api.tables(cos, cfg.a_grid())
     xb = inputs.normal((cfg.n_particles, 3), 62)
