@@ -571,7 +571,7 @@ int bin_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
     // s (or s_set) read (+ p read, s write; adjoint: xi read, pi read/write),
     // key write; a pending kick reads a (and alpha) and writes p (and xi)
     const double N = double(g.N), sb = sizeof(S), mb = sizeof(T);
-    double bytes = 3 * N * sb + 8 * N;
+    double bytes = 3 * N * sb + 8 * N + (b.rec ? 16 * N : 0.0);   // + the CIC records
     if (mode == DRIFT_FWD) bytes += 6 * N * sb;
     if (adj) bytes += 6 * N * sb + 9 * N * mb;
     if (kick) bytes += 3 * N * (mb + sb) + (adj ? 6 * N * mb : 0.0);
@@ -614,8 +614,10 @@ int paint_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
   const double N = double(g.N), sb = sizeof(S), mb = sizeof(T);
   const double core_bytes = double(nch) * double(p->ncell) * mb;
   const double halo_bytes = double(nch) * double(nt) * g.hc * mb;
-  // tiles: list + s + weights read, core and halo faces written
-  const double tile_bytes = 4 * N + 3 * N * sb + double(nch - in.unit) * N * mb + core_bytes + halo_bytes;
+  // tiles: list + positions (the CIC records with FP32 meshes, else s) +
+  // weights read, core and halo faces written
+  const double pos_bytes = p->bin_rec ? 16 * N : 3 * N * sb;
+  const double tile_bytes = 4 * N + pos_bytes + double(nch - in.unit) * N * mb + core_bytes + halo_bytes;
   // halo: halo faces read (but the z faces when deferred), the lower-face
   // core cells read and written
   const int zc = g.tx * g.ty;

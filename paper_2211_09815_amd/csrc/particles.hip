@@ -295,9 +295,10 @@ int gather_typed(Plan* p, GatherMode mode, const GatherArgs& in, hipStream_t st)
   }
 #undef PM_GATHER
   {
-    // positions and the gathered mesh fields once, plus the per-mode particle traffic
+    // list, positions (the CIC records with FP32 meshes, else s) and the
+    // gathered mesh fields once, plus the per-mode particle traffic
     const double N = double(p->nptcl), sb = sizeof(S), mb = sizeof(T);
-    double bytes = 3 * N * sb + double(in.nf) * double(p->ncell) * mb;
+    double bytes = 4 * N + (p->bin_rec ? 16 * N : 3 * N * sb) + double(in.nf) * double(p->ncell) * mb;
     if (mode == GATHER_PLAIN) bytes += double(in.nf) * N * mb;
     if (mode == GATHER_KICK_FWD) bytes += 6 * N * sb + (in.acc ? 3 * N * mb : 0.0);
     if (mode == GATHER_VJP) bytes += 6 * N * mb + (in.acc ? 3 * N * mb : 0.0);
