@@ -245,7 +245,7 @@ def study_precision(args):
 
 
 def study_checkpoints(args):
-    """Piecewise reverse from forward checkpoints (Sec. 4.1): for FP32 state
+    """Piecewise reverse from forward checkpoints (Sec. 3.5): for FP32 state
     and for FP32 mesh + FP64 state, the pass time, the checkpoint memory, the
     reversibility of the recovered initial state and the gradient error
     against the all-FP64 pass, with 0, 7, 21 and 63 evenly spaced

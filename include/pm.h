@@ -3,10 +3,10 @@
  *
  * Li et al., "Differentiable Cosmological Simulation with the Adjoint Method"
  * (arXiv:2211.09815): the particle-mesh force (Sec. 2.2), its vector-Jacobian
- * product (Sec. 4.2), the FastPM kick-drift-kick leapfrog (Sec. 2.3,
- * eq. KDFK) and its adjoint with reverse-time integration (Sec. 4.2,
+ * product (Sec. 3.6), the FastPM kick-drift-kick leapfrog (Sec. 2.3,
+ * eq. KDFK) and its adjoint with reverse-time integration (Sec. 3.6,
  * eqs. KDFKO_adj and KDFKO_grad), the 2LPT initial conditions (Sec. 2.1,
- * eq. lpt) and the final-density objective of Sec. 5.2.
+ * eq. lpt) and the final-density objective of Sec. 4.2.
  *
  * Conventions shared by every call
  * --------------------------------
@@ -137,7 +137,7 @@ int pm_readout(pm_plan plan, const void* disp, const void* mesh, int nch, void* 
  * Poisson gradient, 3 C2R, readout.  acc: [3][N_p] mesh dtype. */
 int pm_force(pm_plan plan, const void* disp, double coef, void* acc, hipStream_t stream);
 
-/* ---- a8: force VJP (Sec. 4.2; scatter/gather VJPs) ---------------------- */
+/* ---- a8: force VJP (Sec. 3.6; scatter/gather VJPs) ---------------------- */
 /* For cotangent acc_bar [3][N_p] of the accelerations:
  *   disp_bar[k][n] = sum_j acc_bar[j][n] d a_j(n) / d x_k(n') summed over n'
  *                    (the VJP with respect to all particle positions),
@@ -217,7 +217,7 @@ int pm_run_fwd(pm_plan plan, pm_state* st, const pm_step_coef* coefs, int n, dou
 int pm_run_adj(pm_plan plan, pm_state* st, pm_adj* adj, const pm_step_coef* coefs, int n,
                double coef, double* theta_bar, hipStream_t stream);
 
-/* ---- piecewise reverse from forward checkpoints (Sec. 4.1) ---------------- */
+/* ---- piecewise reverse from forward checkpoints (Sec. 3.5) ---------------- */
 /* Where the reverse-time integration drifts too far from the forward
  * trajectory (long or strongly nonlinear runs, FP32 state), the backward
  * evolution can be resumed piecewise from states saved during the forward
@@ -249,7 +249,7 @@ int pm_run_fwd_ckpt(pm_plan plan, pm_state* st, const pm_step_coef* coefs, int n
 int pm_run_adj_ckpt(pm_plan plan, pm_state* st, pm_adj* adj, const pm_step_coef* coefs, int n,
                     double coef, const pm_checkpoints* ck, double* theta_bar, hipStream_t stream);
 
-/* ---- a11: objective and its VJP (Sec. 5.2) ------------------------------- */
+/* ---- a11: objective and its VJP (Sec. 4.2) ------------------------------- */
 /* delta = paint(x) N_c/N_p - 1; *J = (1/N_c) sum (delta - target)^2 (device
  * double, overwritten); disp_bar[k][n] = sum_cell dW/dx_k (2 (delta -
  * target)/N_p) (mesh dtype, overwritten; may be NULL). target: [N_c] mesh

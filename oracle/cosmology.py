@@ -168,7 +168,7 @@ def step_coefficients_with_derivative(a_grid, om):
 
 
 def linear_a_grid(a_start, a_end, n):
-    """Time steps linearly spaced in a (Sec. 3)."""
+    """Time steps linearly spaced in a (Sec. 4)."""
     return np.linspace(a_start, a_end, n + 1)
 
 

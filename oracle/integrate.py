@@ -8,14 +8,14 @@ Paper passages followed:
         a_i = F(x_i),                          p_i = p_{i-1/2} + a_i Kb_i,
     with a_0 = F(x_0) before the first step.  Kicks are applied separately
     (not merged) so that each line of the scheme is visible.
-  * eq. explicit_adj / explicit_grad (Sec. 4.1, discretize-then-optimize):
+  * eq. explicit_adj / explicit_grad (Sec. 3.5, discretize-then-optimize):
     the discrete adjoint along the stored forward trajectory is plain reverse
     accumulation of the chain rule through every line of eq. KDFK.
-  * eq. KDFKO_adj and KDFKO_grad (Sec. 4.2): the adjoint KDK stepping from t_i
+  * eq. KDFKO_adj and KDFKO_grad (Sec. 3.6): the adjoint KDK stepping from t_i
     to t_{i-1}, which re-integrates (x, p) backward together with (xi, pi) and
     caches alpha = pi . da/dx and zeta = pi . da/dtheta; the objective gradient
     with respect to theta accumulates the kick and drift factor derivatives.
-  * Sec. 4.1 (end): when the backward evolution drifts from the forward one,
+  * Sec. 3.5 (end): when the backward evolution drifts from the forward one,
     it can be resumed piecewise from states saved during the forward pass.
     Checkpoint j holds s_j and p_{j-1/2}, the values the reverse step j starts
     from; the reverse pass takes s_j from it when its drift reaches t_j and
@@ -78,7 +78,7 @@ def forward(q, s0, p0, coefs, F, store=True, checkpoints=None):
 
 def adjoint_stored(traj, coefs, dcoefs, xbar_n, pbar_n, F):
     """Reverse accumulation of the chain rule through eq. KDFK along the stored
-    trajectory (the 'AD' gradient of Sec. 5.2).
+    trajectory (the 'AD' gradient of Sec. 4.2).
 
     Returns (xi_0, pi_0, dJ/dOmega_m from the steps)."""
     xi = np.array(xbar_n, dtype=np.float64)

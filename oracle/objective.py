@@ -4,7 +4,7 @@ FP64 reference.
 Test infrastructure only (see oracle/__init__.py).
 
 Paper passages followed: eq. O (objective on the observed state) and the
-gradient test of Sec. 5.2, which uses the mean squared error between two
+gradient test of Sec. 4.2, which uses the mean squared error between two
 final CIC density fields on the simulation mesh at a = 1, one of them held
 fixed as the target.
 

@@ -10,7 +10,7 @@ Paper passages followed (Sec. 2.2, "Force Evaluation"):
     -grad phi~ is -i k phi~(k); one forward and three inverse FFTs.
   * the accelerations are gathered from the mesh with the same weights as the
     paint.
-  * Sec. 4.2 (application to simulation): the force VJPs alpha = pi . da/dx and
+  * Sec. 3.6 (application to simulation): the force VJPs alpha = pi . da/dx and
     zeta = pi . da/dtheta entering eq. KDFKO_adj; the scatter/gather VJPs are
     written out by hand (no automatic differentiation).
 

@@ -105,9 +105,9 @@ def value_and_grad(omega, cfg, target, mode="stored", final_state_out=None, chec
     """J and (dJ/domega, dJ/dOmega_m, dJ/dsigma8).
 
     mode = "stored": discrete adjoint along the stored trajectory (plain chain
-    rule, Sec. 4.1); mode = "reverse": adjoint with reverse-time integration
+    rule, Sec. 3.5); mode = "reverse": adjoint with reverse-time integration
     (eq. KDFKO_adj), resumed from forward checkpoints at `checkpoint_steps`
-    (Sec. 4.1) if any.  If `final_state_out` is a dict, the final forward
+    (Sec. 3.5) if any.  If `final_state_out` is a dict, the final forward
     state is stored in it as "s" and "p" ((N, 3) arrays)."""
     q = lattice(cfg)
     s0, p0 = initial_state(omega, cfg)

@@ -1,5 +1,5 @@
 // CIC paint (Sec. 2.2, eq. cic) with the optional fused drift of the KDK step
-// (Sec. 2.3, eq. KDFK) or of the adjoint step (Sec. 4.2, eq. KDFKO_adj).
+// (Sec. 2.3, eq. KDFK) or of the adjoint step (Sec. 3.6, eq. KDFKO_adj).
 //
 // Floating-point atomics to HBM are resolved far from the compute units on
 // this multi-die GPU, so the paint never issues them on the mesh.  Instead

@@ -1,6 +1,6 @@
 // Particle kernels: CIC gather with fused kick (Sec. 2.2 and eq. KDFK), the
-// force-VJP gather (Sec. 4.2, eq. KDFKO_adj) and the density-MSE mesh kernel
-// (Sec. 5.2).  The paint and the particle binning live in paint.hip.
+// force-VJP gather (Sec. 3.6, eq. KDFKO_adj) and the density-MSE mesh kernel
+// (Sec. 4.2).  The paint and the particle binning live in paint.hip.
 //
 // The gather reuses the paint's tile binning: one workgroup per mesh tile
 // loads the tile's box of (tx+1)(ty+1)(tz+1) cells of every field into LDS

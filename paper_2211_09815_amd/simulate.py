@@ -25,7 +25,7 @@ class SimConfig:
     state_dtype: torch.dtype = torch.float64
     lattice_offset: float = 0.0
     # steps j (1..n_steps) whose forward state (s_j, p_{j-1/2}) is saved for
-    # the piecewise reverse pass (Sec. 4.1); empty: plain reverse integration
+    # the piecewise reverse pass (Sec. 3.5); empty: plain reverse integration
     checkpoint_steps: tuple = ()
 
     @property
@@ -33,7 +33,7 @@ class SimConfig:
         return self.n_ptcl ** 3
 
     def a_grid(self):
-        """Steps linearly spaced in a (Sec. 3)."""
+        """Steps linearly spaced in a (Sec. 4)."""
         return np.linspace(self.a_start, self.a_end, self.n_steps + 1)
 
 

@@ -263,7 +263,7 @@ def test_native_loops_match_step_calls(mdt, sdt):
     np.testing.assert_allclose(res[0][-1], res[1][-1], rtol=1e-12)
 
 
-# ---- piecewise reverse from forward checkpoints (Sec. 4.1) --------------------
+# ---- piecewise reverse from forward checkpoints (Sec. 3.5) --------------------
 
 def test_piecewise_reverse_fp64_vs_oracle():
     # FP64 GPU pass resumed from checkpoints at steps 2, 5, 9, 10 against the

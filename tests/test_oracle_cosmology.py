@@ -63,7 +63,7 @@ def test_fastpm_factors_eds():
 
 
 def test_drift_kick_antisymmetry():
-    # D(tc, ta, tb) = -D(tc, tb, ta), same for K (Sec. 4.2)
+    # D(tc, ta, tb) = -D(tc, tb, ta), same for K (Sec. 3.6)
     for (ac, aa, ab) in [(0.3, 0.2, 0.4), (0.75, 0.5, 1.0)]:
         assert C.drift_factor(ac, aa, ab, 0.3) == pytest.approx(-C.drift_factor(ac, ab, aa, 0.3), rel=1e-14)
         assert C.kick_factor(ac, aa, ab, 0.3) == pytest.approx(-C.kick_factor(ac, ab, aa, 0.3), rel=1e-14)
