@@ -297,6 +297,89 @@ int pm_lpt_vjp(pm_plan plan, const void* omega, const pm_cosmo* cosmo,
                const pm_ic_coef* ic, const pm_adj* adj, void* omega_bar,
                double* theta_bar, hipStream_t stream);
 
+/* ---- next 3: light-cone observation and its adjoint (Sec. 2.4, Sec. 3.4) -- */
+/* Every particle is observed once, when it crosses the past light cone of an
+ * observer at a = 1.  On step i (from a_{i-1} to a_i) its position is the
+ * cubic Hermite spline in u = (a - a_{i-1}) / (a_i - a_{i-1}) through x and
+ * dx/da = p w(a), w = 1 / (a^3 E(a)) (dx/dt = p / a^2, Sec. 2.3), at both
+ * ends (x = q + s unwrapped, p the integer-time momenta); the light front
+ * chi(a) = (c/H0) int_a^1 da' / (a'^2 E(a')) (comoving distance, in cells)
+ * is the cubic Hermite spline through chi and dchi/da at both ends.  With
+ * f(u) = |x(u) - observer| - chi(u), the particle is observed in step i when
+ * f(0) < 0 <= f(1), at the root u* of f (safeguarded Newton); it records
+ * x^ = x(u*), p^ = a^3 E(a^) dx/da(u*) and a^ = a_{i-1} + u* (a_i - a_{i-1}).
+ * One copy of the periodic box is observed (no images). */
+
+/* Light-front and velocity factors at one scale factor, with d/dOmega_m. */
+typedef struct {
+    double a;
+    double chi;       /* cells */
+    double dchi;      /* d chi / d a */
+    double w;         /* 1 / (a^3 E(a)) */
+    double chi_om, dchi_om, w_om;
+} pm_lc_coef;
+
+/* One observation step: the factors at a_{i-1} (c0) and a_i (c1). */
+typedef struct {
+    pm_lc_coef c0, c1;
+    double omega_m;
+    double observer[3];   /* cells, same frame as q + s */
+    int32_t step;         /* i >= 1, written to obs_step of observed particles */
+} pm_lc_step;
+
+/* Host-only, FP64: out[k] for a_grid[0..n] (n + 1 entries), for a mesh cell
+ * of `cell` Mpc/h (c/H0 = 2997.92458 Mpc/h).  chi by 8-point Gauss-Legendre
+ * panels in sqrt(a'), Omega_m derivatives by dual numbers.  Returns
+ * PM_EINVAL for NULL arguments, a outside (0, 1] or cell <= 0. */
+int pm_lightcone_tables(const pm_cosmo* cosmo, const double* a_grid, int n, double cell,
+                        pm_lc_coef* out);
+
+/* Observation of step st->step.  s0, p0, s1, p1: [3][N_p] state dtype, the
+ * displacements and integer-time momenta at a_{i-1} and a_i.  For every
+ * particle observed in this step: obs[0..2][n] = x^, obs[3..5][n] = p^,
+ * obs[6][n] = a^ ([7][N_p] state dtype) and obs_step[n] = st->step (int32
+ * [N_p]); other particles' entries are left as they are.  *count (device
+ * double) += the number observed.  Errors: PM_EINVAL for NULL buffers, a
+ * step < 1 or c0.a >= c1.a. */
+int pm_lightcone(pm_plan plan, const pm_lc_step* st, const void* s0, const void* p0,
+                 const void* s1, const void* p1, void* obs, int32_t* obs_step,
+                 double* count, hipStream_t stream);
+
+/* Transpose of pm_lightcone for the particles with obs_step[n] == st->step,
+ * given the cotangent obs_bar ([7][N_p] mesh dtype) of (x^, p^, a^): adds
+ * dJ/dx and dJ/dp at a_{i-1} to x0_bar, p0_bar and at a_i to x1_bar, p1_bar
+ * ([3][N_p] mesh dtype each, +=; any may be NULL to skip it) and the
+ * Omega_m derivative through chi, w and E to theta_bar[0] (device double,
+ * +=).  The root is solved again on the given states, so they must be the
+ * ones observed (or their reverse-time reconstruction).  The dependence of
+ * u* on the states and on Omega_m is included (implicit function theorem). */
+int pm_lightcone_vjp(pm_plan plan, const pm_lc_step* st, const void* s0, const void* p0,
+                     const void* s1, const void* p1, const int32_t* obs_step,
+                     const void* obs_bar, void* x0_bar, void* p0_bar, void* x1_bar,
+                     void* p1_bar, double* theta_bar, hipStream_t stream);
+
+/* The adjoint's bump at integer time k (Sec. 3.4; eq. explicit_adj adds
+ * dJ/dz_k there).  p_k = p_{k-1/2} + a_k Kb_k, so a cotangent p_bar of p_k
+ * also reaches a_k:
+ *   xi += x_bar + Kb c,  pi += p_bar,
+ *   theta_bar[0] += dKb sum(p_bar . acc) + 1.5 Kb (*coef_bar),
+ * where c and *coef_bar are pm_force_vjp's disp_bar and coef_bar for the
+ * cotangent p_bar at x_k, and acc = a_k.  c, acc and coef_bar may be NULL
+ * (Kb = 0: p_0, or a kick the caller's own VJP already covers).  xi, pi,
+ * x_bar, p_bar, c, acc: [3][N_p] mesh dtype. */
+int pm_adj_bump(pm_plan plan, void* xi, void* pi, const void* x_bar, const void* p_bar,
+                const void* c, double Kb, double dKb, const void* acc,
+                const double* coef_bar, double* theta_bar, hipStream_t stream);
+
+/* The kick and drift operators of eq. KDFK on their own (out may alias the
+ * input): p_out = p + acc K (p, p_out state dtype, acc mesh dtype) and
+ * s_out = s + p D (state dtype).  The light-cone driver uses them for the
+ * integer-time momenta and the reverse-time reconstruction one step ahead. */
+int pm_kick(pm_plan plan, const void* p, const void* acc, double K, void* p_out,
+            hipStream_t stream);
+int pm_drift(pm_plan plan, const void* s, const void* p, double D, void* s_out,
+             hipStream_t stream);
+
 /* ---- support: health check and timing ------------------------------------ */
 /* Sets *bad (device int) to 1 if any of n values of dtype in `x` is NaN or
  * Inf (else leaves it).  Returns PM_OK; the caller reads *bad after sync. */
@@ -321,6 +404,7 @@ int pm_check_finite(pm_plan plan, const void* x, int64_t n, int dtype, int* bad,
 #define PM_K_SCATTER     7   /* paint: per-tile particle lists               */
 #define PM_K_PAINT_TILES 8   /* paint: LDS tile sums                         */
 #define PM_K_HALO        9   /* paint: halo faces into the mesh              */
+#define PM_K_LIGHTCONE  10   /* light-cone observation, its VJP and bump      */
 int pm_timing_enable(pm_plan plan, unsigned mask);
 int pm_timing_read(pm_plan plan, int kernel, double* total_ms, int64_t* launches, double* total_bytes);
 

@@ -29,16 +29,17 @@ PM_K_GATHER = 6
 PM_K_SCATTER = 7
 PM_K_PAINT_TILES = 8
 PM_K_HALO = 9
+PM_K_LIGHTCONE = 10
 KERNEL_FAMILIES = {
     "bin": PM_K_BIN, "scatter": PM_K_SCATTER, "paint_tiles": PM_K_PAINT_TILES, "halo_add": PM_K_HALO,
     "fft_r2c_z": PM_K_FFT_R2C_Z, "fft_lines": PM_K_FFT_LINES, "fft_poisson": PM_K_FFT_POISSON,
-    "fft_c2r_z": PM_K_FFT_C2R_Z, "gather": PM_K_GATHER,
+    "fft_c2r_z": PM_K_FFT_C2R_Z, "gather": PM_K_GATHER, "lightcone": PM_K_LIGHTCONE,
 }
 # device kernel symbol of each family (for matching profiler output)
 KERNEL_SYMBOLS = {
     "bin": "k_bin", "scatter": "k_scatter", "paint_tiles": "k_paint_tiles", "halo_add": "k_halo_add",
     "fft_r2c_z": "k_fft_r2c_z", "fft_lines": "k_fft_lines", "fft_poisson": "k_fft_x_fused",
-    "fft_c2r_z": "k_fft_c2r_z", "gather": "k_gather_tiles",
+    "fft_c2r_z": "k_fft_c2r_z", "gather": "k_gather_tiles", "lightcone": "k_lightcone",
 }
 
 c_int = ctypes.c_int
@@ -82,6 +83,16 @@ class PmIcCoef(ctypes.Structure):
                 ("dD1", c_dbl), ("dD2", c_dbl), ("dP1", c_dbl), ("dP2", c_dbl), ("dA", c_dbl)]
 
 
+class PmLcCoef(ctypes.Structure):
+    _fields_ = [("a", c_dbl), ("chi", c_dbl), ("dchi", c_dbl), ("w", c_dbl),
+                ("chi_om", c_dbl), ("dchi_om", c_dbl), ("w_om", c_dbl)]
+
+
+class PmLcStep(ctypes.Structure):
+    _fields_ = [("c0", PmLcCoef), ("c1", PmLcCoef), ("omega_m", c_dbl), ("observer", c_dbl * 3),
+                ("step", c_i32)]
+
+
 P = ctypes.POINTER
 _PROTOS = {
     "pm_plan_create": (c_int, [P(PmConfig), P(c_vp)]),
@@ -109,6 +120,13 @@ _PROTOS = {
     "pm_tables": (c_int, [P(PmCosmo), P(c_dbl), c_int, P(PmStepCoef), P(PmIcCoef)]),
     "pm_lpt": (c_int, [c_vp, c_vp, P(PmCosmo), P(PmIcCoef), P(PmState), c_vp]),
     "pm_lpt_vjp": (c_int, [c_vp, c_vp, P(PmCosmo), P(PmIcCoef), P(PmAdj), c_vp, c_vp, c_vp]),
+    "pm_lightcone_tables": (c_int, [P(PmCosmo), P(c_dbl), c_int, c_dbl, P(PmLcCoef)]),
+    "pm_lightcone": (c_int, [c_vp, P(PmLcStep), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "pm_lightcone_vjp": (c_int, [c_vp, P(PmLcStep), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
+                                 c_vp, c_vp]),
+    "pm_adj_bump": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_dbl, c_dbl, c_vp, c_vp, c_vp, c_vp]),
+    "pm_kick": (c_int, [c_vp, c_vp, c_vp, c_dbl, c_vp, c_vp]),
+    "pm_drift": (c_int, [c_vp, c_vp, c_vp, c_dbl, c_vp, c_vp]),
     "pm_check_finite": (c_int, [c_vp, c_vp, c_i64, c_int, c_vp, c_vp]),
     "pm_timing_enable": (c_int, [c_vp, ctypes.c_uint]),
     "pm_timing_read": (c_int, [c_vp, c_int, P(c_dbl), P(c_i64), P(c_dbl)]),

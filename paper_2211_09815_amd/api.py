@@ -10,7 +10,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import PmAdj, PmCheckpoints, PmConfig, PmCosmo, PmIcCoef, PmState, PmStepCoef, check, lib
+from ._lib import (PmAdj, PmCheckpoints, PmConfig, PmCosmo, PmIcCoef, PmLcCoef, PmLcStep, PmState, PmStepCoef,
+                   check, lib)
 
 _TORCH_DT = {_lib.PM_F32: torch.float32, _lib.PM_F64: torch.float64}
 _CPLX_DT = {_lib.PM_F32: torch.complex64, _lib.PM_F64: torch.complex128}
@@ -66,6 +67,22 @@ def tables(cosmo, a_grid):
     arr = np.array([[c.Ka, c.D, c.Kb, c.dKa, c.dD, c.dKb] for c in coefs[:n]], dtype=np.float64).reshape(n, 6)
     icd = {f: getattr(ic, f) for f, _ in PmIcCoef._fields_}
     return arr, icd
+
+
+def lightcone_tables(cosmo, a_grid, cell):
+    """Host FP64 light-front and velocity factors (pm_lightcone_tables) at
+    every a of a_grid for mesh cells of `cell` Mpc/h: a ctypes array of
+    pm_lc_coef."""
+    a = np.ascontiguousarray(np.asarray(a_grid, dtype=np.float64))
+    out = (PmLcCoef * len(a))()
+    check(lib().pm_lightcone_tables(ctypes.byref(cosmo.c_struct()), a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    len(a) - 1, float(cell), out))
+    return out
+
+
+def lc_step(c0, c1, omega_m, observer, step):
+    """pm_lc_step of step `step` from the factors at its two ends."""
+    return PmLcStep(c0, c1, float(omega_m), (ctypes.c_double * 3)(*[float(v) for v in observer]), int(step))
 
 
 def ic_struct(icd):
@@ -312,6 +329,67 @@ class Plan:
             out = torch.empty(self.mesh, dtype=self.mdt, device=self.device)
         self._t(out, self.mdt, self.n_cells, "out")
         self._c(lib().pm_density(self._h, _ptr(disp), _ptr(out), _stream()))
+        return out
+
+    # ---- light cone -----------------------------------------------------------
+    def _state3(self, t, name):
+        return self._t(t, self.sdt, 3 * self.n_particles, name)
+
+    def _mesh3(self, t, name):
+        return self._t(t, self.mdt, 3 * self.n_particles, name) if t is not None else None
+
+    def lightcone(self, step, s0, p0, s1, p1, obs, obs_step, count):
+        """pm_lightcone: record the particles that cross the light front in
+        `step` (a pm_lc_step) into obs [7, N_p] and obs_step [N_p];
+        count (device FP64, one element) += their number."""
+        for t, nm in ((s0, "s0"), (p0, "p0"), (s1, "s1"), (p1, "p1")):
+            self._state3(t, nm)
+        self._t(obs, self.sdt, 7 * self.n_particles, "obs")
+        self._t(obs_step, torch.int32, self.n_particles, "obs_step")
+        self._t(count, torch.float64, 1, "count")
+        self._c(lib().pm_lightcone(self._h, ctypes.byref(step), _ptr(s0), _ptr(p0), _ptr(s1), _ptr(p1), _ptr(obs),
+                                   _ptr(obs_step), _ptr(count), _stream()))
+
+    def lightcone_vjp(self, step, s0, p0, s1, p1, obs_step, obs_bar, x0_bar, p0_bar, x1_bar, p1_bar, theta_bar):
+        """pm_lightcone_vjp: accumulate the cotangents of the two ends of
+        `step` (any of the four outputs may be None) and theta_bar[0]."""
+        for t, nm in ((s0, "s0"), (p0, "p0"), (s1, "s1"), (p1, "p1")):
+            self._state3(t, nm)
+        self._t(obs_step, torch.int32, self.n_particles, "obs_step")
+        self._t(obs_bar, self.mdt, 7 * self.n_particles, "obs_bar")
+        outs = [self._mesh3(t, nm) for t, nm in ((x0_bar, "x0_bar"), (p0_bar, "p0_bar"), (x1_bar, "x1_bar"),
+                                                 (p1_bar, "p1_bar"))]
+        self._t(theta_bar, torch.float64, 2, "theta_bar")
+        self._c(lib().pm_lightcone_vjp(self._h, ctypes.byref(step), _ptr(s0), _ptr(p0), _ptr(s1), _ptr(p1),
+                                       _ptr(obs_step), _ptr(obs_bar), *[_ptr(t) for t in outs], _ptr(theta_bar),
+                                       _stream()))
+
+    def adj_bump(self, xi, pi, x_bar, p_bar, c, Kb, dKb, acc, coef_bar, theta_bar):
+        """pm_adj_bump: xi += x_bar + Kb c, pi += p_bar and the theta_bar terms."""
+        for t, nm in ((xi, "xi"), (pi, "pi"), (x_bar, "x_bar"), (p_bar, "p_bar")):
+            self._mesh3(t, nm)
+        self._mesh3(c, "c")
+        self._mesh3(acc, "acc")
+        if coef_bar is not None:
+            self._t(coef_bar, torch.float64, 1, "coef_bar")
+        self._t(theta_bar, torch.float64, 2, "theta_bar")
+        self._c(lib().pm_adj_bump(self._h, _ptr(xi), _ptr(pi), _ptr(x_bar), _ptr(p_bar), _ptr(c), float(Kb),
+                                  float(dKb), _ptr(acc), _ptr(coef_bar), _ptr(theta_bar), _stream()))
+
+    def kick(self, p, acc, K, out=None):
+        """pm_kick: out = p + acc K (out may be p)."""
+        self._state3(p, "p")
+        self._mesh3(acc, "acc")
+        out = torch.empty_like(p) if out is None else self._state3(out, "p_out")
+        self._c(lib().pm_kick(self._h, _ptr(p), _ptr(acc), float(K), _ptr(out), _stream()))
+        return out
+
+    def drift(self, s, p, D, out=None):
+        """pm_drift: out = s + p D (out may be s)."""
+        self._state3(s, "s")
+        self._state3(p, "p")
+        out = torch.empty_like(s) if out is None else self._state3(out, "s_out")
+        self._c(lib().pm_drift(self._h, _ptr(s), _ptr(p), float(D), _ptr(out), _stream()))
         return out
 
     # ---- initial conditions -------------------------------------------------

@@ -170,3 +170,79 @@ extern "C" int pm_tables(const pm_cosmo* c, const double* a_grid, int n, pm_step
   }
   return PM_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Light-cone factors (Sec. 2.4): comoving distance to the light front
+// chi(a) = (c/H0) int_a^1 da' / (a'^2 E(a')), its a-derivative and the
+// velocity factor w = 1/(a^3 E) of dx/da = p w, with d/dOmega_m by dual
+// numbers.  With a' = y^2 the integrand becomes 2 / (y^3 E(y^2)), which is
+// smooth down to a' -> 0; it is integrated with 8-point Gauss-Legendre on
+// kLcPanels equal panels in y.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr double kCOverH0 = 2997.92458;   // Mpc/h
+constexpr int kGlOrder = 8;
+constexpr int kLcPanels = 256;
+
+// nodes and weights of m-point Gauss-Legendre on [-1, 1]: Newton iteration on
+// the three-term Legendre recurrence from the usual cosine first guesses
+void gauss_legendre(int m, double* x, double* w) {
+  for (int i = 0; i < m; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (m + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p1 = 1.0, p0 = 0.0;
+      for (int j = 1; j <= m; ++j) {
+        const double pm1 = p0;
+        p0 = p1;
+        p1 = ((2.0 * j - 1.0) * z * p0 - (j - 1.0) * pm1) / j;
+      }
+      dp = m * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+Dual light_front_integral(double a, Dual om) {
+  double gx[kGlOrder], gw[kGlOrder];
+  gauss_legendre(kGlOrder, gx, gw);
+  const double y0 = std::sqrt(a);
+  const double h = (1.0 - y0) / kLcPanels;
+  Dual acc = cst<Dual>(0.0);
+  for (int k = 0; k < kLcPanels; ++k) {
+    const double mid = y0 + (k + 0.5) * h;
+    for (int j = 0; j < kGlOrder; ++j) {
+      const double y = mid + 0.5 * h * gx[j];
+      acc = acc + (gw[j] * 0.5 * h) * (2.0 / (y * y * y * hubble_E(y * y, om)));
+    }
+  }
+  return acc;
+}
+
+}  // namespace
+
+extern "C" int pm_lightcone_tables(const pm_cosmo* c, const double* a_grid, int n, double cell, pm_lc_coef* out) {
+  if (!c || !a_grid || !out || n < 0 || !(cell > 0.0))
+    return set_error(nullptr, PM_EINVAL, "pm_lightcone_tables: bad arguments");
+  if (!(c->omega_m > 0.0 && c->omega_m <= 1.0))
+    return set_error(nullptr, PM_EINVAL, "pm_lightcone_tables: Omega_m out of range");
+  for (int k = 0; k <= n; ++k)
+    if (!(a_grid[k] > 0.0 && a_grid[k] <= 1.0))
+      return set_error(nullptr, PM_EINVAL, "pm_lightcone_tables: a must be in (0, 1]");
+  const Dual om{c->omega_m, 1.0};
+  const double kc = kCOverH0 / cell;
+  for (int k = 0; k <= n; ++k) {
+    const double a = a_grid[k];
+    const Dual chi = kc * light_front_integral(a, om);
+    const Dual e = hubble_E(a, om);
+    const Dual dchi = -kc / ((a * a) * e);
+    const Dual w = 1.0 / ((a * a * a) * e);
+    out[k] = pm_lc_coef{a, chi.v, dchi.v, w.v, chi.d, dchi.d, w.d};
+  }
+  return PM_OK;
+}

@@ -45,7 +45,7 @@ template <bool INV, typename C> __device__ __forceinline__ C cmul_mi(C a) {
 // ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
-constexpr int kTimingFamilies = 10;    // PM_K_* ids are 1..9
+constexpr int kTimingFamilies = 11;    // PM_K_* ids are 1..10
 constexpr int kTimingSlots = 1024;     // launches recorded per family between reads
 struct TimingFamily {
   hipEvent_t ev[2 * kTimingSlots] = {};   // created by pm_timing_enable (families 1..9)

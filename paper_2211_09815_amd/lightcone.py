@@ -1,0 +1,162 @@
+"""Light-cone observation during the forward pass, and the gradient of an
+objective on the observables by the adjoint with reverse-time integration
+(Sec. 2.4, Sec. 3.4, eq. explicit_adj).
+
+Every numeric step runs in libpm (api.py); this module only sequences the
+calls and owns the buffers.
+
+Forward: the kicks are not merged, so that the state holds the integer-time
+momenta p_i that the Hermite splines need: pm_step_fwd(i) without a next step
+leaves (s_i, p_i, a_i), pm_lightcone observes step i from the saved (s_{i-1},
+p_{i-1}), and pm_kick applies the first half kick of step i + 1.
+
+Reverse: the objective's cotangent reaches the states (x_k, p_k) of the two
+ends of each particle's crossing step.  A cotangent of p_k also reaches a_k
+(p_k = p_{k-1/2} + a_k Kb_k), and through the force VJP at x_k the position
+adjoint; pm_adj_bump adds both at t_k, right after pm_step_adj(k + 1) has
+brought the reverse integration to t_k.  The observation of step k needs the
+state at t_{k-1} before the reverse integration gets there, so one step ahead
+the driver reconstructs x_{k-1} (pm_drift) and a_{k-1} (pm_force).  Steps in
+which no particle crosses, and the steps next to them, skip all of this.  The
+gradient is the exact gradient of the discrete forward map, up to the
+reversibility of the reconstruction.
+"""
+import numpy as np
+import torch
+
+from . import api
+
+
+class LightCone:
+    """Observer at `observer` (mesh cells, the frame of q + s) of the run of
+    Simulation `sim`."""
+
+    def __init__(self, sim, observer):
+        self.sim = sim
+        self.observer = [float(v) for v in observer]
+        plan = sim.plan
+        dev, n = plan.device, sim.cfg.n_particles
+        sd = lambda: torch.empty((3, n), dtype=plan.sdt, device=dev)   # noqa: E731
+        md = lambda: torch.zeros((3, n), dtype=plan.mdt, device=dev)   # noqa: E731
+        self.obs = torch.zeros((7, n), dtype=plan.sdt, device=dev)
+        self.obs_step = torch.zeros(n, dtype=torch.int32, device=dev)
+        self.counts = torch.zeros(sim.cfg.n_steps + 1, dtype=torch.float64, device=dev)
+        self.x_tmp, self.p_tmp, self.p_int = sd(), sd(), sd()
+        self.xb = [md(), md()]      # position cotangents of z_k (cur) and z_{k-1} (pending)
+        self.pb = [md(), md()]
+        self.a = [md(), md()]       # a_k (cur) and a_{k-1} (ahead)
+        self.c = md()
+        self.cb = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.n_obs = None
+
+    def tables(self, cosmo):
+        coefs, ic = self.sim.tables(cosmo)
+        cell = self.sim.cfg.box / self.sim.cfg.n_mesh
+        return coefs, ic, api.lightcone_tables(cosmo, self.sim.cfg.a_grid(), cell)
+
+    def _step(self, lc, cosmo, i):
+        return api.lc_step(lc[i - 1], lc[i], cosmo.omega_m, self.observer, i)
+
+    def forward(self, omega, cosmo, tables=None):
+        """2LPT, n KDK steps and the observation of every step.  Leaves
+        (s_n, p_n, a_n) in the simulation and (x^, p^, a^) in self.obs;
+        returns the host array of particles observed per step (index 1..n)."""
+        sim, plan = self.sim, self.sim.plan
+        coefs, ic, lc = tables if tables is not None else self.tables(cosmo)
+        n = len(coefs)
+        coef = 1.5 * cosmo.omega_m
+        st = sim.state()
+        plan.lpt(omega, cosmo, ic, st)
+        self.obs.zero_()
+        self.obs_step.zero_()
+        self.counts.zero_()
+        s_prev, p_prev = self.x_tmp, self.p_tmp
+        s_prev.copy_(sim.s)
+        p_prev.copy_(sim.p)
+        plan.fwd_init(st, coefs[0], coef)
+        for i in range(1, n + 1):
+            plan.step_fwd(st, coefs[i - 1], None, coef)
+            plan.lightcone(self._step(lc, cosmo, i), s_prev, p_prev, sim.s, sim.p, self.obs, self.obs_step,
+                           self.counts[i:i + 1])
+            if i < n:
+                s_prev.copy_(sim.s)
+                p_prev.copy_(sim.p)
+                plan.kick(sim.p, sim.acc, coefs[i][0], out=sim.p)
+        self.n_obs = self.counts.cpu().numpy().round().astype(np.int64)
+        return self.n_obs
+
+    def _swap(self):
+        self.xb.reverse()
+        self.pb.reverse()
+        self.xb[1].zero_()
+        self.pb[1].zero_()
+
+    def gradient(self, omega, cosmo, obs_bar, tables=None):
+        """dJ/domega and dJ/d(Omega_m, sigma8) for the cotangent obs_bar
+        ([7, N_p] mesh dtype) of the observed (x^, p^, a^), after forward()
+        with the same arguments.  Returns (g_omega, theta_bar) on the device."""
+        sim, plan = self.sim, self.sim.plan
+        coefs, ic, lc = tables if tables is not None else self.tables(cosmo)
+        n = len(coefs)
+        cnt = np.concatenate([self.n_obs, [0]])        # cnt[n + 1] = 0
+        coef = 1.5 * cosmo.omega_m
+        st, adj = sim.state(), sim.adj()
+        thb = sim.theta_bar.zero_()
+        sim.xi.zero_()
+        sim.pi.zero_()
+        for t in self.xb + self.pb:
+            t.zero_()
+        need = lambda k: cnt[k] > 0 or cnt[k + 1] > 0   # noqa: E731  cotangents on z_k
+        self.a[0].copy_(sim.acc)                         # a_n
+        s, p = sim.s, sim.p
+
+        def ahead(k, p_half):
+            # x_{k-1}, a_{k-1}, p_{k-1} from (s_k, p_{k-1/2})
+            Ka, D = coefs[k - 1][0], coefs[k - 1][1]
+            plan.drift(s, p_half, -D, out=self.x_tmp)
+            plan.force(self.x_tmp, coef, out=self.a[1])
+            plan.kick(p_half, self.a[1], -Ka, out=self.p_tmp)
+
+        # t_n: pm_adj_init's own VJP at x_n already carries Kb_n pi_n
+        init_ahead = cnt[n] > 0 or (n >= 2 and cnt[n - 1] > 0)
+        if init_ahead:
+            plan.kick(p, self.a[0], -coefs[n - 1][2], out=self.p_int)    # p_{n-1/2}
+            ahead(n, self.p_int)
+        if cnt[n] > 0:
+            plan.lightcone_vjp(self._step(lc, cosmo, n), self.x_tmp, self.p_tmp, s, p, self.obs_step, obs_bar,
+                               self.xb[1], self.pb[1], sim.xi, sim.pi, thb)
+        plan.adj_init(st, adj, coefs[n - 1], coef, thb)
+        self._swap()
+        if init_ahead:
+            self.a.reverse()
+        for i in range(n, 0, -1):
+            plan.step_adj(st, adj, coefs[i - 1], coefs[i - 2] if i > 1 else None, coef, thb)
+            k = i - 1
+            if k == 0:
+                if cnt[1] > 0:
+                    plan.adj_bump(sim.xi, sim.pi, self.xb[0], self.pb[0], None, 0.0, 0.0, None, None, thb)
+                break
+            go_ahead = cnt[k] > 0 or (k >= 2 and cnt[k - 1] > 0)
+            if need(k):
+                plan.kick(p, self.a[0], coefs[k - 1][2], out=self.p_int)   # p_k
+            if go_ahead:
+                ahead(k, p)
+            if cnt[k] > 0:
+                plan.lightcone_vjp(self._step(lc, cosmo, k), self.x_tmp, self.p_tmp, s, self.p_int, self.obs_step,
+                                   obs_bar, self.xb[1], self.pb[1], self.xb[0], self.pb[0], thb)
+            if need(k):
+                self.cb.zero_()
+                self._force_vjp(s, self.pb[0], coef)
+                Kb, dKb = coefs[k - 1][2], coefs[k - 1][5]
+                plan.adj_bump(sim.xi, sim.pi, self.xb[0], self.pb[0], self.c, Kb, dKb, self.a[0], self.cb, thb)
+                self._swap()
+            if go_ahead:
+                self.a.reverse()
+        g_omega = plan.lpt_vjp(omega, cosmo, ic, adj, thb)
+        return g_omega, thb
+
+    def _force_vjp(self, disp, acc_bar, coef):
+        from ._lib import lib
+        plan = self.sim.plan
+        plan._c(lib().pm_force_vjp(plan._h, api._ptr(disp), api._ptr(acc_bar), float(coef), api._ptr(self.c),
+                                   api._ptr(self.cb), None, api._stream()))

@@ -1,0 +1,238 @@
+"""GPU parity of the light-cone observation (Sec. 2.4), its VJP, the adjoint
+bump and the end-to-end gradient of an objective on the observables (Sec.
+3.4, eq. explicit_adj) against the FP64 oracle.
+
+Tolerances: the tables and the per-step operators in FP64 follow the oracle
+to rounding (the GPU root is a Newton root to 1e-15 in u, the oracle's a
+bisection one to 2^-64); FP32 state rounds the outputs to float.  End to end,
+FP64 mode follows the oracle's stored-trajectory gradient to 1e-8 relative
+(the reverse pass reconstructs the states), mixed mode to 1e-3.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import cosmology as ocos
+from oracle import lightcone as olc
+from oracle import simulate as osim
+from paper_2211_09815_amd import inputs
+from gpu_util import announce, dev, host, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    from paper_2211_09815_amd import api
+    return api
+
+
+OM = 0.3
+
+
+def test_lightcone_tables_match_oracle():
+    api = _api()
+    grid = ocos.linear_a_grid(1 / 64, 1.0, 63)
+    cell = 2.0
+    tab = api.lightcone_tables(api.Cosmology(), grid, cell)
+    for k in (0, 20, 50, 62, 63):
+        chi, dchi, chi_om, dchi_om = olc.light_front(grid[k], OM, cell)
+        w, w_om = olc.velocity_factor(grid[k], OM)
+        c = tab[k]
+        assert c.a == grid[k]
+        assert c.chi == pytest.approx(chi, rel=1e-12, abs=1e-9)
+        assert c.chi_om == pytest.approx(chi_om, rel=1e-11, abs=1e-9)
+        assert c.dchi == pytest.approx(dchi, rel=1e-14)
+        assert c.dchi_om == pytest.approx(dchi_om, rel=1e-13)
+        assert c.w == pytest.approx(w, rel=1e-14)
+        assert c.w_om == pytest.approx(w_om, rel=1e-13)
+
+
+def _step_case(api, sdt, mdt, n=16, nm=32, box=64.0, a0=0.85, seed=4):
+    """States at a0 and a0 + 1/32 of a 16^3 lattice whose box the light front
+    sweeps during the step, plus a few particles the step does not observe."""
+    plan = api.Plan(nm, n, box=box, mesh_dtype=mdt, state_dtype=sdt)
+    cell = box / nm
+    a1 = a0 + 1.0 / 32
+    am = 0.5 * (a0 + a1)
+    X = np.array([nm / 2 - olc.light_front(am, OM, cell)[0], nm / 2 + 0.3, nm / 2 - 0.2])
+    q = osim.lattice(osim.SimConfig(n, nm, box, 0.1, 1.0, 1))
+    rng = np.random.default_rng(seed)
+    s0 = rng.normal(0, 1.5, q.shape)
+    p0 = rng.normal(0, 30.0, q.shape)
+    p1 = p0 + rng.normal(0, 3.0, q.shape)
+    s1 = s0 + (a1 - a0) * 0.5 * (p0 * olc.velocity_factor(a0, OM)[0] + p1 * olc.velocity_factor(a1, OM)[0])
+    # a band pushed inside the front at a1 and one outside it at a0: not observed
+    s0[:64, 0] -= 60.0
+    s1[:64, 0] -= 60.0
+    s0[64:128, 0] += 60.0
+    s1[64:128, 0] += 60.0
+    tab = api.lightcone_tables(api.Cosmology(), [a0, a1], cell)
+    st = api.lc_step(tab[0], tab[1], OM, X, 3)
+    ost = olc.Step(a0, a1, OM, cell, X)
+    return plan, st, ost, q, (s0, p0, s1, p1)
+
+
+def _t3(a, dtype):
+    return dev(np.ascontiguousarray(np.asarray(a).T), dtype)
+
+
+@pytest.mark.parametrize("sdt,mdt", [(torch.float64, torch.float64), (torch.float64, torch.float32),
+                                     (torch.float32, torch.float32)])
+def test_observation_step_vs_oracle(sdt, mdt):
+    api = _api()
+    announce("light-cone step %s/%s" % (sdt, mdt))
+    plan, st, ost, q, (s0, p0, s1, p1) = _step_case(api, sdt, mdt)
+    if sdt == torch.float32:   # the oracle sees the float inputs the GPU sees
+        s0, p0, s1, p1 = (np.asarray(v, np.float32).astype(np.float64) for v in (s0, p0, s1, p1))
+    N = plan.n_particles
+    obs = torch.full((7, N), -7.0, dtype=sdt, device="cuda")
+    ostep = torch.full((N,), -1, dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.float64, device="cuda")
+    plan.lightcone(st, _t3(s0, sdt), _t3(p0, sdt), _t3(s1, sdt), _t3(p1, sdt), obs, ostep, count)
+    m, xh, ph, ah, _ = olc.observe_step(ost, q + s0, p0, q + s1, p1)
+    got_step = ostep.cpu().numpy()
+    assert 3000 < m.sum() <= N - 128
+    np.testing.assert_array_equal(got_step == 3, m)
+    assert np.all(got_step[~m] == -1)                      # untouched
+    assert float(count.cpu()[0]) == m.sum()
+    o = host(obs)
+    assert np.all(o[:, ~m] == -7.0)
+    rt = 1e-12 if sdt == torch.float64 else 2e-7
+    np.testing.assert_allclose(o[0:3, m].T, xh, rtol=rt, atol=rt * np.abs(xh).max())
+    assert rel_l2(o[3:6, m].T, ph) < (1e-11 if sdt == torch.float64 else 1e-6)
+    np.testing.assert_allclose(o[6, m], ah, rtol=rt, atol=0)
+
+
+@pytest.mark.parametrize("sdt,mdt", [(torch.float64, torch.float64), (torch.float64, torch.float32)])
+def test_observation_vjp_vs_oracle(sdt, mdt):
+    api = _api()
+    announce("light-cone VJP %s/%s" % (sdt, mdt))
+    plan, st, ost, q, (s0, p0, s1, p1) = _step_case(api, sdt, mdt)
+    N = plan.n_particles
+    m = olc.crossing_mask(ost, q + s0, q + s1)
+    ostep = torch.as_tensor(np.where(m, 3, 0).astype(np.int32), device="cuda")
+    g = inputs.normal((7, N), inputs.SEED_COTANGENT)
+    if mdt == torch.float32:
+        g = g.astype(np.float32).astype(np.float64)
+    outs = [torch.full((3, N), 0.5, dtype=mdt, device="cuda") for _ in range(4)]
+    thb = torch.zeros(2, dtype=torch.float64, device="cuda")
+    plan.lightcone_vjp(st, _t3(s0, sdt), _t3(p0, sdt), _t3(s1, sdt), _t3(p1, sdt), ostep, dev(g, mdt), *outs, thb)
+    x0, x1 = (q + s0)[m], (q + s1)[m]
+    v0, v1 = olc._tangents(ost, p0[m], p1[m])
+    u = olc.crossing_root(ost, x0, v0, x1, v1)
+    gm = g[:, m].T
+    ref = olc.observe_step_vjp(ost, x0, p0[m], x1, p1[m], u, gm[:, 0:3], gm[:, 3:6], gm[:, 6])
+    tol = 1e-10 if mdt == torch.float64 else 1e-6
+    for k in range(4):
+        got = host(outs[k])
+        assert np.all(got[:, ~m] == 0.5)                   # only observed particles are touched
+        assert rel_l2(got[:, m].T - 0.5, ref[k]) < tol
+    assert float(thb.cpu()[0]) == pytest.approx(ref[4], rel=1e-10)
+    assert float(thb.cpu()[1]) == 0.0
+
+
+@pytest.mark.parametrize("mdt", [torch.float64, torch.float32])
+def test_adj_bump_kick_drift(mdt):
+    api = _api()
+    announce("adj bump / kick / drift %s" % mdt)
+    sdt = torch.float64
+    plan = api.Plan(16, 8, mesh_dtype=mdt, state_dtype=sdt if mdt == torch.float64 else torch.float64)
+    N = plan.n_particles
+    rng = np.random.default_rng(9)
+    xi, pi, xb, pb, c, a = (rng.standard_normal((3, N)) for _ in range(6))
+    if mdt == torch.float32:
+        xi, pi, xb, pb, c, a = (v.astype(np.float32).astype(np.float64) for v in (xi, pi, xb, pb, c, a))
+    txi, tpi = dev(xi, mdt), dev(pi, mdt)
+    cb = torch.tensor([0.37], dtype=torch.float64, device="cuda")
+    thb = torch.tensor([1.0, 2.0], dtype=torch.float64, device="cuda")
+    Kb, dKb = 0.21, -0.05
+    plan.adj_bump(txi, tpi, dev(xb, mdt), dev(pb, mdt), dev(c, mdt), Kb, dKb, dev(a, mdt), cb, thb)
+    tol = 1e-15 if mdt == torch.float64 else 3e-7
+    assert rel_l2(host(txi), xi + xb + Kb * c) < tol
+    assert rel_l2(host(tpi), pi + pb) < tol
+    ref = 1.0 + dKb * np.sum(pb * a) + 1.5 * Kb * 0.37
+    assert float(thb.cpu()[0]) == pytest.approx(ref, rel=1e-12)
+    assert float(thb.cpu()[1]) == 2.0
+    # no correction term (p_0): only the two sums
+    plan.adj_bump(txi, tpi, dev(xb, mdt), dev(pb, mdt), None, 0.0, 0.0, None, None, thb)
+    assert rel_l2(host(txi), xi + 2 * xb + Kb * c) < tol
+    assert float(thb.cpu()[0]) == pytest.approx(ref, rel=1e-12)
+    s, p = rng.standard_normal((3, N)), rng.standard_normal((3, N))
+    out = plan.kick(dev(p, sdt), dev(a, mdt), 0.7)
+    assert rel_l2(host(out), p + 0.7 * a) < 1e-15
+    out = plan.drift(dev(s, sdt), dev(p, sdt), -0.3)
+    assert rel_l2(host(out), s - 0.3 * p) < 1e-15
+
+
+def test_lightcone_rejects_bad_steps():
+    api = _api()
+    plan, st, _, _, (s0, p0, s1, p1) = _step_case(api, torch.float64, torch.float64)
+    N = plan.n_particles
+    args = [_t3(v, torch.float64) for v in (s0, p0, s1, p1)]
+    obs = torch.zeros((7, N), dtype=torch.float64, device="cuda")
+    ostep = torch.zeros(N, dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.float64, device="cuda")
+    bad = api.lc_step(st.c1, st.c0, OM, (0, 0, 0), 1)       # a0 > a1
+    with pytest.raises(api._lib.PmError):
+        plan.lightcone(bad, *args, obs, ostep, count)
+    bad = api.lc_step(st.c0, st.c1, OM, (0, 0, 0), 0)       # step 0
+    with pytest.raises(api._lib.PmError):
+        plan.lightcone(bad, *args, obs, ostep, count)
+
+
+# ---- end to end ---------------------------------------------------------------
+
+def _lightcone_setup(n=8, nm=16, box=32.0, steps=4, split_step=None):
+    cfg = osim.SimConfig(n, nm, box, 1.0 / 16, 1.0, steps)
+    grid = cfg.a_grid()
+    k = steps - 1 if split_step is None else split_step
+    chi_k = olc.light_front(grid[k], OM, box / nm)[0]
+    return cfg, np.array([nm / 2.0 - chi_k, nm / 2.0, nm / 2.0])
+
+
+def _gpu_run(cfg, X, omega, w, mdt, sdt):
+    api = _api()
+    from paper_2211_09815_amd.lightcone import LightCone
+    from paper_2211_09815_amd.simulate import SimConfig, Simulation
+    sim = Simulation(SimConfig(cfg.n_ptcl, cfg.n_mesh, cfg.box, cfg.a_start, cfg.a_end, cfg.n_steps, mdt, sdt))
+    lc = LightCone(sim, X)
+    cosmo = api.Cosmology()
+    tabs = lc.tables(cosmo)
+    om_t = dev(omega, mdt)
+    counts = lc.forward(om_t, cosmo, tabs)
+    obs = host(lc.obs)
+    ostep = lc.obs_step.cpu().numpy()
+    g, th = lc.gradient(om_t, cosmo, dev(w, mdt), tabs)
+    return counts, obs, ostep, host(g), host(th)
+
+
+@pytest.mark.parametrize("n,nm,box,steps,split", [(8, 16, 32.0, 4, None), (16, 16, 64.0, 12, 9)])
+def test_end_to_end_fp64_vs_oracle(n, nm, box, steps, split):
+    announce("light-cone end to end FP64 %d/%d/%d" % (n, nm, steps))
+    cfg, X = _lightcone_setup(n, nm, box, steps, split)
+    omega = inputs.white_noise(n, 0)
+    w = inputs.normal((cfg.n_particles, 7), inputs.SEED_COTANGENT)
+    J, g_ref, th_ref, obs_ref, step_ref = olc.value_and_grad(omega, cfg, X, w)
+    counts, obs, ostep, g, th = _gpu_run(cfg, X, omega, np.ascontiguousarray(w.T), torch.float64, torch.float64)
+    np.testing.assert_array_equal(ostep, step_ref)
+    assert list(counts[1:]) == list(np.bincount(step_ref, minlength=steps + 1)[1:])
+    assert rel_l2(obs.T, obs_ref) < 1e-11
+    Jg = float(np.sum(w[ostep > 0] * obs.T[ostep > 0]))
+    assert Jg == pytest.approx(J, rel=1e-11)
+    assert rel_l2(g, g_ref) < 1e-8
+    np.testing.assert_allclose(th, th_ref, rtol=1e-8)
+
+
+def test_end_to_end_mixed_vs_oracle():
+    announce("light-cone end to end mixed")
+    cfg, X = _lightcone_setup(16, 16, 64.0, 12, 9)
+    omega = inputs.white_noise(16, 0)
+    w = inputs.normal((cfg.n_particles, 7), inputs.SEED_COTANGENT).astype(np.float32).astype(np.float64)
+    J, g_ref, th_ref, obs_ref, step_ref = olc.value_and_grad(omega, cfg, X, w)
+    counts, obs, ostep, g, th = _gpu_run(cfg, X, omega.astype(np.float32), np.ascontiguousarray(w.T),
+                                         torch.float32, torch.float64)
+    same = ostep == step_ref
+    assert same.mean() > 0.999                     # crossings at a step boundary may move by one step
+    assert rel_l2(obs.T[same], obs_ref[same]) < 1e-5
+    assert rel_l2(g, g_ref) < 1e-3
+    np.testing.assert_allclose(th, th_ref, rtol=1e-3)
