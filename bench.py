@@ -370,6 +370,85 @@ def study_force(args, reps=10):
             "kernel_families": fams, "peak_GBps": HBM_PEAK_GBS}
 
 
+def study_lightcone(args):
+    """Light-cone observation (Sec. 2.4) and the exact gradient of an
+    objective on the observables (Sec. 3.4): an observer at the centre of
+    the box of the workload, FP32 mesh and FP64 state, a linear objective
+    with seeded weights on the 7 observed values of every particle.  Reports
+    the forward and gradient times next to the plain final-density pass, the
+    light-cone kernels' share and rate, a check that every particle is
+    observed exactly once, and the FP64 oracle on a small run beside it."""
+    import numpy as np
+    import torch
+
+    from paper_2211_09815_amd import inputs
+    from paper_2211_09815_amd._lib import PM_K_LIGHTCONE
+    from paper_2211_09815_amd.lightcone import LightCone
+    n, nm, box, nsteps, a0 = WORKLOADS[args.workload]
+    sim, cosmo, tabs, omega = _setup_run(n, nm, box, nsteps, a0, torch.float32, torch.float64)
+    N = n ** 3
+    lc = LightCone(sim, (nm / 2.0,) * 3)
+    ltabs = lc.tables(cosmo)
+    w = torch.empty((7, N), dtype=torch.float32, device="cuda")
+    for k in range(7):   # seeded weights, one row at a time to bound host memory
+        w[k].copy_(torch.as_tensor(inputs.normal(N, inputs.SEED_COTANGENT + k, dtype=np.float32)))
+    res = {}
+    for rep in range(2):     # the first repetition is the warm-up
+        sim.plan.timing_enable([PM_K_LIGHTCONE])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        counts = lc.forward(omega, cosmo, ltabs)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ms_f, nl_f, by_f = sim.plan.timing_read(PM_K_LIGHTCONE)
+        sim.plan.timing_enable([PM_K_LIGHTCONE])
+        g, th = lc.gradient(omega, cosmo, w, ltabs)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ms_g, nl_g, by_g = sim.plan.timing_read(PM_K_LIGHTCONE)
+        sim.plan.timing_enable(())
+        log("lightcone rep %d: forward %.3f s, gradient %.3f s" % (rep, t1 - t0, t2 - t1))
+    steps_seen = [int(i) for i in np.nonzero(counts)[0]]
+    ostep = lc.obs_step.cpu().numpy()
+    grid = sim.cfg.a_grid()
+    ah = lc.obs[6].cpu().numpy()
+    in_step = bool(np.all((ah > grid[ostep - 1]) & (ah <= grid[ostep]))) if np.all(ostep > 0) else False
+    res["forward_ms"] = 1000 * (t1 - t0)
+    res["gradient_ms"] = 1000 * (t2 - t1)
+    res["particle_steps_per_s"] = N * nsteps / (t2 - t0)
+    res["observed_per_step"] = {str(i): int(counts[i]) for i in steps_seen}
+    res["every_particle_observed_once"] = bool(int(counts.sum()) == N and np.all(ostep > 0) and in_step)
+    gbs = (by_f / 1e9) / (ms_f / 1e3) if ms_f > 0 else None
+    res["k_lightcone"] = {"launches": nl_f, "ms_total": ms_f, "avg_launch_ms": ms_f / max(nl_f, 1),
+                          "algorithmic_bytes_per_launch": by_f / max(nl_f, 1), "algorithmic_GBps": gbs,
+                          "frac_of_peak": gbs / HBM_PEAK_GBS if gbs else None,
+                          "bytes_note": "two FP64 displacement arrays read per step; the momenta and the "
+                                        "outputs of the observed particles are extra"}
+    res["gradient_lightcone_kernels"] = {"launches": nl_g, "ms_total": ms_g}
+    res["dJ_dtheta"] = th.cpu().tolist()
+    res["grad_omega_norm"] = float(torch.linalg.vector_norm(g.double()))
+    # the plain pass of the same run for comparison
+    target = torch.zeros((nm,) * 3, dtype=torch.float32, device="cuda")
+    _timed_pass(sim, omega, cosmo, target, tabs)
+    _, _, _, dt = _timed_pass(sim, omega, cosmo, target, tabs)
+    res["plain_pass_ms"] = 1000 * dt
+    # the oracle beside it: forward with observation and the stored-trajectory
+    # gradient, 32^3 particles on a 64^3 mesh (128 Mpc/h), 10 steps a=1/16..1
+    from oracle import lightcone as olc
+    from oracle import simulate as osim
+    ocfg = osim.SimConfig(32, 64, 128.0, 1.0 / 16, 1.0, 10)
+    om_o = inputs.white_noise(32, inputs.SEED_RUN)
+    wo = inputs.normal((32 ** 3, 7), inputs.SEED_COTANGENT)
+    t0 = time.perf_counter()
+    olc.value_and_grad(om_o, ocfg, np.array([32.0, 32.0, 32.0]), wo)
+    dt_o = time.perf_counter() - t0
+    res["oracle"] = {"value": 32 ** 3 * 10 / dt_o, "unit": "particle-steps/s", "seconds": dt_o,
+                     "sample": "32^3 particles, 64^3 mesh, 10 steps, forward with observation and the "
+                               "stored-trajectory gradient (FP64 numpy oracle)"}
+    return {"study": "lightcone", "workload": "%d^3 particles, %d^3 mesh, %.0f Mpc/h, %d steps a=%.5f..1, "
+            "observer at the box centre, FP32 mesh / FP64 state" % (n, nm, box, nsteps, a0), "result": res}
+
+
 def study_fd_theta(args, hs=(1e-3, 3e-4)):
     """dJ/d(Omega_m, sigma8) from the adjoint pass against central finite
     differences of the forward model (two step sizes, relative to theta)."""
@@ -423,11 +502,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-ref", action="store_true",
                     help="skip the all-FP64 reference pass used for the gradient rel-L2")
-    ap.add_argument("--study", choices=["precision", "force", "fd-theta", "checkpoints"],
+    ap.add_argument("--study", choices=["precision", "force", "fd-theta", "checkpoints", "lightcone"],
                     help="print a study instead of the benchmark line: precision = FP32 / mixed / FP64 "
                          "reversibility, gradient error and memory vs steps; force = single force and VJP "
                          "per stage at 256^3 particles on a 512^3 mesh; fd-theta = dJ/dtheta against central "
-                         "differences; checkpoints = piecewise reverse from forward checkpoints")
+                         "differences; checkpoints = piecewise reverse from forward checkpoints; "
+                         "lightcone = light-cone observation and its gradient")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -442,7 +522,7 @@ def main():
     families = _lib.KERNEL_FAMILIES
     if args.study:
         out = {"precision": study_precision, "force": study_force, "fd-theta": study_fd_theta,
-               "checkpoints": study_checkpoints}[args.study](args)
+               "checkpoints": study_checkpoints, "lightcone": study_lightcone}[args.study](args)
         print(json.dumps(out), flush=True)
         return
 
