@@ -236,3 +236,38 @@ def test_end_to_end_mixed_vs_oracle():
     assert rel_l2(obs.T[same], obs_ref[same]) < 1e-5
     assert rel_l2(g, g_ref) < 1e-3
     np.testing.assert_allclose(th, th_ref, rtol=1e-3)
+
+
+def test_full_size_observation_properties():
+    # the 512^3 workload of the light-cone study (forward with observation):
+    # properties that hold at any size, and a sample against the oracle's
+    # cubic light front at each observed a^
+    api = _api()
+    from paper_2211_09815_amd.lightcone import LightCone
+    from paper_2211_09815_amd.simulate import SimConfig, Simulation
+    announce("light-cone full size 512^3 forward")
+    n = nm = 512
+    box, steps, a0 = 512.0, 63, 1.0 / 64
+    sim = Simulation(SimConfig(n, nm, box, a0, 1.0, steps, torch.float32, torch.float64))
+    X = (nm / 2.0,) * 3
+    lc = LightCone(sim, X)
+    cosmo = api.Cosmology()
+    tabs = lc.tables(cosmo)
+    counts = lc.forward(dev(inputs.white_noise(n, 0, dtype=np.float32), torch.float32), cosmo, tabs)
+    N = n ** 3
+    assert counts.sum() == N
+    ostep = lc.obs_step.cpu().numpy()
+    assert ostep.min() >= 1
+    assert list(np.bincount(ostep, minlength=steps + 1)) == list(counts)
+    grid = sim.cfg.a_grid()
+    ah = lc.obs[6].cpu().numpy()
+    assert np.all((ah > grid[ostep - 1]) & (ah <= grid[ostep]))
+    idx = inputs.probe_indices(N, 2048)
+    xh = lc.obs[0:3, idx].cpu().numpy().T
+    for i in np.unique(ostep[idx]):
+        sel = ostep[idx] == i
+        st = olc.Step(grid[i - 1], grid[i], OM, box / nm, X)
+        u = (ah[idx][sel] - st.a0) / st.da
+        h, _, _ = olc.hermite(u)
+        front = h[0] * st.c0 + h[1] * st.da * st.dc0 + h[2] * st.c1 + h[3] * st.da * st.dc1
+        np.testing.assert_allclose(np.linalg.norm(xh[sel] - np.array(X), axis=1), front, rtol=1e-9, atol=1e-9)
