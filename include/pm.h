@@ -6,7 +6,9 @@
  * product (Sec. 3.6), the FastPM kick-drift-kick leapfrog (Sec. 2.3,
  * eq. KDFK) and its adjoint with reverse-time integration (Sec. 3.6,
  * eqs. KDFKO_adj and KDFKO_grad), the 2LPT initial conditions (Sec. 2.1,
- * eq. lpt) and the final-density objective of Sec. 4.2.
+ * eq. lpt), the final-density objective of Sec. 4.2, and the light-cone
+ * observation of Sec. 2.4 with the adjoint of an objective on the
+ * observables (Sec. 3.4).
  *
  * Conventions shared by every call
  * --------------------------------

@@ -213,13 +213,16 @@ class Plan:
         self._c(lib().pm_force(self._h, _ptr(disp), float(coef), _ptr(out), _stream()))
         return out
 
-    def force_vjp(self, disp, acc_bar, coef, want_acc=True):
-        """(disp_bar, coef_bar (device FP64 scalar), acc or None)."""
+    def force_vjp(self, disp, acc_bar, coef, want_acc=True, out=None, coef_bar=None):
+        """(disp_bar, coef_bar (device FP64 scalar, +=), acc or None); `out`
+        and `coef_bar` may be given to reuse buffers."""
         self._disp(disp)
         self._t(acc_bar, self.mdt, 3 * self.n_particles, "acc_bar")
-        xbar = torch.empty((3, self.n_particles), dtype=self.mdt, device=self.device)
+        xbar = torch.empty((3, self.n_particles), dtype=self.mdt, device=self.device) if out is None else \
+            self._t(out, self.mdt, 3 * self.n_particles, "out")
         acc = torch.empty_like(xbar) if want_acc else None
-        cbar = torch.zeros(1, dtype=torch.float64, device=self.device)
+        cbar = torch.zeros(1, dtype=torch.float64, device=self.device) if coef_bar is None else \
+            self._t(coef_bar, torch.float64, 1, "coef_bar")
         self._c(lib().pm_force_vjp(self._h, _ptr(disp), _ptr(acc_bar), float(coef), _ptr(xbar), _ptr(cbar),
                                    _ptr(acc), _stream()))
         return xbar, cbar, acc

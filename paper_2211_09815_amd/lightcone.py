@@ -146,7 +146,7 @@ class LightCone:
                                    obs_bar, self.xb[1], self.pb[1], self.xb[0], self.pb[0], thb)
             if need(k):
                 self.cb.zero_()
-                self._force_vjp(s, self.pb[0], coef)
+                plan.force_vjp(s, self.pb[0], coef, want_acc=False, out=self.c, coef_bar=self.cb)
                 Kb, dKb = coefs[k - 1][2], coefs[k - 1][5]
                 plan.adj_bump(sim.xi, sim.pi, self.xb[0], self.pb[0], self.c, Kb, dKb, self.a[0], self.cb, thb)
                 self._swap()
@@ -154,9 +154,3 @@ class LightCone:
                 self.a.reverse()
         g_omega = plan.lpt_vjp(omega, cosmo, ic, adj, thb)
         return g_omega, thb
-
-    def _force_vjp(self, disp, acc_bar, coef):
-        from ._lib import lib
-        plan = self.sim.plan
-        plan._c(lib().pm_force_vjp(plan._h, api._ptr(disp), api._ptr(acc_bar), float(coef), api._ptr(self.c),
-                                   api._ptr(self.cb), None, api._stream()))

@@ -223,14 +223,15 @@ def test_end_to_end_fp64_vs_oracle(n, nm, box, steps, split):
     np.testing.assert_allclose(th, th_ref, rtol=1e-8)
 
 
-def test_end_to_end_mixed_vs_oracle():
-    announce("light-cone end to end mixed")
+@pytest.mark.parametrize("sdt", [torch.float64, torch.float32])
+def test_end_to_end_fp32_mesh_vs_oracle(sdt):
+    announce("light-cone end to end FP32 mesh, %s state" % sdt)
     cfg, X = _lightcone_setup(16, 16, 64.0, 12, 9)
     omega = inputs.white_noise(16, 0)
     w = inputs.normal((cfg.n_particles, 7), inputs.SEED_COTANGENT).astype(np.float32).astype(np.float64)
     J, g_ref, th_ref, obs_ref, step_ref = olc.value_and_grad(omega, cfg, X, w)
     counts, obs, ostep, g, th = _gpu_run(cfg, X, omega.astype(np.float32), np.ascontiguousarray(w.T),
-                                         torch.float32, torch.float64)
+                                         torch.float32, sdt)
     same = ostep == step_ref
     assert same.mean() > 0.999                     # crossings at a step boundary may move by one step
     assert rel_l2(obs.T[same], obs_ref[same]) < 1e-5
