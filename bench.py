@@ -118,6 +118,32 @@ def _setup_run(n, nm, box, nsteps, a0, mdt, sdt, seed=None, checkpoint_steps=())
     return sim, cosmo, tabs, omega
 
 
+def hbm_warmup(gib):
+    """Allocate device memory in 1 GiB pieces, up to `gib` GiB or all but
+    8 GiB of what is free, and release it, before the plan and the state are
+    allocated.  On MI355X the large buffers allocated after such a cycle run
+    the whole pass several percent faster than buffers allocated first in a
+    fresh process (measured; the kernels are the same).  Returns (GiB cycled,
+    seconds)."""
+    import torch
+    if gib <= 0:
+        return 0, 0.0
+    t0 = time.perf_counter()
+    free, _ = torch.cuda.mem_get_info()
+    want = min(int(gib), int(free >> 30) - 8)
+    chunks = []
+    try:
+        for _ in range(max(want, 0)):
+            chunks.append(torch.empty(1 << 30, dtype=torch.uint8, device="cuda"))
+    except RuntimeError:
+        pass
+    got = len(chunks)
+    del chunks
+    torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    return got, time.perf_counter() - t0
+
+
 def _timed_pass(sim, omega, cosmo, target, tabs):
     import torch
     torch.cuda.synchronize()
@@ -492,6 +518,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--hbm-warmup", type=int, default=1024, metavar="GIB",
+                    help="untimed setup: allocate and release up to GIB GiB (at most all but 8 GiB of the free "
+                         "device memory) before the plan and the state are allocated; 0: off")
     ap.add_argument("--workload", default="512", choices=sorted(WORKLOADS))
     ap.add_argument("--kernel", default="auto",
                     help="kernel family for the roofline object (default: the one with the most time)")
@@ -530,6 +559,9 @@ def main():
     mdt = torch.float32 if args.mesh_dtype == "f32" else torch.float64
     sdt = torch.float32 if args.state_dtype == "f32" else torch.float64
     torch.cuda.set_device(0)
+    warm_gib, warm_s = hbm_warmup(args.hbm_warmup)
+    if warm_gib:
+        log("HBM warm-up: %d GiB allocated and released in %.1f s" % (warm_gib, warm_s))
     if args.copy_calibration:
         x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
@@ -648,6 +680,9 @@ def main():
             "state_dtype": args.state_dtype,
             "peak_mem_gb": (peak_mem + plan_ws) / 1e9,
             "peak_mem_note": "torch allocator peak plus the plan's own workspace",
+            "hbm_warmup_gib": warm_gib,
+            "hbm_warmup_note": "untimed setup step: device memory allocated and released before the plan and "
+                               "the state; the timed work is unchanged",
         },
         "roofline": {
             "bound": "hbm",
