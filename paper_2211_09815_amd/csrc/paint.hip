@@ -365,34 +365,36 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
         d1 = T(x1 - f1);
         d2 = T(x2 - f2);
       }
-      const T wx[2] = {T(1) - d0, d0}, wy[2] = {T(1) - d1, d1}, wz[2] = {T(1) - d2, d2};
+      const T ux0 = T(1) - d0, uy0 = T(1) - d1, uz0 = T(1) - d2;
       double wc[NCH];
 #pragma unroll
       for (int c = 0; c < NCH; ++c)
         wc[c] = ((UNIT && c == 0) ? 1.0 : double(ws[k][c - (UNIT ? 1 : 0)])) * sc[c];
+      // The 8 corners in an order rotated by the lane: lanes whose particles
+      // share a cell then add to different cells in the same LDS atomic
+      // instruction instead of serialising on one address.  The integer sums
+      // do not depend on the order.
+      const int rot = tid & 7;
 #pragma unroll
-      for (int i0 = 0; i0 < 2; ++i0)
+      for (int j = 0; j < 8; ++j) {
+        const int cn = (j + rot) & 7;
+        const int i0 = cn >> 2, i1 = (cn >> 1) & 1, i2 = cn & 1;
+        const T wxy = (i0 ? d0 : ux0) * (i1 ? d1 : uy0);
+        const double ww = double(wxy * (i2 ? d2 : uz0));
+        const int r = ((l0 + i0) * ey + (l1 + i1)) * ez + l2 + i2;
 #pragma unroll
-        for (int i1 = 0; i1 < 2; ++i1) {
-          const T wxy = wx[i0] * wy[i1];
-          const int rowb = ((l0 + i0) * ey + (l1 + i1)) * ez + l2;
-#pragma unroll
-          for (int i2 = 0; i2 < 2; ++i2) {
-            const double ww = double(wxy * wz[i2]);
-#pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-              long long q;
-              if constexpr (F32) {
-                // |ww wc| < 2^51: round to the nearest integer (ties to even)
-                // in the low mantissa bits of 1.5 * 2^52 + ww wc
-                q = __double_as_longlong(fma(ww, wc[c], 6755399441055744.0)) - 0x4338000000000000ll;
-              } else {
-                q = __double2ll_rn(ww * wc[c]);
-              }
-              atomicAdd(&box[c * kBoxMax + rowb + i2], (unsigned long long)q);
-            }
+        for (int c = 0; c < NCH; ++c) {
+          long long q;
+          if constexpr (F32) {
+            // |ww wc| < 2^51: round to the nearest integer (ties to even)
+            // in the low mantissa bits of 1.5 * 2^52 + ww wc
+            q = __double_as_longlong(fma(ww, wc[c], 6755399441055744.0)) - 0x4338000000000000ll;
+          } else {
+            q = __double2ll_rn(ww * wc[c]);
           }
+          atomicAdd(&box[c * kBoxMax + r], (unsigned long long)q);
         }
+      }
     }
   };
 
