@@ -29,7 +29,9 @@ Readings (the paper gives no formulas for these; each is ours):
       step i when f(0) < 0 <= f(1), at the root u* of f in [0, 1].  One copy
       of the periodic box is observed (unwrapped positions x = q + s, no
       images); a particle outside the front at a_0 is never observed.  If a
-      particle satisfied the test in two steps, the later one wins.
+      particle satisfied the test in two steps, the later one wins.  At the
+      observer itself (distance 0, possible only at a = 1) the distance's
+      gradient is taken as zero.
   L4  Observed state: x^ = x(u*), p^ = a^3 E(a^) dx/da (u*) (so p^ equals the
       integer-time momentum at either end of the step), a^ = a_{i-1} + u* da.
   L5  Integer-time momenta of the KDK scheme: p_i = p_{i-1/2} + a_i Kb_i.
@@ -175,7 +177,9 @@ def observe_step_vjp(st, x0, p0, x1, p1, u, gx, gp, ga):
     vel = _spline(d, x0, v0, x1, v1)          # dx/du
     acc = _spline(dd, x0, v0, x1, v1)         # d2x/du2
     rel = pos - st.X
-    rhat = rel / np.linalg.norm(rel, axis=1)[:, None]
+    r = np.linalg.norm(rel, axis=1)
+    # |x - X| has no gradient at the observer itself; reading L3 takes it as zero there
+    rhat = np.divide(rel, r[:, None], out=np.zeros_like(rel), where=r[:, None] > 0)
     ahat = st.a0 + u * da
     E = _E(ahat, st.om)
     S = ahat ** 3 * E

@@ -186,7 +186,8 @@ __global__ __launch_bounds__(kThreads) void k_lightcone_vjp(const LcGeo L, const
       acc[k] = comb(dd, Tr.x0[k], Tr.v0[k], Tr.x1[k], Tr.v1[k]);
       r2 += pos[k] * pos[k];
     }
-    const double rinv = 1.0 / sqrt(r2);
+    // |x - X| has no gradient at the observer itself; take it as zero there
+    const double rinv = r2 > 0.0 ? 1.0 / sqrt(r2) : 0.0;
     const double ah = L.a0 + u * L.da;
     const double a3 = ah * ah * ah;
     const double E = sqrt(L.om / a3 + (1.0 - L.om));

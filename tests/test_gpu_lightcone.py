@@ -164,6 +164,35 @@ def test_adj_bump_kick_drift(mdt):
     assert rel_l2(host(out), s - 0.3 * p) < 1e-15
 
 
+def test_particle_at_the_observer_has_a_finite_vjp():
+    # lattice particle 0 reaches the observer's position at a = 1
+    api = _api()
+    announce("light-cone particle at the observer")
+    plan = api.Plan(16, 8, box=32.0, mesh_dtype=torch.float64, state_dtype=torch.float64)
+    N = plan.n_particles
+    a0, a1, cell = 1.0 - 1.0 / 32, 1.0, 2.0
+    q = osim.lattice(osim.SimConfig(8, 16, 32.0, 0.1, 1.0, 1))
+    X = q[0] + np.array([0.25, -0.5, 0.125])
+    p = np.zeros((N, 3))
+    p[:, 0] = 2.0
+    s1 = np.zeros((N, 3))
+    s1[0] = X - q[0]
+    s0 = s1 - (a1 - a0) * olc.velocity_factor(a0, OM)[0] * p
+    tab = api.lightcone_tables(api.Cosmology(), [a0, a1], cell)
+    st = api.lc_step(tab[0], tab[1], OM, X, 1)
+    obs = torch.zeros((7, N), dtype=torch.float64, device="cuda")
+    ostep = torch.zeros(N, dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.float64, device="cuda")
+    args = [_t3(v, torch.float64) for v in (s0, p, s1, p)]
+    plan.lightcone(st, *args, obs, ostep, count)
+    assert int(ostep.cpu()[0]) == 1
+    assert float(obs.cpu()[6, 0]) == pytest.approx(1.0, abs=1e-15)
+    outs = [torch.zeros((3, N), dtype=torch.float64, device="cuda") for _ in range(4)]
+    thb = torch.zeros(2, dtype=torch.float64, device="cuda")
+    plan.lightcone_vjp(st, *args, ostep, torch.ones((7, N), dtype=torch.float64, device="cuda"), *outs, thb)
+    assert all(np.all(np.isfinite(host(t))) for t in outs) and np.isfinite(float(thb.cpu()[0]))
+
+
 def test_lightcone_rejects_bad_steps():
     api = _api()
     plan, st, _, _, (s0, p0, s1, p1) = _step_case(api, torch.float64, torch.float64)

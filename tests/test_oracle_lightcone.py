@@ -202,3 +202,16 @@ def test_run_gradient_matches_central_differences():
             vals.append((L.objective_value(omega, cp, X, w) - L.objective_value(omega, cm, X, w)) / (2 * hh))
         assert vals[0] == pytest.approx(vals[1], rel=1e-6)
         assert gt[k] == pytest.approx(vals[1], rel=1e-6)
+
+
+def test_vjp_is_finite_for_a_particle_at_the_observer():
+    # a particle that reaches the observer's position at a = 1 crosses there
+    # (f(1) = 0); the distance has no gradient at that point (reading L3)
+    st = L.Step(1.0 - 1.0 / 32, 1.0, OM, CELL, (5.0, 6.0, 7.0))
+    x1 = np.array([[5.0, 6.0, 7.0]])
+    p = np.array([[3.0, -2.0, 1.0]])
+    x0 = x1 - st.da * st.w0 * p
+    m, xh, ph, ah, u = L.observe_step(st, x0, p, x1, p)
+    assert m.tolist() == [True] and ah[0] == pytest.approx(1.0, abs=1e-15)
+    bars = L.observe_step_vjp(st, x0, p, x1, p, u, np.ones((1, 3)), np.ones((1, 3)), np.ones(1))
+    assert all(np.all(np.isfinite(b)) for b in bars)
