@@ -159,6 +159,31 @@ def _rel_l2(a, b):
                  / torch.linalg.vector_norm(b.double().reshape(-1)))
 
 
+def stream_bandwidth(plan, gib=2, reps=5):
+    """Best rate of the library's STREAM-like kernels (pm_stream) over a
+    `gib` GiB buffer: pure read, copy (read + write bytes) and pure write."""
+    import torch
+    from paper_2211_09815_amd import _lib
+    x = torch.zeros((gib << 30) // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    out = {}
+    for name, mode, src, dst in (("read", _lib.PM_STREAM_READ, x, None), ("copy", _lib.PM_STREAM_COPY, x, y),
+                                 ("write", _lib.PM_STREAM_WRITE, None, y)):
+        plan.stream(mode, src, dst)
+        best = 0.0
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            nbytes = plan.stream(mode, src, dst)
+            e1.record()
+            e1.synchronize()
+            best = max(best, nbytes / 1e9 / (e0.elapsed_time(e1) / 1e3))
+        out[name] = best
+    del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_bandwidth(gib=2, reps=5):
     """Best device-to-device copy rate (read + write bytes / time) of a
     `gib` GiB buffer: the practical HBM ceiling next to the published peak."""
@@ -649,6 +674,9 @@ def main():
     log("J %.6e  |dJ/domega| %.6e  dJ/dtheta %s  finite %s" % (Jv, gn, thv, ok))
     copy_gbs = copy_bandwidth()
     log("device copy: %.0f GB/s" % copy_gbs)
+    stream_gbs = stream_bandwidth(sim.plan)
+    log("stream kernels: read %.0f, copy %.0f, write %.0f GB/s" % (stream_gbs["read"], stream_gbs["copy"],
+                                                                   stream_gbs["write"]))
     ref = None
     if not args.no_fp64_ref and (args.mesh_dtype, args.state_dtype) != ("f64", "f64"):
         g_keep, th_keep = g.double().clone(), th.clone()
@@ -698,6 +726,9 @@ def main():
             "algorithmic_bytes_per_launch": kbytes / klaunch if klaunch else None,
             "device_copy_GBps": copy_gbs,
             "frac_of_copy": (achieved / copy_gbs) if achieved else None,
+            "stream_GBps": stream_gbs,
+            "stream_note": "the library's own STREAM-like kernels (pm_stream), best of 5 over 2 GiB: pure "
+                           "read, copy (read + write bytes), pure write",
         },
         "kernels": kernels,
         "kernels_note": ("per-family times of the last warmup pass, which times every family; the timed "

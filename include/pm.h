@@ -388,6 +388,18 @@ int pm_drift(pm_plan plan, const void* s, const void* p, double D, void* s_out,
 int pm_check_finite(pm_plan plan, const void* x, int64_t n, int dtype, int* bad,
                     hipStream_t stream);
 
+/* STREAM-like bandwidth kernels (measurement support): the HBM rate of a
+ * pure read of nbytes at src (mode PM_STREAM_READ), of a copy src -> dst
+ * (PM_STREAM_COPY) and of a pure write of zeros to dst (PM_STREAM_WRITE),
+ * with 16-byte vectors in grid-stride loops over 2048 workgroups.  nbytes: a
+ * positive multiple of 16; src and dst 16-byte aligned device pointers, not
+ * overlapping.  The caller times the call (e.g. with events on `stream`).
+ * Errors: PM_EINVAL for a bad mode, size or pointer. */
+#define PM_STREAM_READ  0
+#define PM_STREAM_COPY  1
+#define PM_STREAM_WRITE 2
+int pm_stream(pm_plan plan, int mode, const void* src, void* dst, int64_t nbytes, hipStream_t stream);
+
 /* Kernel timing.  pm_timing_enable(plan, mask) times every launch of the
  * kernel families whose bit (1 << PM_K_*) is set in mask (0 switches timing
  * off); each launch is bracketed by HIP events on the stream it runs on.

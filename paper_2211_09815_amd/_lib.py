@@ -30,6 +30,10 @@ PM_K_SCATTER = 7
 PM_K_PAINT_TILES = 8
 PM_K_HALO = 9
 PM_K_LIGHTCONE = 10
+
+PM_STREAM_READ = 0
+PM_STREAM_COPY = 1
+PM_STREAM_WRITE = 2
 KERNEL_FAMILIES = {
     "bin": PM_K_BIN, "scatter": PM_K_SCATTER, "paint_tiles": PM_K_PAINT_TILES, "halo_add": PM_K_HALO,
     "fft_r2c_z": PM_K_FFT_R2C_Z, "fft_lines": PM_K_FFT_LINES, "fft_poisson": PM_K_FFT_POISSON,
@@ -127,6 +131,7 @@ _PROTOS = {
     "pm_adj_bump": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_dbl, c_dbl, c_vp, c_vp, c_vp, c_vp]),
     "pm_kick": (c_int, [c_vp, c_vp, c_vp, c_dbl, c_vp, c_vp]),
     "pm_drift": (c_int, [c_vp, c_vp, c_vp, c_dbl, c_vp, c_vp]),
+    "pm_stream": (c_int, [c_vp, c_int, c_vp, c_vp, c_i64, c_vp]),
     "pm_check_finite": (c_int, [c_vp, c_vp, c_i64, c_int, c_vp, c_vp]),
     "pm_timing_enable": (c_int, [c_vp, ctypes.c_uint]),
     "pm_timing_read": (c_int, [c_vp, c_int, P(c_dbl), P(c_i64), P(c_dbl)]),

@@ -416,6 +416,18 @@ class Plan:
         self._c(lib().pm_check_finite(self._h, _ptr(x), x.numel(), _code(x.dtype), _ptr(bad), _stream()))
         return bad
 
+    def stream(self, mode, src=None, dst=None):
+        """pm_stream: one STREAM-like pass (read src, copy src -> dst, or
+        write dst) on the current stream; returns the bytes moved."""
+        t = src if src is not None else dst
+        if t is None or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("stream needs contiguous device tensors")
+        nbytes = t.numel() * t.element_size()
+        if src is not None and dst is not None and dst.numel() * dst.element_size() < nbytes:
+            raise ValueError("dst is smaller than src")
+        self._c(lib().pm_stream(self._h, int(mode), _ptr(src), _ptr(dst), nbytes, _stream()))
+        return nbytes * (2 if mode == _lib.PM_STREAM_COPY else 1)
+
     def timing_enable(self, kernels=()):
         """Time the given PM_K_* kernel families (empty: switch timing off)."""
         mask = 0

@@ -219,3 +219,21 @@ def test_plan_destroy_leaves_no_pending_hip_error():
         x = torch.ones(1024, device="cuda")
         assert float((x * 2).sum()) == 2048.0
         torch.cuda.synchronize()
+
+
+def test_stream_kernels_copy_write_and_reject_bad_sizes():
+    from paper_2211_09815_amd import _lib, api
+    announce("stream kernels")
+    plan = api.Plan(16, 8, mesh_dtype=torch.float32, state_dtype=torch.float32)
+    x = torch.arange(1 << 20, dtype=torch.float32, device="cuda")
+    y = torch.full_like(x, -1.0)
+    assert plan.stream(_lib.PM_STREAM_COPY, x, y) == 2 * x.numel() * 4
+    assert torch.equal(x, y)
+    assert plan.stream(_lib.PM_STREAM_READ, x, None) == x.numel() * 4
+    plan.stream(_lib.PM_STREAM_WRITE, None, y)
+    torch.cuda.synchronize()
+    assert int(torch.count_nonzero(y)) == 0
+    with pytest.raises(_lib.PmError):
+        plan.stream(_lib.PM_STREAM_COPY, x[1:], y)          # 4-byte offset: not 16-byte aligned
+    with pytest.raises(_lib.PmError):
+        plan.stream(7, x, y)
