@@ -14,6 +14,7 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -543,6 +544,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-warmup-child", dest="warmup_child", action="store_false",
+                    help="skip the child process of the HBM warm-up (for a run whose previous process already "
+                         "cycled the memory, e.g. under a profiler)")
     ap.add_argument("--hbm-warmup", type=int, default=1024, metavar="GIB",
                     help="untimed setup: allocate and release up to GIB GiB (at most all but 8 GiB of the free "
                          "device memory) before the plan and the state are allocated; 0: off")
@@ -568,6 +572,15 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the mesh would shard as slabs with all-to-all transposes; not built)", file=sys.stderr)
         sys.exit(2)
+
+    if args.hbm_warmup > 0 and args.warmup_child and not args.study:
+        # the same cycle first in a short child process, before this process
+        # touches the GPU: memory that an earlier process allocated and
+        # released runs faster than memory a process is the first to use
+        t0 = time.perf_counter()
+        rc = subprocess.run([sys.executable, "-c", "import bench; bench.hbm_warmup(%d)" % args.hbm_warmup],
+                            cwd=os.path.dirname(os.path.abspath(__file__))).returncode
+        log("HBM warm-up in a child process: exit %d, %.1f s" % (rc, time.perf_counter() - t0))
 
     import torch
 
@@ -709,8 +722,10 @@ def main():
             "peak_mem_gb": (peak_mem + plan_ws) / 1e9,
             "peak_mem_note": "torch allocator peak plus the plan's own workspace",
             "hbm_warmup_gib": warm_gib,
-            "hbm_warmup_note": "untimed setup step: device memory allocated and released before the plan and "
-                               "the state; the timed work is unchanged",
+            "hbm_warmup_child": bool(args.warmup_child and args.hbm_warmup > 0),
+            "hbm_warmup_note": "untimed setup step: device memory allocated and released, first in a child "
+                               "process and then in this one, before the plan and the state; the timed work is "
+                               "unchanged",
         },
         "roofline": {
             "bound": "hbm",
