@@ -268,6 +268,24 @@ def test_end_to_end_fp32_mesh_vs_oracle(sdt):
     np.testing.assert_allclose(th, th_ref, rtol=1e-3)
 
 
+def test_no_particle_observed_gives_a_zero_gradient():
+    # an observer so far away that the front has passed the box before a_0:
+    # nothing is observed, and the gradient of any objective on the
+    # observables is zero
+    api = _api()
+    from paper_2211_09815_amd.lightcone import LightCone
+    from paper_2211_09815_amd.simulate import SimConfig, Simulation
+    announce("light cone with nothing observed")
+    sim = Simulation(SimConfig(8, 16, 32.0, 1.0 / 16, 1.0, 4, torch.float64, torch.float64))
+    lc = LightCone(sim, (1.0e6, 0.0, 0.0))
+    cosmo = api.Cosmology()
+    om = dev(inputs.white_noise(8, 0), torch.float64)
+    counts = lc.forward(om, cosmo)
+    assert counts.sum() == 0 and int(lc.obs_step.abs().sum()) == 0
+    g, th = lc.gradient(om, cosmo, torch.ones((7, 8 ** 3), dtype=torch.float64, device="cuda"))
+    assert float(torch.count_nonzero(g)) == 0 and host(th).tolist() == [0.0, 0.0]
+
+
 def test_full_size_observation_properties():
     # the 512^3 workload of the light-cone study (forward with observation):
     # properties that hold at any size, and a sample against the oracle's
