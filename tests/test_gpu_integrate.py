@@ -397,3 +397,20 @@ def test_checkpoints_reduce_the_reversal_error_of_fp32_state():
     assert e0 > 0
     assert e4 < e0
     assert rev["all"] <= rev["every4"] <= rev["none"]
+
+
+def test_pass_is_reproducible_run_to_run():
+    # the paint sums in fixed point, so J and dJ/domega repeat bitwise; the
+    # FP64 partial sums behind dJ/dtheta follow the particle order inside a
+    # tile, which the binning's atomics may change between runs
+    api = _api()
+    from paper_2211_09815_amd.simulate import SimConfig, Simulation
+    announce("run-to-run reproducibility")
+    sim = Simulation(SimConfig(16, 32, 64.0, 1 / 16, 1.0, 6, torch.float32, torch.float64))
+    cosmo = api.Cosmology()
+    omega = dev(inputs.white_noise(16, 0), torch.float32)
+    target = dev(np.zeros((32, 32, 32)), torch.float32)
+    r1 = [t.clone() for t in sim.value_and_grad(omega, cosmo, target)]
+    r2 = [t.clone() for t in sim.value_and_grad(omega, cosmo, target)]
+    assert torch.equal(r1[0], r2[0]) and torch.equal(r1[1], r2[1])
+    np.testing.assert_allclose(host(r1[2]), host(r2[2]), rtol=1e-13)

@@ -237,3 +237,23 @@ def test_stream_kernels_copy_write_and_reject_bad_sizes():
         plan.stream(_lib.PM_STREAM_COPY, x[1:], y)          # 4-byte offset: not 16-byte aligned
     with pytest.raises(_lib.PmError):
         plan.stream(7, x, y)
+
+
+@pytest.mark.parametrize("mdt,tol", [(torch.float64, 1e-12), (torch.float32, 2e-6)])
+def test_force_momentum_conservation_and_zero_self_force(mdt, tol):
+    # paint and readout share the CIC weights and the gradient operator is
+    # anti-self-adjoint, so the pair forces cancel (sum of a = 0) and a lone
+    # particle feels no force from its own density
+    from paper_2211_09815_amd import api
+    announce("force invariants %s" % mdt)
+    sdt = torch.float64
+    plan = api.Plan(32, 16, mesh_dtype=mdt, state_dtype=sdt)
+    disp = dev(inputs.normal((3, plan.n_particles), 21, scale=3.0), sdt)
+    a = host(plan.force(disp, 0.45))
+    assert np.abs(a.sum(axis=1)).max() < tol * np.abs(a).sum()
+    one = api.Plan(16, 1, mesh_dtype=mdt, state_dtype=sdt)
+    for k in range(4):
+        d = dev(inputs.uniform((3, 1), 30 + k, 0.0, 16.0), sdt)
+        a1 = host(one.force(d, 0.45))
+        # a neighbour one cell away pulls with ~1e2 here; float32 FFT noise is ~1e-4 of that
+        assert np.abs(a1).max() < (1e-10 if mdt == torch.float64 else 1e-3)
