@@ -367,26 +367,26 @@ def study_force(args, reps=10):
     plan.lpt(omega, cosmo, ic, st)
     s = st["s"]
     cot = torch.as_tensor(inputs.normal((3, n ** 3), inputs.SEED_COTANGENT, dtype=np.float32), device="cuda")
-    coef = 1.5 * cosmo.omega_m
+    om = cosmo.omega_m
     N, Nc = n ** 3, nm ** 3
     Ns = nm * nm * (nm // 2 + 1)
     f4, c8 = 4.0, 8.0
     rho = plan.paint(s)
     dk = plan.fft_r2c(rho)
-    gk = plan.poisson_grad(dk[0], coef)
+    gk = plan.poisson_grad(dk[0], om)
     g = plan.fft_c2r(gk)
     stages = [
         ("paint", lambda: plan.paint(s, out=rho), N * 12 + Nc * f4),
         ("r2c", lambda: plan.fft_r2c(rho, out=dk), Nc * f4 + Ns * c8),
-        ("poisson_grad (unfused)", lambda: plan.poisson_grad(dk[0], coef, out=gk), 4 * Ns * c8),
+        ("poisson_grad (unfused)", lambda: plan.poisson_grad(dk[0], om, out=gk), 4 * Ns * c8),
         # the inverse transform works in place on its input; the timing of a
         # transform does not depend on the values it is given
         ("3x c2r", lambda: plan.fft_c2r(gk, out=g, destroy_input=True), 3 * (Ns * c8 + Nc * f4)),
         ("readout (3 fields)", lambda: plan.readout(s, g), N * 12 + 3 * Nc * f4 + 3 * N * f4),
-        ("force (fused: paint, r2c, gradient in the x pass, 3x c2r, readout)", lambda: plan.force(s, coef),
+        ("force (fused: paint, r2c, gradient in the x pass, 3x c2r, readout)", lambda: plan.force(s, om),
          N * 12 + Nc * f4 + (Nc * f4 + Ns * c8) + 3 * (Ns * c8 + Nc * f4) + 3 * Nc * f4 + 3 * N * f4),
         ("force VJP (4-channel paint, 4x r2c, combine in the x pass, 4x c2r, 4-field gather)",
-         lambda: plan.force_vjp(s, cot, coef, want_acc=False),
+         lambda: plan.force_vjp(s, cot, om, want_acc=False),
          N * 12 + 3 * N * f4 + 4 * Nc * f4 + 4 * (Nc * f4 + Ns * c8) + 4 * (Ns * c8 + Nc * f4) + 4 * Nc * f4
          + N * 12 + 3 * N * f4 + 3 * N * f4),
     ]
@@ -405,8 +405,8 @@ def study_force(args, reps=10):
                      "frac_of_peak": by / 1e9 / (ms / 1e3) / HBM_PEAK_GBS})
     # kernel families inside the fused force and the VJP
     fams = {}
-    for label, fn in (("force", lambda: plan.force(s, coef)),
-                      ("force_vjp", lambda: plan.force_vjp(s, cot, coef, want_acc=False))):
+    for label, fn in (("force", lambda: plan.force(s, om)),
+                      ("force_vjp", lambda: plan.force_vjp(s, cot, om, want_acc=False))):
         plan.timing_enable(_lib.KERNEL_FAMILIES.values())
         for _ in range(reps):
             fn()

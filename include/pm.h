@@ -18,8 +18,10 @@
  *    (pm_last_error(NULL) gives the last plan-creation error of the calling
  *    thread).
  *  - Units: positions, displacements and momenta are in mesh cells, time in
- *    1/H0 (H0 = 1).  The force coefficient `coef` is 1.5 * Omega_m (the
- *    Poisson equation for phi~ = a phi, Sec. 2.2).
+ *    1/H0 (H0 = 1).  Calls that evaluate the force take `omega_m` (> 0) and
+ *    form the Poisson coefficient 1.5 * Omega_m themselves (the Poisson
+ *    equation for phi~ = a phi, Sec. 2.2); their derivative outputs are with
+ *    respect to Omega_m.
  *  - Particles: N_p = ptcl[0]*ptcl[1]*ptcl[2] in row-major lattice order.
  *    Particle n = (i*ptcl[1] + j)*ptcl[2] + k sits at the Lagrangian position
  *    q = (i, j, k) * r + lattice_offset with r[a] = mesh[a] / ptcl[a]; only
@@ -39,7 +41,7 @@
  *    the first pm_lpt / pm_lpt_vjp call allocates; pm_workspace_bytes
  *    reports both.  The other calls allocate nothing.
  *  - Streams: every call is asynchronous on the given stream (0 = default).
- *    Scalars reported on the device (J, coef_bar, theta_bar) are ready after
+ *    Scalars reported on the device (J, omega_m_bar, theta_bar) are ready after
  *    the stream is synchronised.  A plan is not thread-safe; calls made with
  *    one plan on different streams must be ordered by the caller.
  *  - Determinism: the paint sums each mesh tile in 64-bit fixed point with
@@ -121,11 +123,11 @@ int pm_paint(pm_plan plan, const void* disp, const void* weights, int nch,
 int pm_fft(pm_plan plan, int dir, void* in, void* out, int batch, hipStream_t stream);
 
 /* ---- a5: Poisson gradient (Sec. 2.2) ----------------------------------- */
-/* grad_k[j](k) = T_j(k) delta_k(k), T_j = i k_j coef / k^2, k_j = 2 pi m_j /
- * mesh[j]; zero at k = 0 and on the Nyquist plane of axis j (so that each
- * operator is real and exactly anti-self-adjoint).  delta_k: one half
- * spectrum; grad_k: [3] half spectra (must not overlap delta_k). */
-int pm_poisson_grad(pm_plan plan, const void* delta_k, void* grad_k, double coef,
+/* grad_k[j](k) = T_j(k) delta_k(k), T_j = i k_j 1.5 omega_m / k^2, k_j =
+ * 2 pi m_j / mesh[j]; zero at k = 0 and on the Nyquist plane of axis j (so
+ * that each operator is real and exactly anti-self-adjoint).  delta_k: one
+ * half spectrum; grad_k: [3] half spectra (must not overlap delta_k). */
+int pm_poisson_grad(pm_plan plan, const void* delta_k, void* grad_k, double omega_m,
                     hipStream_t stream);
 
 /* ---- a7: CIC readout (Sec. 2.2) ---------------------------------------- */
@@ -137,17 +139,18 @@ int pm_readout(pm_plan plan, const void* disp, const void* mesh, int nch, void* 
 /* ---- a3..a7 composed: PM force ----------------------------------------- */
 /* acc = -grad phi~ at the particles: paint, delta = rho N_c/N_p - 1, R2C,
  * Poisson gradient, 3 C2R, readout.  acc: [3][N_p] mesh dtype. */
-int pm_force(pm_plan plan, const void* disp, double coef, void* acc, hipStream_t stream);
+int pm_force(pm_plan plan, const void* disp, double omega_m, void* acc, hipStream_t stream);
 
 /* ---- a8: force VJP (Sec. 3.6; scatter/gather VJPs) ---------------------- */
 /* For cotangent acc_bar [3][N_p] of the accelerations:
  *   disp_bar[k][n] = sum_j acc_bar[j][n] d a_j(n) / d x_k(n') summed over n'
  *                    (the VJP with respect to all particle positions),
- *   *coef_bar     += sum_{n,j} acc_bar[j][n] a_j(n) / coef   (device double),
+ *   *omega_m_bar  += sum_{n,j} acc_bar[j][n] a_j(n) / omega_m   (device
+ *                    double; a is proportional to Omega_m),
  *   acc_out        = a (optional, may be NULL).
  * disp_bar: [3][N_p] mesh dtype, overwritten. */
-int pm_force_vjp(pm_plan plan, const void* disp, const void* acc_bar, double coef,
-                 void* disp_bar, double* coef_bar, void* acc_out, hipStream_t stream);
+int pm_force_vjp(pm_plan plan, const void* disp, const void* acc_bar, double omega_m,
+                 void* disp_bar, double* omega_m_bar, void* acc_out, hipStream_t stream);
 
 /* ---- a1: step coefficients and KDK steps (Sec. 2.3, eq. KDFK) ------------ */
 /* Step i (1-based) goes from a_{i-1} to a_i through a_{i-1/2}:
@@ -169,7 +172,7 @@ typedef struct {
 
 /* Forward start: a_0 = F(x_0); p <- p_0 + a_0 first->Ka.
  * In: (s_0, p_0).  Out: (s_0, p_{1/2}). */
-int pm_fwd_init(pm_plan plan, pm_state* st, const pm_step_coef* first, double coef,
+int pm_fwd_init(pm_plan plan, pm_state* st, const pm_step_coef* first, double omega_m,
                 hipStream_t stream);
 
 /* Forward step i with merged kicks:
@@ -179,11 +182,13 @@ int pm_fwd_init(pm_plan plan, pm_state* st, const pm_step_coef* first, double co
  * stored in st->acc when st->acc != NULL.
  * In: (s_{i-1}, p_{i-1/2}).  Out: (s_i, p_{i+1/2}) or (s_n, p_n). */
 int pm_step_fwd(pm_plan plan, pm_state* st, const pm_step_coef* cur,
-                const pm_step_coef* next, double coef, hipStream_t stream);
+                const pm_step_coef* next, double omega_m, hipStream_t stream);
 
 /* ---- a9/a10: adjoint with reverse-time integration (eq. KDFKO_adj) ------ */
 /* theta_bar: device double[2], accumulated (+=): [0] dJ/dOmega_m, [1]
- * dJ/dsigma8 (the steps only touch [0]; coef must equal 1.5 Omega_m). */
+ * dJ/dsigma8 (the steps only touch [0]).  The Omega_m derivative covers both
+ * the step coefficients (their d/dOmega_m in pm_step_coef) and the force,
+ * which is proportional to Omega_m: zeta = (pi . a) / omega_m. */
 
 /* Reverse start at t_n.  In: (s_n, p_n, acc = a_n or NULL to recompute),
  * (xi_n, pi_n).  Computes alpha_n, zeta_n = pi_n . da/d(x, Omega_m) at x_n,
@@ -191,7 +196,7 @@ int pm_step_fwd(pm_plan plan, pm_state* st, const pm_step_coef* cur,
  * theta_bar[0] += (pi_n . a_n) dKb_n + zeta_n Kb_n.
  * Out: (s_n, p_{n-1/2}), (xi_{n-1/2}, pi_n). */
 int pm_adj_init(pm_plan plan, pm_state* st, pm_adj* adj, const pm_step_coef* last,
-                double coef, double* theta_bar, hipStream_t stream);
+                double omega_m, double* theta_bar, hipStream_t stream);
 
 /* Reverse step i (i = n..1) with merged kicks:
  *   theta_bar[0] += (xi_{i-1/2} . p_{i-1/2}) dD_i
@@ -204,7 +209,7 @@ int pm_adj_init(pm_plan plan, pm_state* st, pm_adj* adj, const pm_step_coef* las
  * Out: (s_{i-1}, p_{i-3/2}), (xi_{i-3/2}, pi_{i-1}), or at i = 1
  * (s_0, p_0), (xi_0, pi_0). */
 int pm_step_adj(pm_plan plan, pm_state* st, pm_adj* adj, const pm_step_coef* cur,
-                const pm_step_coef* prev, double coef, double* theta_bar,
+                const pm_step_coef* prev, double omega_m, double* theta_bar,
                 hipStream_t stream);
 
 /* Whole loops (native drivers of the two calls above).  coefs: host array of
@@ -214,10 +219,10 @@ int pm_step_adj(pm_plan plan, pm_state* st, pm_adj* adj, const pm_step_coef* cur
  * stores a there and leaves its kick to the next step's drift (the plan's
  * workspace holds alpha for the adjoint).  After pm_run_fwd, acc holds a_n
  * as after the step calls; after pm_run_adj its contents are unspecified. */
-int pm_run_fwd(pm_plan plan, pm_state* st, const pm_step_coef* coefs, int n, double coef,
+int pm_run_fwd(pm_plan plan, pm_state* st, const pm_step_coef* coefs, int n, double omega_m,
                hipStream_t stream);
 int pm_run_adj(pm_plan plan, pm_state* st, pm_adj* adj, const pm_step_coef* coefs, int n,
-               double coef, double* theta_bar, hipStream_t stream);
+               double omega_m, double* theta_bar, hipStream_t stream);
 
 /* ---- piecewise reverse from forward checkpoints (Sec. 3.5) ---------------- */
 /* Where the reverse-time integration drifts too far from the forward
@@ -238,7 +243,7 @@ typedef struct {
 
 /* pm_run_fwd that also copies p_{j-1/2} (before step j) and s_j (after step
  * j) into checkpoint j.  Extra traffic: two state copies per checkpoint. */
-int pm_run_fwd_ckpt(pm_plan plan, pm_state* st, const pm_step_coef* coefs, int n, double coef,
+int pm_run_fwd_ckpt(pm_plan plan, pm_state* st, const pm_step_coef* coefs, int n, double omega_m,
                     const pm_checkpoints* ck, hipStream_t stream);
 
 /* pm_run_adj resuming from the checkpoints: the reverse step j + 1 lands its
@@ -249,7 +254,7 @@ int pm_run_fwd_ckpt(pm_plan plan, pm_state* st, const pm_step_coef* coefs, int n
  * the adjoint runs on the forward trajectory itself.  Errors: PM_EINVAL for
  * unordered or out-of-range steps or NULL buffers (before any launch). */
 int pm_run_adj_ckpt(pm_plan plan, pm_state* st, pm_adj* adj, const pm_step_coef* coefs, int n,
-                    double coef, const pm_checkpoints* ck, double* theta_bar, hipStream_t stream);
+                    double omega_m, const pm_checkpoints* ck, double* theta_bar, hipStream_t stream);
 
 /* ---- a11: objective and its VJP (Sec. 4.2) ------------------------------- */
 /* delta = paint(x) N_c/N_p - 1; *J = (1/N_c) sum (delta - target)^2 (device
@@ -262,6 +267,23 @@ int pm_density_mse(pm_plan plan, const void* disp, const void* target, double* J
 /* Density contrast of a unit-mass paint: delta = paint(x) N_c/N_p - 1
  * (the field the objective compares; [N_c] mesh dtype, overwritten). */
 int pm_density(pm_plan plan, const void* disp, void* delta, hipStream_t stream);
+
+/* ---- support: power spectrum (Sec. 2.1, eq. Plin) -------------------------- */
+/* The paper defines P through <delta(k) delta(k')> = V P(k).  For the half
+ * spectrum delta_k of a real field (pm_fft(+1); [n][n][n/2+1] mesh-dtype
+ * complex, cubic mesh n^3 and cubic box L = cfg.box[0]), with the integer
+ * wavevector m (k = 2 pi m / L), shell b = round(|m|) for b = 1..n/2:
+ *   P[b-1]     = sum_shell w |delta_k V / N_c|^2 / V / sum_shell w,
+ *   k[b-1]     = (2 pi / L) sum_shell w |m| / sum_shell w,
+ *   count[b-1] = sum_shell w,
+ * w = 2 for modes with 0 < mz < n/2 (each stands for its conjugate too) and
+ * 1 on the mz = 0 and mz = n/2 planes.  No window deconvolution.  k, P,
+ * count: device double [n/2], overwritten.  The shell sums are reduced in a
+ * fixed order (no atomics), so repeated calls are bitwise equal.  Scratch:
+ * the plan's spectrum buffers.  Errors: PM_EINVAL (NULL pointers),
+ * PM_EUNSUPPORTED (mesh or box not cubic). */
+int pm_power_spectrum(pm_plan plan, const void* delta_k, double* k, double* P, double* count,
+                      hipStream_t stream);
 
 /* ---- support: cosmology tables (Appendix A, eqs. G_eval and Plin) --------- */
 typedef struct {
@@ -364,14 +386,14 @@ int pm_lightcone_vjp(pm_plan plan, const pm_lc_step* st, const void* s0, const v
  * dJ/dz_k there).  p_k = p_{k-1/2} + a_k Kb_k, so a cotangent p_bar of p_k
  * also reaches a_k:
  *   xi += x_bar + Kb c,  pi += p_bar,
- *   theta_bar[0] += dKb sum(p_bar . acc) + 1.5 Kb (*coef_bar),
- * where c and *coef_bar are pm_force_vjp's disp_bar and coef_bar for the
- * cotangent p_bar at x_k, and acc = a_k.  c, acc and coef_bar may be NULL
- * (Kb = 0: p_0, or a kick the caller's own VJP already covers).  xi, pi,
- * x_bar, p_bar, c, acc: [3][N_p] mesh dtype. */
+ *   theta_bar[0] += dKb sum(p_bar . acc) + Kb (*omega_m_bar),
+ * where c and *omega_m_bar are pm_force_vjp's disp_bar and omega_m_bar for
+ * the cotangent p_bar at x_k, and acc = a_k.  c, acc and omega_m_bar may be
+ * NULL (Kb = 0: p_0, or a kick the caller's own VJP already covers).  xi,
+ * pi, x_bar, p_bar, c, acc: [3][N_p] mesh dtype. */
 int pm_adj_bump(pm_plan plan, void* xi, void* pi, const void* x_bar, const void* p_bar,
                 const void* c, double Kb, double dKb, const void* acc,
-                const double* coef_bar, double* theta_bar, hipStream_t stream);
+                const double* omega_m_bar, double* theta_bar, hipStream_t stream);
 
 /* The kick and drift operators of eq. KDFK on their own (out may alias the
  * input): p_out = p + acc K (p, p_out state dtype, acc mesh dtype) and

@@ -186,13 +186,15 @@ class Plan:
         self._c(lib().pm_fft(self._h, -1, _ptr(src), _ptr(out), batch, _stream()))
         return out
 
-    def poisson_grad(self, delta_k, coef, out=None):
+    def poisson_grad(self, delta_k, omega_m, out=None):
+        """Poisson gradient (pm_poisson_grad): [3] half spectra T_j delta_k,
+        T_j = i k_j 1.5 omega_m / k^2."""
         nsp = int(np.prod(self.spec_shape))
         self._t(delta_k, self.cdt, nsp, "delta_k")
         if out is None:
             out = torch.empty((3,) + self.spec_shape, dtype=self.cdt, device=self.device)
         self._t(out, self.cdt, 3 * nsp, "out")
-        self._c(lib().pm_poisson_grad(self._h, _ptr(delta_k), _ptr(out), float(coef), _stream()))
+        self._c(lib().pm_poisson_grad(self._h, _ptr(delta_k), _ptr(out), float(omega_m), _stream()))
         return out
 
     def readout(self, disp, mesh, out=None):
@@ -205,25 +207,26 @@ class Plan:
         self._c(lib().pm_readout(self._h, _ptr(disp), _ptr(mesh), nch, _ptr(out), _stream()))
         return out
 
-    def force(self, disp, coef, out=None):
+    def force(self, disp, omega_m, out=None):
+        """PM force (pm_force): accelerations [3, N_p] at q + disp."""
         self._disp(disp)
         if out is None:
             out = torch.empty((3, self.n_particles), dtype=self.mdt, device=self.device)
         self._t(out, self.mdt, 3 * self.n_particles, "acc")
-        self._c(lib().pm_force(self._h, _ptr(disp), float(coef), _ptr(out), _stream()))
+        self._c(lib().pm_force(self._h, _ptr(disp), float(omega_m), _ptr(out), _stream()))
         return out
 
-    def force_vjp(self, disp, acc_bar, coef, want_acc=True, out=None, coef_bar=None):
-        """(disp_bar, coef_bar (device FP64 scalar, +=), acc or None); `out`
-        and `coef_bar` may be given to reuse buffers."""
+    def force_vjp(self, disp, acc_bar, omega_m, want_acc=True, out=None, omega_m_bar=None):
+        """(disp_bar, omega_m_bar (device FP64 scalar, +=), acc or None);
+        `out` and `omega_m_bar` may be given to reuse buffers."""
         self._disp(disp)
         self._t(acc_bar, self.mdt, 3 * self.n_particles, "acc_bar")
         xbar = torch.empty((3, self.n_particles), dtype=self.mdt, device=self.device) if out is None else \
             self._t(out, self.mdt, 3 * self.n_particles, "out")
         acc = torch.empty_like(xbar) if want_acc else None
-        cbar = torch.zeros(1, dtype=torch.float64, device=self.device) if coef_bar is None else \
-            self._t(coef_bar, torch.float64, 1, "coef_bar")
-        self._c(lib().pm_force_vjp(self._h, _ptr(disp), _ptr(acc_bar), float(coef), _ptr(xbar), _ptr(cbar),
+        cbar = torch.zeros(1, dtype=torch.float64, device=self.device) if omega_m_bar is None else \
+            self._t(omega_m_bar, torch.float64, 1, "omega_m_bar")
+        self._c(lib().pm_force_vjp(self._h, _ptr(disp), _ptr(acc_bar), float(omega_m), _ptr(xbar), _ptr(cbar),
                                    _ptr(acc), _stream()))
         return xbar, cbar, acc
 
@@ -243,40 +246,40 @@ class Plan:
     def _adj(adj):
         return PmAdj(adj["xi"].data_ptr(), adj["pi"].data_ptr())
 
-    def fwd_init(self, state, first, coef):
+    def fwd_init(self, state, first, omega_m):
         self._c(lib().pm_fwd_init(self._h, ctypes.byref(self._st(state)), ctypes.byref(step_coef(first)),
-                                  float(coef), _stream()))
+                                  float(omega_m), _stream()))
 
-    def step_fwd(self, state, cur, nxt, coef):
+    def step_fwd(self, state, cur, nxt, omega_m):
         n = ctypes.byref(step_coef(nxt)) if nxt is not None else None
         self._c(lib().pm_step_fwd(self._h, ctypes.byref(self._st(state)), ctypes.byref(step_coef(cur)), n,
-                                  float(coef), _stream()))
+                                  float(omega_m), _stream()))
 
-    def adj_init(self, state, adj, last, coef, theta_bar):
+    def adj_init(self, state, adj, last, omega_m, theta_bar):
         self._t(theta_bar, torch.float64, 2, "theta_bar")
         self._c(lib().pm_adj_init(self._h, ctypes.byref(self._st(state)), ctypes.byref(self._adj(adj)),
-                                  ctypes.byref(step_coef(last)), float(coef), _ptr(theta_bar), _stream()))
+                                  ctypes.byref(step_coef(last)), float(omega_m), _ptr(theta_bar), _stream()))
 
-    def step_adj(self, state, adj, cur, prev, coef, theta_bar):
+    def step_adj(self, state, adj, cur, prev, omega_m, theta_bar):
         self._t(theta_bar, torch.float64, 2, "theta_bar")
         pv = ctypes.byref(step_coef(prev)) if prev is not None else None
         self._c(lib().pm_step_adj(self._h, ctypes.byref(self._st(state)), ctypes.byref(self._adj(adj)),
-                                  ctypes.byref(step_coef(cur)), pv, float(coef), _ptr(theta_bar), _stream()))
+                                  ctypes.byref(step_coef(cur)), pv, float(omega_m), _ptr(theta_bar), _stream()))
 
     def _coef_array(self, coefs):
         coefs = np.asarray(coefs, dtype=np.float64).reshape(-1, 6)
         arr = (PmStepCoef * len(coefs))(*[step_coef(r) for r in coefs])
         return arr, len(coefs)
 
-    def run_fwd(self, state, coefs, coef):
+    def run_fwd(self, state, coefs, omega_m):
         arr, n = self._coef_array(coefs)
-        self._c(lib().pm_run_fwd(self._h, ctypes.byref(self._st(state)), arr, n, float(coef), _stream()))
+        self._c(lib().pm_run_fwd(self._h, ctypes.byref(self._st(state)), arr, n, float(omega_m), _stream()))
 
-    def run_adj(self, state, adj, coefs, coef, theta_bar):
+    def run_adj(self, state, adj, coefs, omega_m, theta_bar):
         self._t(theta_bar, torch.float64, 2, "theta_bar")
         arr, n = self._coef_array(coefs)
         self._c(lib().pm_run_adj(self._h, ctypes.byref(self._st(state)), ctypes.byref(self._adj(adj)), arr, n,
-                                 float(coef), _ptr(theta_bar), _stream()))
+                                 float(omega_m), _ptr(theta_bar), _stream()))
 
     def new_checkpoints(self, steps):
         """Buffers for forward checkpoints at the given steps (1..n): a dict
@@ -300,19 +303,19 @@ class Plan:
                           ctypes.cast(pp, ctypes.POINTER(ctypes.c_void_p)))
         return c, (steps, sp, pp)     # keep the arrays alive for the call
 
-    def run_fwd_ckpt(self, state, coefs, coef, checkpoints):
+    def run_fwd_ckpt(self, state, coefs, omega_m, checkpoints):
         arr, n = self._coef_array(coefs)
         c, keep = self._ck(checkpoints)
-        self._c(lib().pm_run_fwd_ckpt(self._h, ctypes.byref(self._st(state)), arr, n, float(coef),
+        self._c(lib().pm_run_fwd_ckpt(self._h, ctypes.byref(self._st(state)), arr, n, float(omega_m),
                                       ctypes.byref(c) if c is not None else None, _stream()))
         del keep
 
-    def run_adj_ckpt(self, state, adj, coefs, coef, checkpoints, theta_bar):
+    def run_adj_ckpt(self, state, adj, coefs, omega_m, checkpoints, theta_bar):
         self._t(theta_bar, torch.float64, 2, "theta_bar")
         arr, n = self._coef_array(coefs)
         c, keep = self._ck(checkpoints)
         self._c(lib().pm_run_adj_ckpt(self._h, ctypes.byref(self._st(state)), ctypes.byref(self._adj(adj)), arr,
-                                      n, float(coef), ctypes.byref(c) if c is not None else None,
+                                      n, float(omega_m), ctypes.byref(c) if c is not None else None,
                                       _ptr(theta_bar), _stream()))
         del keep
 
@@ -367,17 +370,17 @@ class Plan:
                                        _ptr(obs_step), _ptr(obs_bar), *[_ptr(t) for t in outs], _ptr(theta_bar),
                                        _stream()))
 
-    def adj_bump(self, xi, pi, x_bar, p_bar, c, Kb, dKb, acc, coef_bar, theta_bar):
+    def adj_bump(self, xi, pi, x_bar, p_bar, c, Kb, dKb, acc, omega_m_bar, theta_bar):
         """pm_adj_bump: xi += x_bar + Kb c, pi += p_bar and the theta_bar terms."""
         for t, nm in ((xi, "xi"), (pi, "pi"), (x_bar, "x_bar"), (p_bar, "p_bar")):
             self._mesh3(t, nm)
         self._mesh3(c, "c")
         self._mesh3(acc, "acc")
-        if coef_bar is not None:
-            self._t(coef_bar, torch.float64, 1, "coef_bar")
+        if omega_m_bar is not None:
+            self._t(omega_m_bar, torch.float64, 1, "omega_m_bar")
         self._t(theta_bar, torch.float64, 2, "theta_bar")
         self._c(lib().pm_adj_bump(self._h, _ptr(xi), _ptr(pi), _ptr(x_bar), _ptr(p_bar), _ptr(c), float(Kb),
-                                  float(dKb), _ptr(acc), _ptr(coef_bar), _ptr(theta_bar), _stream()))
+                                  float(dKb), _ptr(acc), _ptr(omega_m_bar), _ptr(theta_bar), _stream()))
 
     def kick(self, p, acc, K, out=None):
         """pm_kick: out = p + acc K (out may be p)."""
@@ -394,6 +397,20 @@ class Plan:
         out = torch.empty_like(s) if out is None else self._state3(out, "s_out")
         self._c(lib().pm_drift(self._h, _ptr(s), _ptr(p), float(D), _ptr(out), _stream()))
         return out
+
+    def power_spectrum(self, field, spectrum=False):
+        """Shell-averaged power spectrum (pm_power_spectrum) of a real field
+        ([n, n, n] mesh dtype; transformed with pm_fft first), or of a half
+        spectrum when spectrum=True.  Returns device FP64 tensors (k, P,
+        count) of n/2 shells b = 1..n/2 (k in h/Mpc for a box in Mpc/h)."""
+        if spectrum:
+            dk = self._t(field, self.cdt, int(np.prod(self.spec_shape)), "delta_k")
+        else:
+            dk = self.fft_r2c(self._t(field, self.mdt, self.n_cells, "field"))
+        nb = self.mesh[0] // 2
+        k, P, cnt = (torch.empty(nb, dtype=torch.float64, device=self.device) for _ in range(3))
+        self._c(lib().pm_power_spectrum(self._h, _ptr(dk), _ptr(k), _ptr(P), _ptr(cnt), _stream()))
+        return k, P, cnt
 
     # ---- initial conditions -------------------------------------------------
     def lpt(self, omega, cosmo, ic, state):

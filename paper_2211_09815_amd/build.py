@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpm.so")
-SOURCES = ["api.hip", "fft.hip", "fft_lines.hip", "fft_z.hip", "fft_fused.hip", "paint.hip", "particles.hip", "cosmo.hip", "lpt.hip", "lightcone.hip", "stream.hip"]
+SOURCES = ["api.hip", "fft.hip", "fft_lines.hip", "fft_z.hip", "fft_fused.hip", "paint.hip", "particles.hip", "cosmo.hip", "lpt.hip", "lightcone.hip", "spectrum.hip", "stream.hip"]
 ARCH = "gfx950"
 
 

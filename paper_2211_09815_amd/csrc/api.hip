@@ -139,42 +139,49 @@ T* mesh_ptr(Plan* p, int i) { return static_cast<T*>(p->mesh[i]); }
 template <typename T>
 cplx<T>* spec_ptr(Plan* p, int i) { return static_cast<cplx<T>*>(p->spec[i]); }
 
-// coefficient of the fused Poisson multiplier: coef * N_c / N_p (delta = rho N_c/N_p - 1)
-double mass_coef(const Plan* p, double coef) { return coef * double(p->ncell) / double(p->nptcl); }
+// The Poisson equation for phi~ = a phi in units H0 = 1 has the source
+// 1.5 Omega_m delta (Sec. 2.2); every entry point takes Omega_m and forms the
+// coefficient here, so callers never repeat the 1.5.
+double poisson_coef(double omega_m) { return 1.5 * omega_m; }
+
+// coefficient of the fused Poisson multiplier: 1.5 Omega_m N_c / N_p (delta = rho N_c/N_p - 1)
+double mass_coef(const Plan* p, double omega_m) {
+  return poisson_coef(omega_m) * double(p->ncell) / double(p->nptcl);
+}
 
 // Both follow a paint made with defer_z: the R2C adds the paint's z faces.
 template <typename T>
-int force_fields(Plan* p, double coef, hipStream_t st) {
+int force_fields(Plan* p, double omega_m, hipStream_t st) {
   // mesh0 holds the painted mass; leaves g_0..2 in mesh0..2
   T* reals[3] = {mesh_ptr<T>(p, 0), mesh_ptr<T>(p, 1), mesh_ptr<T>(p, 2)};
   cplx<T>* specs[3] = {spec_ptr<T>(p, 0), spec_ptr<T>(p, 1), spec_ptr<T>(p, 2)};
   const ZFold zf = paint_zfold(p);
-  return fft_spectral_op<T>(p, mesh_shape(p), SPEC_GRAD3, reals, specs, T(mass_coef(p, coef)), &zf, st);
+  return fft_spectral_op<T>(p, mesh_shape(p), SPEC_GRAD3, reals, specs, T(mass_coef(p, omega_m)), &zf, st);
 }
 
 template <typename T>
-int vjp_fields(Plan* p, double coef, hipStream_t st) {
+int vjp_fields(Plan* p, double omega_m, hipStream_t st) {
   // mesh0..3 hold [rho, gbar_x, gbar_y, gbar_z]; leaves [g_x, g_y, g_z, rhobar]
   T* reals[4] = {mesh_ptr<T>(p, 0), mesh_ptr<T>(p, 1), mesh_ptr<T>(p, 2), mesh_ptr<T>(p, 3)};
   cplx<T>* specs[4] = {spec_ptr<T>(p, 0), spec_ptr<T>(p, 1), spec_ptr<T>(p, 2), spec_ptr<T>(p, 3)};
   const ZFold zf = paint_zfold(p);
-  return fft_spectral_op<T>(p, mesh_shape(p), SPEC_ADJ4, reals, specs, T(mass_coef(p, coef)), &zf, st);
+  return fft_spectral_op<T>(p, mesh_shape(p), SPEC_ADJ4, reals, specs, T(mass_coef(p, omega_m)), &zf, st);
 }
 
 // paint (with the z faces deferred) and the force or VJP fields
-int paint_force_fields(Plan* p, DriftMode mode, PaintArgs pa, double coef, hipStream_t st) {
+int paint_force_fields(Plan* p, DriftMode mode, PaintArgs pa, double omega_m, hipStream_t st) {
   pa.defer_z = true;
   if (int rc = paint_launch(p, mode, pa, st)) return rc;
-  return p->cfg.mesh_dtype == PM_F64 ? force_fields<double>(p, coef, st) : force_fields<float>(p, coef, st);
+  return p->cfg.mesh_dtype == PM_F64 ? force_fields<double>(p, omega_m, st) : force_fields<float>(p, omega_m, st);
 }
-int paint_vjp_fields(Plan* p, DriftMode mode, PaintArgs pa, double coef, hipStream_t st) {
+int paint_vjp_fields(Plan* p, DriftMode mode, PaintArgs pa, double omega_m, hipStream_t st) {
   pa.defer_z = true;
   if (int rc = paint_launch(p, mode, pa, st)) return rc;
-  return p->cfg.mesh_dtype == PM_F64 ? vjp_fields<double>(p, coef, st) : vjp_fields<float>(p, coef, st);
+  return p->cfg.mesh_dtype == PM_F64 ? vjp_fields<double>(p, omega_m, st) : vjp_fields<float>(p, omega_m, st);
 }
 
-int check_coef(Plan* p, double coef) {
-  if (!std::isfinite(coef) || coef <= 0) return set_error(p, PM_EINVAL, "coef must be finite and > 0");
+int check_omega_m(Plan* p, double omega_m) {
+  if (!std::isfinite(omega_m) || omega_m <= 0) return set_error(p, PM_EINVAL, "omega_m must be finite and > 0");
   return PM_OK;
 }
 
@@ -189,7 +196,7 @@ int check_step(Plan* p, const pm_step_coef* c, const char* name) {
 size_t state_bytes(const Plan* p);
 
 int check_adj_args(Plan* p, const pm_state* stt, const pm_adj* adj, const pm_step_coef* cur,
-                   const pm_step_coef* prev, double coef, const double* theta_bar) {
+                   const pm_step_coef* prev, double omega_m, const double* theta_bar) {
   if (!stt || !adj) return set_error(p, PM_EINVAL, "state or adjoint is NULL");
   if (int rc = check_ptr(p, stt->s, "state.s")) return rc;
   if (int rc = check_ptr(p, stt->p, "state.p")) return rc;
@@ -199,13 +206,13 @@ int check_adj_args(Plan* p, const pm_state* stt, const pm_adj* adj, const pm_ste
   if (int rc = check_step(p, cur, "cur")) return rc;
   if (prev)
     if (int rc = check_step(p, prev, "prev")) return rc;
-  return check_coef(p, coef);
+  return check_omega_m(p, omega_m);
 }
 
 // Reverse step i (eq. KDFKO_adj with merged kicks).  With s_set, the drift
 // lands on the stored positions s_{i-1} instead of s_i - p_{i-1/2} D_i; with
 // p_set, p_{i-3/2} is replaced by the stored momentum after the kick.
-int step_adj(Plan* p, pm_state* stt, pm_adj* adj, const pm_step_coef* cur, const pm_step_coef* prev, double coef,
+int step_adj(Plan* p, pm_state* stt, pm_adj* adj, const pm_step_coef* cur, const pm_step_coef* prev, double omega_m,
              double* theta_bar, const void* s_set, const void* p_set, hipStream_t st) {
   PaintArgs pa{};
   pa.s = stt->s;
@@ -218,7 +225,7 @@ int step_adj(Plan* p, pm_state* stt, pm_adj* adj, const pm_step_coef* cur, const
   pa.D = cur->D;
   pa.partials = p->partials;
   pa.s_set = s_set;
-  if (int rc = paint_vjp_fields(p, s_set ? DRIFT_SET : DRIFT_ADJ, pa, coef, st)) return rc;
+  if (int rc = paint_vjp_fields(p, s_set ? DRIFT_SET : DRIFT_ADJ, pa, omega_m, st)) return rc;
   const double K = cur->Ka + (prev ? prev->Kb : 0.0);
   const double dK = cur->dKa + (prev ? prev->dKb : 0.0);
   GatherArgs ga{};
@@ -231,10 +238,11 @@ int step_adj(Plan* p, pm_state* stt, pm_adj* adj, const pm_step_coef* cur, const
   ga.K = K;
   ga.binned = true;
   if (int rc = gather_launch(p, GATHER_KICK_ADJ, ga, st)) return rc;
-  // theta_bar[0] += (xi.p) dD  (drift partials)  +  (pi.a)(dK + K 1.5/coef)  (tile partials)
+  // theta_bar[0] += (xi.p) dD  (drift partials)  +  (pi.a)(dK + K/Omega_m)  (tile partials; a is
+  // proportional to Omega_m, so zeta = (pi.a)/Omega_m)
   const double fd[4] = {cur->dD, 0.0, 0.0, 0.0};
   if (int rc = reduce_partials(p, blocks_for_particles(p), fd, theta_bar, true, st)) return rc;
-  const double fk[4] = {0.0, dK + K * 1.5 / coef, 0.0, 0.0};
+  const double fk[4] = {0.0, dK + K / omega_m, 0.0, 0.0};
   if (int rc = reduce_buffer(p, p->tile_partials, p->ntiles, fk, theta_bar, true, st)) return rc;
   if (p_set) PM_HIP_CHECK(p, hipMemcpyAsync(stt->p, p_set, state_bytes(p), hipMemcpyDeviceToDevice, st));
   return PM_OK;
@@ -474,13 +482,14 @@ int pm_fft(pm_plan h, int dir, void* in, void* out, int batch, hipStream_t st) {
                            p->ncell, float(2.0 / double(p->ncell)), st);
 }
 
-int pm_poisson_grad(pm_plan h, const void* delta_k, void* grad_k, double coef, hipStream_t st) {
+int pm_poisson_grad(pm_plan h, const void* delta_k, void* grad_k, double omega_m, hipStream_t st) {
   CHECK_PLAN(h);
   if (int rc = check_ptr(p, delta_k, "delta_k")) return rc;
   if (int rc = check_ptr(p, grad_k, "grad_k")) return rc;
-  if (int rc = check_coef(p, coef)) return rc;
+  if (int rc = check_omega_m(p, omega_m)) return rc;
   if (int rc = set_device(p)) return rc;
   const FftShape s = mesh_shape(p);
+  const double coef = poisson_coef(omega_m);
   if (p->cfg.mesh_dtype == PM_F64)
     return poisson_grad_spec<double>(p, s, static_cast<const cplx<double>*>(delta_k),
                                      static_cast<cplx<double>*>(grad_k), coef, st);
@@ -503,17 +512,17 @@ int pm_readout(pm_plan h, const void* disp, const void* mesh, int nch, void* out
   return gather_launch(p, GATHER_PLAIN, a, st);
 }
 
-int pm_force(pm_plan h, const void* disp, double coef, void* acc, hipStream_t st) {
+int pm_force(pm_plan h, const void* disp, double omega_m, void* acc, hipStream_t st) {
   CHECK_PLAN(h);
   if (int rc = check_ptr(p, disp, "disp")) return rc;
   if (int rc = check_ptr(p, acc, "acc")) return rc;
-  if (int rc = check_coef(p, coef)) return rc;
+  if (int rc = check_omega_m(p, omega_m)) return rc;
   if (int rc = set_device(p)) return rc;
   PaintArgs pa{};
   pa.s = disp;
   pa.unit = 1;
   pa.mesh = p->mesh[0];
-  if (int rc = paint_force_fields(p, DRIFT_NONE, pa, coef, st)) return rc;
+  if (int rc = paint_force_fields(p, DRIFT_NONE, pa, omega_m, st)) return rc;
   GatherArgs ga{};
   ga.s = disp;
   ga.mesh = p->mesh[0];
@@ -523,14 +532,14 @@ int pm_force(pm_plan h, const void* disp, double coef, void* acc, hipStream_t st
   return gather_launch(p, GATHER_PLAIN, ga, st);
 }
 
-int pm_force_vjp(pm_plan h, const void* disp, const void* acc_bar, double coef, void* disp_bar, double* coef_bar,
-                 void* acc_out, hipStream_t st) {
+int pm_force_vjp(pm_plan h, const void* disp, const void* acc_bar, double omega_m, void* disp_bar,
+                 double* omega_m_bar, void* acc_out, hipStream_t st) {
   CHECK_PLAN(h);
   if (int rc = check_ptr(p, disp, "disp")) return rc;
   if (int rc = check_ptr(p, acc_bar, "acc_bar")) return rc;
   if (int rc = check_ptr(p, disp_bar, "disp_bar")) return rc;
-  if (int rc = check_ptr(p, coef_bar, "coef_bar")) return rc;
-  if (int rc = check_coef(p, coef)) return rc;
+  if (int rc = check_ptr(p, omega_m_bar, "omega_m_bar")) return rc;
+  if (int rc = check_omega_m(p, omega_m)) return rc;
   if (int rc = set_device(p)) return rc;
   PaintArgs pa{};
   pa.s = disp;
@@ -538,7 +547,7 @@ int pm_force_vjp(pm_plan h, const void* disp, const void* acc_bar, double coef, 
   pa.w = acc_bar;
   pa.nw = 3;
   pa.mesh = p->mesh[0];
-  if (int rc = paint_vjp_fields(p, DRIFT_NONE, pa, coef, st)) return rc;
+  if (int rc = paint_vjp_fields(p, DRIFT_NONE, pa, omega_m, st)) return rc;
   GatherArgs ga{};
   ga.s = disp;
   ga.mesh = p->mesh[0];
@@ -548,23 +557,24 @@ int pm_force_vjp(pm_plan h, const void* disp, const void* acc_bar, double coef, 
   ga.cot = acc_bar;
   ga.binned = true;
   if (int rc = gather_launch(p, GATHER_VJP, ga, st)) return rc;
-  const double f[4] = {0.0, 1.0 / coef, 0.0, 0.0};
-  return reduce_buffer(p, p->tile_partials, p->ntiles, f, coef_bar, true, st);
+  // a is proportional to Omega_m: d(abar.a)/dOmega_m = (abar.a)/Omega_m
+  const double f[4] = {0.0, 1.0 / omega_m, 0.0, 0.0};
+  return reduce_buffer(p, p->tile_partials, p->ntiles, f, omega_m_bar, true, st);
 }
 
-int pm_fwd_init(pm_plan h, pm_state* stt, const pm_step_coef* first, double coef, hipStream_t st) {
+int pm_fwd_init(pm_plan h, pm_state* stt, const pm_step_coef* first, double omega_m, hipStream_t st) {
   CHECK_PLAN(h);
   if (!stt) return set_error(p, PM_EINVAL, "state is NULL");
   if (int rc = check_ptr(p, stt->s, "state.s")) return rc;
   if (int rc = check_ptr(p, stt->p, "state.p")) return rc;
   if (int rc = check_step(p, first, "first")) return rc;
-  if (int rc = check_coef(p, coef)) return rc;
+  if (int rc = check_omega_m(p, omega_m)) return rc;
   if (int rc = set_device(p)) return rc;
   PaintArgs pa{};
   pa.s = stt->s;
   pa.unit = 1;
   pa.mesh = p->mesh[0];
-  if (int rc = paint_force_fields(p, DRIFT_NONE, pa, coef, st)) return rc;
+  if (int rc = paint_force_fields(p, DRIFT_NONE, pa, omega_m, st)) return rc;
   GatherArgs ga{};
   ga.s = stt->s;
   ga.mesh = p->mesh[0];
@@ -575,7 +585,7 @@ int pm_fwd_init(pm_plan h, pm_state* stt, const pm_step_coef* first, double coef
   return gather_launch(p, GATHER_KICK_FWD, ga, st);
 }
 
-int pm_step_fwd(pm_plan h, pm_state* stt, const pm_step_coef* cur, const pm_step_coef* next, double coef,
+int pm_step_fwd(pm_plan h, pm_state* stt, const pm_step_coef* cur, const pm_step_coef* next, double omega_m,
                 hipStream_t st) {
   CHECK_PLAN(h);
   if (!stt) return set_error(p, PM_EINVAL, "state is NULL");
@@ -584,7 +594,7 @@ int pm_step_fwd(pm_plan h, pm_state* stt, const pm_step_coef* cur, const pm_step
   if (int rc = check_step(p, cur, "cur")) return rc;
   if (next)
     if (int rc = check_step(p, next, "next")) return rc;
-  if (int rc = check_coef(p, coef)) return rc;
+  if (int rc = check_omega_m(p, omega_m)) return rc;
   if (int rc = set_device(p)) return rc;
   PaintArgs pa{};
   pa.s = stt->s;
@@ -592,7 +602,7 @@ int pm_step_fwd(pm_plan h, pm_state* stt, const pm_step_coef* cur, const pm_step
   pa.unit = 1;
   pa.mesh = p->mesh[0];
   pa.D = cur->D;
-  if (int rc = paint_force_fields(p, DRIFT_FWD, pa, coef, st)) return rc;
+  if (int rc = paint_force_fields(p, DRIFT_FWD, pa, omega_m, st)) return rc;
   GatherArgs ga{};
   ga.s = stt->s;
   ga.mesh = p->mesh[0];
@@ -604,8 +614,8 @@ int pm_step_fwd(pm_plan h, pm_state* stt, const pm_step_coef* cur, const pm_step
   return gather_launch(p, GATHER_KICK_FWD, ga, st);
 }
 
-int pm_adj_init(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* last, double coef, double* theta_bar,
-                hipStream_t st) {
+int pm_adj_init(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* last, double omega_m,
+                double* theta_bar, hipStream_t st) {
   CHECK_PLAN(h);
   if (!stt || !adj) return set_error(p, PM_EINVAL, "state or adjoint is NULL");
   if (int rc = check_ptr(p, stt->s, "state.s")) return rc;
@@ -614,7 +624,7 @@ int pm_adj_init(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* last,
   if (int rc = check_ptr(p, adj->pi, "adj.pi")) return rc;
   if (int rc = check_ptr(p, theta_bar, "theta_bar")) return rc;
   if (int rc = check_step(p, last, "last")) return rc;
-  if (int rc = check_coef(p, coef)) return rc;
+  if (int rc = check_omega_m(p, omega_m)) return rc;
   if (int rc = set_device(p)) return rc;
   PaintArgs pa{};
   pa.s = stt->s;
@@ -622,7 +632,7 @@ int pm_adj_init(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* last,
   pa.w = adj->pi;
   pa.nw = 3;
   pa.mesh = p->mesh[0];
-  if (int rc = paint_vjp_fields(p, DRIFT_NONE, pa, coef, st)) return rc;
+  if (int rc = paint_vjp_fields(p, DRIFT_NONE, pa, omega_m, st)) return rc;
   GatherArgs ga{};
   ga.s = stt->s;
   ga.mesh = p->mesh[0];
@@ -634,26 +644,26 @@ int pm_adj_init(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* last,
   ga.K = last->Kb;
   ga.binned = true;
   if (int rc = gather_launch(p, GATHER_KICK_ADJ, ga, st)) return rc;
-  // theta_bar[0] += (pi.a) dKb + zeta Kb,  zeta = (pi.a) * 1.5 / coef
-  const double f[4] = {0.0, last->dKb + last->Kb * 1.5 / coef, 0.0, 0.0};
+  // theta_bar[0] += (pi.a) dKb + zeta Kb,  zeta = (pi.a) / Omega_m
+  const double f[4] = {0.0, last->dKb + last->Kb / omega_m, 0.0, 0.0};
   return reduce_buffer(p, p->tile_partials, p->ntiles, f, theta_bar, true, st);
 }
 
 int pm_step_adj(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* cur, const pm_step_coef* prev,
-                double coef, double* theta_bar, hipStream_t st) {
+                double omega_m, double* theta_bar, hipStream_t st) {
   CHECK_PLAN(h);
-  if (int rc = check_adj_args(p, stt, adj, cur, prev, coef, theta_bar)) return rc;
+  if (int rc = check_adj_args(p, stt, adj, cur, prev, omega_m, theta_bar)) return rc;
   if (int rc = set_device(p)) return rc;
-  return step_adj(p, stt, adj, cur, prev, coef, theta_bar, nullptr, nullptr, st);
+  return step_adj(p, stt, adj, cur, prev, omega_m, theta_bar, nullptr, nullptr, st);
 }
 
-int pm_run_fwd(pm_plan h, pm_state* stt, const pm_step_coef* coefs, int n, double coef, hipStream_t st) {
-  return pm_run_fwd_ckpt(h, stt, coefs, n, coef, nullptr, st);
+int pm_run_fwd(pm_plan h, pm_state* stt, const pm_step_coef* coefs, int n, double omega_m, hipStream_t st) {
+  return pm_run_fwd_ckpt(h, stt, coefs, n, omega_m, nullptr, st);
 }
 
-int pm_run_adj(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* coefs, int n, double coef,
+int pm_run_adj(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* coefs, int n, double omega_m,
                double* theta_bar, hipStream_t st) {
-  return pm_run_adj_ckpt(h, stt, adj, coefs, n, coef, nullptr, theta_bar, st);
+  return pm_run_adj_ckpt(h, stt, adj, coefs, n, omega_m, nullptr, theta_bar, st);
 }
 
 // The native loops.  With st->acc given, every kick is left pending: the
@@ -663,18 +673,18 @@ int pm_run_adj(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* coefs,
 // Kicks and drifts use the same fused multiply-adds in both places, so the
 // result is bitwise that of the step calls.  Without st->acc the loops are the
 // step calls.
-int pm_run_fwd_ckpt(pm_plan h, pm_state* stt, const pm_step_coef* coefs, int n, double coef,
+int pm_run_fwd_ckpt(pm_plan h, pm_state* stt, const pm_step_coef* coefs, int n, double omega_m,
                     const pm_checkpoints* ck, hipStream_t st) {
   CHECK_PLAN(h);
   if (!coefs || n < 1) return set_error(p, PM_EINVAL, "need n >= 1 step coefficients");
   if (int rc = check_checkpoints(p, ck, n)) return rc;
   const size_t bytes = state_bytes(p);
   if (!stt || !stt->acc) {
-    if (int rc = pm_fwd_init(h, stt, &coefs[0], coef, st)) return rc;
+    if (int rc = pm_fwd_init(h, stt, &coefs[0], omega_m, st)) return rc;
     for (int i = 0; i < n; ++i) {
       const int k = checkpoint_index(ck, i + 1);
       if (k >= 0) PM_HIP_CHECK(p, hipMemcpyAsync(ck->p[k], stt->p, bytes, hipMemcpyDeviceToDevice, st));
-      if (int rc = pm_step_fwd(h, stt, &coefs[i], i + 1 < n ? &coefs[i + 1] : nullptr, coef, st)) return rc;
+      if (int rc = pm_step_fwd(h, stt, &coefs[i], i + 1 < n ? &coefs[i + 1] : nullptr, omega_m, st)) return rc;
       if (k >= 0) PM_HIP_CHECK(p, hipMemcpyAsync(ck->s[k], stt->s, bytes, hipMemcpyDeviceToDevice, st));
     }
     return PM_OK;
@@ -683,14 +693,14 @@ int pm_run_fwd_ckpt(pm_plan h, pm_state* stt, const pm_step_coef* coefs, int n, 
   if (int rc = check_ptr(p, stt->p, "state.p")) return rc;
   for (int i = 0; i < n; ++i)
     if (int rc = check_step(p, &coefs[i], "coefs[i]")) return rc;
-  if (int rc = check_coef(p, coef)) return rc;
+  if (int rc = check_omega_m(p, omega_m)) return rc;
   if (int rc = set_device(p)) return rc;
   // a_0 = F(x_0); the kick p_0 + a_0 Ka_1 is left pending
   PaintArgs pa{};
   pa.s = stt->s;
   pa.unit = 1;
   pa.mesh = p->mesh[0];
-  if (int rc = paint_force_fields(p, DRIFT_NONE, pa, coef, st)) return rc;
+  if (int rc = paint_force_fields(p, DRIFT_NONE, pa, omega_m, st)) return rc;
   GatherArgs ga{};
   ga.s = stt->s;
   ga.mesh = p->mesh[0];
@@ -708,7 +718,7 @@ int pm_run_fwd_ckpt(pm_plan h, pm_state* stt, const pm_step_coef* coefs, int n, 
     pb.D = coefs[i].D;
     pb.kick_a = stt->acc;
     pb.Kp = Kp;
-    if (int rc = paint_force_fields(p, DRIFT_FWD, pb, coef, st)) return rc;
+    if (int rc = paint_force_fields(p, DRIFT_FWD, pb, omega_m, st)) return rc;
     // the drift has applied the kick and moved the particles: (s_{i+1}, p_{i+1/2})
     const int k = checkpoint_index(ck, i + 1);
     if (k >= 0) {
@@ -721,14 +731,14 @@ int pm_run_fwd_ckpt(pm_plan h, pm_state* stt, const pm_step_coef* coefs, int n, 
   return kick_flush(p, stt->p, stt->acc, Kp, false, nullptr, nullptr, 0.0, st);
 }
 
-int pm_run_adj_ckpt(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* coefs, int n, double coef,
+int pm_run_adj_ckpt(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* coefs, int n, double omega_m,
                     const pm_checkpoints* ck, double* theta_bar, hipStream_t st) {
   CHECK_PLAN(h);
   if (!coefs || n < 1) return set_error(p, PM_EINVAL, "need n >= 1 step coefficients");
   if (int rc = check_checkpoints(p, ck, n)) return rc;
   for (int i = 0; i < n; ++i)
     if (int rc = check_step(p, &coefs[i], "coefs[i]")) return rc;
-  if (int rc = pm_adj_init(h, stt, adj, &coefs[n - 1], coef, theta_bar, st)) return rc;
+  if (int rc = pm_adj_init(h, stt, adj, &coefs[n - 1], omega_m, theta_bar, st)) return rc;
   const int kn = checkpoint_index(ck, n);
   if (kn >= 0) PM_HIP_CHECK(p, hipMemcpyAsync(stt->p, ck->p[kn], state_bytes(p), hipMemcpyDeviceToDevice, st));
   const bool defer = stt->acc != nullptr;
@@ -742,7 +752,7 @@ int pm_run_adj_ckpt(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* c
     const pm_step_coef* cur = &coefs[i];
     const pm_step_coef* prev = i > 0 ? &coefs[i - 1] : nullptr;
     if (!defer) {
-      if (int rc = step_adj(p, stt, adj, cur, prev, coef, theta_bar, s_set, p_set, st)) return rc;
+      if (int rc = step_adj(p, stt, adj, cur, prev, omega_m, theta_bar, s_set, p_set, st)) return rc;
       continue;
     }
     PaintArgs pa{};
@@ -762,7 +772,7 @@ int pm_run_adj_ckpt(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* c
       pa.Kp = Kp;
       pa.Kx = Kx;
     }
-    if (int rc = paint_vjp_fields(p, s_set ? DRIFT_SET : DRIFT_ADJ, pa, coef, st)) return rc;
+    if (int rc = paint_vjp_fields(p, s_set ? DRIFT_SET : DRIFT_ADJ, pa, omega_m, st)) return rc;
     const double K = cur->Ka + (prev ? prev->Kb : 0.0);
     const double dK = cur->dKa + (prev ? prev->dKb : 0.0);
     // a and alpha at x_i, pi.a partials; the kick p -= a K, xi += alpha K is left pending
@@ -777,7 +787,7 @@ int pm_run_adj_ckpt(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* c
     if (int rc = gather_launch(p, GATHER_VJP, ga, st)) return rc;
     const double fd[4] = {cur->dD, 0.0, 0.0, 0.0};
     if (int rc = reduce_partials(p, blocks_for_particles(p), fd, theta_bar, true, st)) return rc;
-    const double fk[4] = {0.0, dK + K * 1.5 / coef, 0.0, 0.0};
+    const double fk[4] = {0.0, dK + K / omega_m, 0.0, 0.0};
     if (int rc = reduce_buffer(p, p->tile_partials, p->ntiles, fk, theta_bar, true, st)) return rc;
     pending = true;
     Kp = K;

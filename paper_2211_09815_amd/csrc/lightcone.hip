@@ -388,7 +388,7 @@ extern "C" int pm_lightcone_vjp(pm_plan h, const pm_lc_step* st, const void* s0,
 }
 
 extern "C" int pm_adj_bump(pm_plan h, void* xi, void* pi, const void* x_bar, const void* p_bar, const void* c,
-                           double Kb, double dKb, const void* acc, const double* coef_bar, double* theta_bar,
+                           double Kb, double dKb, const void* acc, const double* omega_m_bar, double* theta_bar,
                            hipStream_t stream) {
   LC_PLAN(h);
   const void* ptrs[] = {xi, pi, x_bar, p_bar, theta_bar};
@@ -404,15 +404,15 @@ extern "C" int pm_adj_bump(pm_plan h, void* xi, void* pi, const void* x_bar, con
   if (p->cfg.mesh_dtype == PM_F64)
     hipLaunchKernelGGL(k_adj_bump<double>, dim3(blocks), dim3(kThreads), 0, stream, static_cast<double*>(xi),
                        static_cast<double*>(pi), static_cast<const double*>(x_bar), static_cast<const double*>(p_bar),
-                       static_cast<const double*>(c), Kb, static_cast<const double*>(acc), coef_bar, n3, p->partials);
+                       static_cast<const double*>(c), Kb, static_cast<const double*>(acc), omega_m_bar, n3, p->partials);
   else
     hipLaunchKernelGGL(k_adj_bump<float>, dim3(blocks), dim3(kThreads), 0, stream, static_cast<float*>(xi),
                        static_cast<float*>(pi), static_cast<const float*>(x_bar), static_cast<const float*>(p_bar),
-                       static_cast<const float*>(c), float(Kb), static_cast<const float*>(acc), coef_bar, n3,
+                       static_cast<const float*>(c), float(Kb), static_cast<const float*>(acc), omega_m_bar, n3,
                        p->partials);
   PM_HIP_CHECK(p, hipGetLastError());
   timing_end(p, PM_K_LIGHTCONE, stream, double(n3) * mb * (6.0 + (c ? 1.0 : 0.0) + (acc ? 1.0 : 0.0)));
-  const double f[4] = {acc ? dKb : 0.0, coef_bar ? 1.5 * Kb : 0.0, 0.0, 0.0};
+  const double f[4] = {acc ? dKb : 0.0, omega_m_bar ? Kb : 0.0, 0.0, 0.0};
   if (f[0] == 0.0 && f[1] == 0.0) return PM_OK;
   return reduce_partials(p, blocks, f, theta_bar, true, stream);
 }

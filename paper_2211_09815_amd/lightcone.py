@@ -64,7 +64,7 @@ class LightCone:
         sim, plan = self.sim, self.sim.plan
         coefs, ic, lc = tables if tables is not None else self.tables(cosmo)
         n = len(coefs)
-        coef = 1.5 * cosmo.omega_m
+        om = cosmo.omega_m
         st = sim.state()
         plan.lpt(omega, cosmo, ic, st)
         self.obs.zero_()
@@ -73,9 +73,9 @@ class LightCone:
         s_prev, p_prev = self.x_tmp, self.p_tmp
         s_prev.copy_(sim.s)
         p_prev.copy_(sim.p)
-        plan.fwd_init(st, coefs[0], coef)
+        plan.fwd_init(st, coefs[0], om)
         for i in range(1, n + 1):
-            plan.step_fwd(st, coefs[i - 1], None, coef)
+            plan.step_fwd(st, coefs[i - 1], None, om)
             plan.lightcone(self._step(lc, cosmo, i), s_prev, p_prev, sim.s, sim.p, self.obs, self.obs_step,
                            self.counts[i:i + 1])
             if i < n:
@@ -99,7 +99,7 @@ class LightCone:
         coefs, ic, lc = tables if tables is not None else self.tables(cosmo)
         n = len(coefs)
         cnt = np.concatenate([self.n_obs, [0]])        # cnt[n + 1] = 0
-        coef = 1.5 * cosmo.omega_m
+        om = cosmo.omega_m
         st, adj = sim.state(), sim.adj()
         thb = sim.theta_bar.zero_()
         sim.xi.zero_()
@@ -114,7 +114,7 @@ class LightCone:
             # x_{k-1}, a_{k-1}, p_{k-1} from (s_k, p_{k-1/2})
             Ka, D = coefs[k - 1][0], coefs[k - 1][1]
             plan.drift(s, p_half, -D, out=self.x_tmp)
-            plan.force(self.x_tmp, coef, out=self.a[1])
+            plan.force(self.x_tmp, om, out=self.a[1])
             plan.kick(p_half, self.a[1], -Ka, out=self.p_tmp)
 
         # t_n: pm_adj_init's own VJP at x_n already carries Kb_n pi_n
@@ -125,12 +125,12 @@ class LightCone:
         if cnt[n] > 0:
             plan.lightcone_vjp(self._step(lc, cosmo, n), self.x_tmp, self.p_tmp, s, p, self.obs_step, obs_bar,
                                self.xb[1], self.pb[1], sim.xi, sim.pi, thb)
-        plan.adj_init(st, adj, coefs[n - 1], coef, thb)
+        plan.adj_init(st, adj, coefs[n - 1], om, thb)
         self._swap()
         if init_ahead:
             self.a.reverse()
         for i in range(n, 0, -1):
-            plan.step_adj(st, adj, coefs[i - 1], coefs[i - 2] if i > 1 else None, coef, thb)
+            plan.step_adj(st, adj, coefs[i - 1], coefs[i - 2] if i > 1 else None, om, thb)
             k = i - 1
             if k == 0:
                 if cnt[1] > 0:
@@ -146,7 +146,7 @@ class LightCone:
                                    obs_bar, self.xb[1], self.pb[1], self.xb[0], self.pb[0], thb)
             if need(k):
                 self.cb.zero_()
-                plan.force_vjp(s, self.pb[0], coef, want_acc=False, out=self.c, coef_bar=self.cb)
+                plan.force_vjp(s, self.pb[0], om, want_acc=False, out=self.c, omega_m_bar=self.cb)
                 Kb, dKb = coefs[k - 1][2], coefs[k - 1][5]
                 plan.adj_bump(sim.xi, sim.pi, self.xb[0], self.pb[0], self.c, Kb, dKb, self.a[0], self.cb, thb)
                 self._swap()

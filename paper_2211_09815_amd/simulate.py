@@ -67,9 +67,9 @@ class Simulation:
         st = self.state()
         self.plan.lpt(omega, cosmo, ic, st)
         if self.checkpoints is None:
-            self.plan.run_fwd(st, coefs, 1.5 * cosmo.omega_m)
+            self.plan.run_fwd(st, coefs, cosmo.omega_m)
         else:
-            self.plan.run_fwd_ckpt(st, coefs, 1.5 * cosmo.omega_m, self.checkpoints)
+            self.plan.run_fwd_ckpt(st, coefs, cosmo.omega_m, self.checkpoints)
         return coefs, ic
 
     def final_density(self, omega, cosmo):
@@ -84,9 +84,9 @@ class Simulation:
         self.pi.zero_()
         self.theta_bar.zero_()
         if self.checkpoints is None:
-            self.plan.run_adj(self.state(), self.adj(), coefs, 1.5 * cosmo.omega_m, self.theta_bar)
+            self.plan.run_adj(self.state(), self.adj(), coefs, cosmo.omega_m, self.theta_bar)
         else:
-            self.plan.run_adj_ckpt(self.state(), self.adj(), coefs, 1.5 * cosmo.omega_m, self.checkpoints,
+            self.plan.run_adj_ckpt(self.state(), self.adj(), coefs, cosmo.omega_m, self.checkpoints,
                                    self.theta_bar)
         g_omega = self.plan.lpt_vjp(omega, cosmo, ic, self.adj(), self.theta_bar)
         return J, g_omega, self.theta_bar.clone()

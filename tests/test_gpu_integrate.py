@@ -55,15 +55,15 @@ def test_forward_steps_vs_oracle(mdt, sdt, tol):
     s_ref, p_ref, a_ref, _ = oint.forward(q, s0, p0, coefs, F, store=False)
     st = plan.new_state(dev(soa(s0), sdt), dev(soa(p0), sdt))
     rows = np.concatenate([coefs, dcoefs], axis=1)
-    plan.run_fwd(st, rows, 0.45)
+    plan.run_fwd(st, rows, 0.3)
     assert rel_l2(aos(host(st["s"])), s_ref) < tol
     assert rel_l2(aos(host(st["p"])), p_ref) < tol
     assert rel_l2(aos(host(st["acc"])), a_ref) < tol
     # the per-step calls give the same result as the native loop
     st2 = plan.new_state(dev(soa(s0), sdt), dev(soa(p0), sdt))
-    plan.fwd_init(st2, rows[0], 0.45)
+    plan.fwd_init(st2, rows[0], 0.3)
     for i in range(len(rows)):
-        plan.step_fwd(st2, rows[i], rows[i + 1] if i + 1 < len(rows) else None, 0.45)
+        plan.step_fwd(st2, rows[i], rows[i + 1] if i + 1 < len(rows) else None, 0.3)
     assert rel_l2(host(st2["s"]), host(st["s"])) < (1e-14 if mdt == torch.float64 else 1e-6)
 
 
@@ -86,7 +86,7 @@ def test_adjoint_steps_vs_oracle(n, nm, mdt, sdt, tol):
     st = {"s": dev(soa(s_n), sdt), "p": dev(soa(p_n), sdt), "acc": dev(soa(a_n), mdt)}
     adj = {"xi": dev(soa(xi_n), mdt), "pi": dev(soa(pi_n), mdt)}
     tb = torch.zeros(2, dtype=torch.float64, device="cuda")
-    plan.run_adj(st, adj, np.concatenate([coefs, dcoefs], axis=1), 0.45, tb)
+    plan.run_adj(st, adj, np.concatenate([coefs, dcoefs], axis=1), 0.3, tb)
     assert rel_l2(aos(host(st["s"])), sb) < tol
     assert rel_l2(aos(host(st["p"])), pb) < tol
     assert rel_l2(aos(host(adj["xi"])), xi0) < tol
@@ -243,20 +243,20 @@ def test_native_loops_match_step_calls(mdt, sdt):
     for native in (True, False):
         st = plan.new_state(dev(soa(s0), sdt), dev(soa(p0), sdt))
         if native:
-            plan.run_fwd(st, rows, 0.45)
+            plan.run_fwd(st, rows, 0.3)
         else:
-            plan.fwd_init(st, rows[0], 0.45)
+            plan.fwd_init(st, rows[0], 0.3)
             for i in range(steps):
-                plan.step_fwd(st, rows[i], rows[i + 1] if i + 1 < steps else None, 0.45)
+                plan.step_fwd(st, rows[i], rows[i + 1] if i + 1 < steps else None, 0.3)
         fwd = (host(st["s"]), host(st["p"]), host(st["acc"]))
         adj = {"xi": dev(inputs.normal((3, n ** 3), 60, 0.01), mdt), "pi": dev(inputs.normal((3, n ** 3), 61, 0.01), mdt)}
         tb = torch.zeros(2, dtype=torch.float64, device="cuda")
         if native:
-            plan.run_adj(st, adj, rows, 0.45, tb)
+            plan.run_adj(st, adj, rows, 0.3, tb)
         else:
-            plan.adj_init(st, adj, rows[-1], 0.45, tb)
+            plan.adj_init(st, adj, rows[-1], 0.3, tb)
             for i in range(steps - 1, -1, -1):
-                plan.step_adj(st, adj, rows[i], rows[i - 1] if i > 0 else None, 0.45, tb)
+                plan.step_adj(st, adj, rows[i], rows[i - 1] if i > 0 else None, 0.3, tb)
         res.append(fwd + (host(st["s"]), host(st["p"]), host(adj["xi"]), host(adj["pi"]), host(tb)))
     for a, b in zip(res[0][:-1], res[1][:-1]):
         np.testing.assert_array_equal(a, b)
@@ -301,13 +301,13 @@ def test_piecewise_reverse_fp64_vs_oracle():
 def _ck_pass(plan, rows, s0, p0, sdt, mdt, ck, xi_n, pi_n, wipe_p=False):
     n3 = s0.shape[0]
     st = plan.new_state(dev(soa(s0), sdt), dev(soa(p0), sdt))
-    plan.run_fwd_ckpt(st, rows, 0.45, ck)
+    plan.run_fwd_ckpt(st, rows, 0.3, ck)
     fwd = (host(st["s"]), host(st["p"]))
     if wipe_p:
         st["p"].zero_()
     adj = {"xi": dev(xi_n, mdt), "pi": dev(pi_n, mdt)}
     tb = torch.zeros(2, dtype=torch.float64, device="cuda")
-    plan.run_adj_ckpt(st, adj, rows, 0.45, ck, tb)
+    plan.run_adj_ckpt(st, adj, rows, 0.3, ck, tb)
     assert adj["xi"].shape == (3, n3)
     return fwd, (host(st["s"]), host(st["p"]), host(adj["xi"]), host(adj["pi"]), host(tb))
 
@@ -333,7 +333,7 @@ def test_checkpoint_at_last_step_replaces_final_momentum():
     np.testing.assert_allclose(r1[4], r2[4], rtol=1e-12)     # theta_bar: FP64 partial sums in any order
     # the checkpointed forward loop leaves the state of the plain loop
     st = plan.new_state(dev(soa(s0), torch.float64), dev(soa(p0), torch.float64))
-    plan.run_fwd(st, rows, 0.45)
+    plan.run_fwd(st, rows, 0.3)
     np.testing.assert_array_equal(host(st["s"]), f1[0])
     np.testing.assert_array_equal(host(st["p"]), f1[1])
     # no checkpoints: the loops equal pm_run_fwd / pm_run_adj
@@ -341,7 +341,7 @@ def test_checkpoint_at_last_step_replaces_final_momentum():
     f3, r3 = _ck_pass(plan, rows, s0, p0, torch.float64, torch.float32, empty, xi_n, pi_n)
     adj = {"xi": dev(xi_n, torch.float32), "pi": dev(pi_n, torch.float32)}
     tb = torch.zeros(2, dtype=torch.float64, device="cuda")
-    plan.run_adj(st, adj, rows, 0.45, tb)
+    plan.run_adj(st, adj, rows, 0.3, tb)
     for a, b in zip(r3[:4], (host(st["s"]), host(st["p"]), host(adj["xi"]), host(adj["pi"]))):
         np.testing.assert_array_equal(a, b)
     np.testing.assert_allclose(r3[4], host(tb), rtol=1e-12)
@@ -361,7 +361,7 @@ def test_checkpoints_reject_bad_steps():
         ck["s"] = [torch.zeros((3, n ** 3), dtype=torch.float64, device="cuda") for _ in bad]
         ck["p"] = [torch.zeros((3, n ** 3), dtype=torch.float64, device="cuda") for _ in bad]
         with pytest.raises(PmError) as e:
-            plan.run_fwd_ckpt(st, rows, 0.45, ck)
+            plan.run_fwd_ckpt(st, rows, 0.3, ck)
         assert e.value.code == PM_EINVAL
 
 

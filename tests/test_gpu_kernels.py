@@ -110,7 +110,7 @@ def test_poisson_grad_vs_oracle(mdt):
     mesh = (16, 32, 8)
     plan = _plan(mesh, (2, 2, 2), mdt)
     dk = np.fft.rfftn(inputs.normal(mesh, 50))
-    g = host(plan.poisson_grad(dev(dk, plan.cdt), 0.45))
+    g = host(plan.poisson_grad(dev(dk, plan.cdt), 0.3))       # Omega_m; the oracle takes 1.5 Omega_m
     ref = opm.poisson_gradient(dk, mesh, 0.45)
     tol = 1e-6 if mdt == torch.float32 else 1e-14
     for j in range(3):
@@ -131,9 +131,9 @@ def test_force_vs_oracle(mesh, ptcl, scale, mdt, sdt):
     q, s = _particles(ptcl, r, 51, scale)
     s_dev = dev(soa(s), sdt)
     s_used = aos(host(s_dev))
-    coef = 0.45
-    a = aos(host(plan.force(s_dev, coef)))
-    ref = opm.force(q + s_used, mesh, len(q), coef)
+    om = 0.3                     # the oracle takes the Poisson coefficient 1.5 Omega_m
+    a = aos(host(plan.force(s_dev, om)))
+    ref = opm.force(q + s_used, mesh, len(q), 1.5 * om)
     tol = 1e-5 if mdt == torch.float32 else 1e-12
     assert rel_l2(a, ref) < tol
     assert np.abs(a.sum(0)).max() < (1e-4 if mdt == torch.float32 else 1e-10) * np.abs(a).sum()
@@ -148,13 +148,14 @@ def test_force_vjp_vs_oracle(mesh, ptcl, scale, mdt):
     q, s = _particles(ptcl, r, 52, scale)
     s_dev = dev(soa(s), torch.float64)
     abar = inputs.normal((len(q), 3), 53)
-    coef = 0.45
-    xbar, cbar, acc = plan.force_vjp(s_dev, dev(soa(abar), mdt), coef)
-    xb_ref, cb_ref, a_ref = opm.force_vjp(q + s, abar, mesh, len(q), coef)
+    om = 0.3
+    xbar, ombar, acc = plan.force_vjp(s_dev, dev(soa(abar), mdt), om)
+    xb_ref, cb_ref, a_ref = opm.force_vjp(q + s, abar, mesh, len(q), 1.5 * om)
     tol = 2e-5 if mdt == torch.float32 else 1e-11
     assert rel_l2(aos(host(xbar)), xb_ref) < tol
     assert rel_l2(aos(host(acc)), a_ref) < tol
-    assert abs(host(cbar)[0] - cb_ref) < tol * abs(cb_ref)
+    # the library reports d/dOmega_m = 1.5 d/dcoef
+    assert abs(host(ombar)[0] - 1.5 * cb_ref) < tol * abs(1.5 * cb_ref)
 
 
 @pytest.mark.parametrize("mesh,ptcl,scale", FORCE_CASES)

@@ -150,7 +150,7 @@ def test_adj_bump_kick_drift(mdt):
     tol = 1e-15 if mdt == torch.float64 else 3e-7
     assert rel_l2(host(txi), xi + xb + Kb * c) < tol
     assert rel_l2(host(tpi), pi + pb) < tol
-    ref = 1.0 + dKb * np.sum(pb * a) + 1.5 * Kb * 0.37
+    ref = 1.0 + dKb * np.sum(pb * a) + Kb * 0.37
     assert float(thb.cpu()[0]) == pytest.approx(ref, rel=1e-12)
     assert float(thb.cpu()[1]) == 2.0
     # no correction term (p_0): only the two sums
