@@ -36,7 +36,9 @@ def test_force_autograd_vs_oracle(mdt, tol):
     # the functional form returns the same numbers
     xb, ob = pmx.force_vjp(disp.detach(), dev(soa(w), mdt), 0.3, plan)
     np.testing.assert_array_equal(host(xb), host(disp.grad).astype(host(xb).dtype))
-    assert float(ob.cpu()) == float(om.grad)
+    # the FP64 per-tile partials behind omega_m_bar follow the order of the
+    # particles within a tile, which the binning's atomics set: equal to rounding
+    assert float(ob.cpu()) == pytest.approx(float(om.grad), rel=1e-13)
 
 
 def test_force_autograd_omega_m_central_difference():

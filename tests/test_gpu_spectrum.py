@@ -5,9 +5,11 @@ to Parseval's identity.  P is defined through <delta(k) delta(k')> = V P(k)
 (Sec. 2.1, eq. Plin).
 
 Tolerances: the shell counts are integers and must match exactly; the shell
-mean |k| does not depend on the field (1e-14); P follows the oracle to
-rounding in FP64 mode (1e-12 per shell) and to the float32 FFT's rounding in
-FP32 mode (2e-5 per shell, relative to that shell's value).
+mean |k| does not depend on the field and differs only by the order of its
+FP64 sum over up to ~1e5 modes (1e-12); P follows the oracle to rounding in
+FP64 mode (1e-11 per shell, the same summation-order bound) and to the
+float32 FFT's rounding in FP32 mode (2e-5 per shell, relative to that
+shell's value).
 """
 import numpy as np
 import pytest
@@ -44,13 +46,13 @@ def _compare(n, box, mdt, seed, tol):
     k, P, cnt = (host(t) for t in plan.power_spectrum(dev(x, mdt)))
     k_ref, P_ref, c_ref = oobj.power_spectrum(x, box)
     np.testing.assert_array_equal(cnt, c_ref)
-    np.testing.assert_allclose(k, k_ref, rtol=1e-14)
+    np.testing.assert_allclose(k, k_ref, rtol=1e-12)
     np.testing.assert_allclose(P, P_ref, rtol=tol)
     return plan, x
 
 
 @pytest.mark.parametrize("n", [4, 8, 16, 32, 64, 128])
-@pytest.mark.parametrize("mdt,tol", [(torch.float64, 1e-12), (torch.float32, 2e-5)])
+@pytest.mark.parametrize("mdt,tol", [(torch.float64, 1e-11), (torch.float32, 2e-5)])
 def test_power_spectrum_vs_oracle(n, mdt, tol):
     announce("power spectrum n=%d %s" % (n, mdt))
     _compare(n, 3.0 * n, mdt, 70 + n, tol)
