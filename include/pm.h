@@ -285,6 +285,20 @@ int pm_density(pm_plan plan, const void* disp, void* delta, hipStream_t stream);
 int pm_power_spectrum(pm_plan plan, const void* delta_k, double* k, double* P, double* count,
                       hipStream_t stream);
 
+/* Allocation-free form of pm_power_spectrum, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): no plan, and nothing is allocated or
+ * freed.  Same estimator and outputs as pm_power_spectrum for a cubic mesh
+ * of side n and box side `box` (Mpc/h); delta_k: [n][n][n/2+1] complex of
+ * mesh_dtype (PM_F32 or PM_F64).  Its partial sums live in a static device
+ * array of 12 MiB per GPU (held until the process ends), which covers every
+ * mesh side up to 1024; a larger n is refused with PM_ESHAPE.  Every call on
+ * one GPU uses that GPU's copy, so calls that overlap on one GPU (different
+ * streams or threads) race; callers order them.  Errors (pm_last_error(NULL)):
+ * PM_EINVAL, PM_ESHAPE, PM_EDEVICE. */
+int pm_power_spectrum_noalloc(int n, double box, int mesh_dtype, const void* delta_k, double* k,
+                              double* P, double* count, hipStream_t stream);
+
 /* ---- support: cosmology tables (Appendix A, eqs. G_eval and Plin) --------- */
 typedef struct {
     double omega_m, omega_b, h, n_s, sigma8, t_cmb;

@@ -132,6 +132,7 @@ _PROTOS = {
     "pm_kick": (c_int, [c_vp, c_vp, c_vp, c_dbl, c_vp, c_vp]),
     "pm_drift": (c_int, [c_vp, c_vp, c_vp, c_dbl, c_vp, c_vp]),
     "pm_power_spectrum": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "pm_power_spectrum_noalloc": (c_int, [c_int, c_dbl, c_int, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "pm_stream": (c_int, [c_vp, c_int, c_vp, c_vp, c_i64, c_vp]),
     "pm_check_finite": (c_int, [c_vp, c_vp, c_i64, c_int, c_vp, c_vp]),
     "pm_timing_enable": (c_int, [c_vp, ctypes.c_uint]),

@@ -14,8 +14,11 @@
 // second kernel sums the partials of each shell over the planes in a fixed
 // order.  No atomics, so repeated calls give bitwise equal results.
 //
-// pm_power_spectrum keeps its partials in the plan's spectrum scratch.
+// Two entry points share the kernels: pm_power_spectrum keeps its partials
+// in the plan's spectrum scratch, pm_power_spectrum_noalloc in the file-scope
+// device array `scratch` below, for callers that cannot allocate.
 #include <cmath>
+#include <mutex>
 
 #include "pm_internal.h"
 
@@ -23,6 +26,8 @@ namespace pmx {
 namespace {
 
 constexpr int kSpecThreads = 256;
+constexpr int kMaxMesh = 1024;                                      // largest mesh side of the library
+constexpr int64_t kPartialDoubles = int64_t(kMaxMesh / 2) * kMaxMesh * 3;   // [shells][planes][3]
 
 // floor(sqrt(v)) for 0 <= v < 2^52, exact
 __device__ __forceinline__ int64_t isqrt_floor(int64_t v) {
@@ -137,6 +142,40 @@ hipError_t pk_launch(int n, double box, int dtype, const void* dk, double* part,
   return hipGetLastError();
 }
 
+bool pow2_side(int n) { return n >= 4 && n <= kMaxMesh && (n & (n - 1)) == 0; }
+
+// ---------------------------------------------------------------------------
+// allocation-free variant: the partials live in this file-scope device array
+// (one copy per GPU, held until the process ends).  Its address on a device
+// comes from hipGetSymbolAddress, taken once per device with that device
+// current; host code never uses the name itself as a device address.
+// ---------------------------------------------------------------------------
+__device__ __align__(256) double scratch[kPartialDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// address of `scratch` on the current device (looked up on the first call)
+int scratch_on_current_device(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return set_error(nullptr, PM_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices)
+    return set_error(nullptr, PM_EDEVICE, "device %d is beyond the %d devices the scratch table covers", dev,
+                     kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return set_error(nullptr, PM_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return PM_OK;
+}
+
 }  // namespace
 }  // namespace pmx
 
@@ -160,5 +199,22 @@ extern "C" int pm_power_spectrum(pm_plan h, const void* delta_k, double* k, doub
   if (cur != p->device) PM_HIP_CHECK(p, hipSetDevice(p->device));
   PM_HIP_CHECK(p, pk_launch(n, box, p->cfg.mesh_dtype, delta_k, static_cast<double*>(p->spec[3]), k, P, count,
                             stream));
+  return PM_OK;
+}
+
+extern "C" int pm_power_spectrum_noalloc(int n, double box, int mesh_dtype, const void* delta_k, double* k,
+                                         double* P, double* count, hipStream_t stream) {
+  if (!delta_k || !k || !P || !count)
+    return set_error(nullptr, PM_EINVAL, "delta_k, k, P and count must not be NULL");
+  if (n > kMaxMesh)
+    return set_error(nullptr, PM_ESHAPE, "mesh side %d exceeds the %d that the static scratch (%lld bytes) holds",
+                     n, kMaxMesh, static_cast<long long>(kPartialDoubles * sizeof(double)));
+  if (!pow2_side(n)) return set_error(nullptr, PM_ESHAPE, "mesh side must be a power of two in [4, %d]", kMaxMesh);
+  if (!(std::isfinite(box) && box > 0.0)) return set_error(nullptr, PM_EINVAL, "box must be finite and > 0");
+  if (mesh_dtype != PM_F32 && mesh_dtype != PM_F64) return set_error(nullptr, PM_EINVAL, "dtype must be PM_F32 or PM_F64");
+  double* part = nullptr;
+  if (int rc = scratch_on_current_device(&part)) return rc;
+  const hipError_t e = pk_launch(n, box, mesh_dtype, delta_k, part, k, P, count, stream);
+  if (e != hipSuccess) return set_error(nullptr, PM_EDEVICE, "power spectrum launch: %s", hipGetErrorString(e));
   return PM_OK;
 }
