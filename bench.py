@@ -48,9 +48,10 @@ FAMILY_SOURCES = {
 }
 
 
-def measured_traffic(family):
-    """HBM bytes per launch of `family` from the rocprofv3 counter summary in
-    profiles/, or None if there is none or the kernel source changed since."""
+def measured_traffic(family, workload):
+    """HBM bytes per launch of `family` at `workload` from the rocprofv3
+    counter summary in profiles/, or None if there is none for that workload
+    or the kernel source changed since the counters were taken."""
     import glob
     import hashlib
     import re
@@ -62,8 +63,9 @@ def measured_traffic(family):
     digest = h.hexdigest()[:16]
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         for line in open(path):
-            m = re.search(r"traffic_per_launch_bytes=([0-9.e+]+) family=(\w+) source_sha256=(\w+)", line)
-            if m and m.group(2) == family and m.group(3) == digest:
+            m = re.search(r"traffic_per_launch_bytes=([0-9.e+]+) family=(\w+) workload=(\w+) source_sha256=(\w+)",
+                          line)
+            if m and m.group(2) == family and m.group(3) == workload and m.group(4) == digest:
                 return float(m.group(1))
     return None
 
@@ -205,20 +207,45 @@ def copy_bandwidth(gib=2, reps=5):
     return best
 
 
-def fp64_reference(args, target64, g_mixed, th_mixed):
+def final_state_outputs(sim, omega, cosmo, tabs):
+    """Forward pass only: the final displacement s_n (FP64 copy) and the
+    power spectrum (k, P) of the final density contrast (pm_power_spectrum)."""
+    sim.forward(omega, cosmo, tabs)
+    s_fin = sim.s.double().clone()
+    k, P, _ = sim.plan.power_spectrum(sim.plan.density(sim.s))
+    return s_fin, k.clone(), P.clone()
+
+
+def fp64_reference(args, target64, g_mixed, th_mixed, s_mixed, pk_mixed):
     """One all-FP64 pass on the same workload (same white noise and target):
-    its throughput and the relative L2 error of the benchmarked gradients."""
+    its throughput, and the error of each benchmarked output against it:
+    final positions, the density power spectrum and the gradients."""
     import torch
     n, nm, box, nsteps, a0 = WORKLOADS[args.workload]
     log("all-FP64 reference pass")
     sim, cosmo, tabs, omega = _setup_run(n, nm, box, nsteps, a0, torch.float64, torch.float64)
     _timed_pass(sim, omega, cosmo, target64, tabs)  # warm-up
     J, g, th, dt = _timed_pass(sim, omega, cosmo, target64, tabs)
+    s64, k64, P64 = final_state_outputs(sim, omega, cosmo, tabs)
+    ds = s_mixed - s64
+    relP = (pk_mixed[1].double() / P64 - 1.0).abs().cpu()
+    nq = max(1, (nm // 2) // 2)           # shells b = 1 .. N/4
     return {
         "fp64_reference": {"value": n ** 3 * nsteps / dt, "unit": "particle-steps/s", "ms_per_step": 1000 * dt,
                            "J": float(J.cpu()[0]), "dJ_dtheta": th.cpu().tolist()},
         "grad_omega_rel_l2_vs_fp64": _rel_l2(g_mixed, g),
         "dJ_dtheta_rel_err_vs_fp64": [abs(float(a) - float(b)) / abs(float(b)) for a, b in zip(th_mixed.cpu(), th.cpu())],
+        "final_positions_vs_fp64": {"rel_l2_of_displacement": _rel_l2(s_mixed, s64),
+                                    "rms_err_cells": float(ds.pow(2).mean().sqrt()),
+                                    "max_err_cells": float(ds.abs().max())},
+        "power_spectrum_vs_fp64": {"max_rel_err_first_quarter": float(relP[:nq].max()),
+                                   "max_rel_err_all": float(relP.max()),
+                                   "rel_err_per_shell": [float(x) for x in relP],
+                                   "k_h_per_mpc": [float(x) for x in k64.cpu()],
+                                   "P_fp64": [float(x) for x in P64.cpu()],
+                                   "note": "final density contrast of the forward pass at a = 1, shells "
+                                           "round(|m|) = 1 .. N/2 (pm_power_spectrum); first quarter: "
+                                           "shells 1 .. N/4"},
     }
 
 
@@ -240,6 +267,7 @@ def study_precision(args):
     torch.cuda.empty_cache()
     res = {}
     grads = {}
+    finals = {}
     for mdt, sdt in modes:
         key = "%s-mesh/%s-state" % (mdt, sdt)
         log("precision: " + key)
@@ -266,14 +294,23 @@ def study_precision(args):
             },
         }
         grads[key] = (g.double().clone(), th.clone())
+        finals[key] = final_state_outputs(sim, omega, cosmo, tabs)
         del sim, omega, target, st0, s0, p0, ds, dp, g
         torch.cuda.empty_cache()
     g64, th64 = grads["f64-mesh/f64-state"]
+    s64, _, P64 = finals["f64-mesh/f64-state"]
+    nq = max(1, nm // 4)
     for key, (g, th) in grads.items():
         res[key]["grad_omega_rel_l2_vs_fp64"] = _rel_l2(g, g64)
         res[key]["dJ_dtheta_rel_err_vs_fp64"] = [abs(float(a) - float(b)) / abs(float(b))
                                                  for a, b in zip(th.cpu(), th64.cpu())]
-    del grads, g64
+        s_fin, _, P = finals[key]
+        relP = (P / P64 - 1.0).abs()
+        res[key]["final_positions_vs_fp64"] = {"rel_l2_of_displacement": _rel_l2(s_fin, s64),
+                                               "max_err_cells": float((s_fin - s64).abs().max())}
+        res[key]["power_spectrum_vs_fp64"] = {"max_rel_err_first_quarter": float(relP[:nq].max()),
+                                              "max_rel_err_all": float(relP.max())}
+    del grads, g64, finals, s64
     torch.cuda.empty_cache()
     # adjoint memory against the number of steps (mixed precision)
     mem = {}
@@ -539,17 +576,59 @@ def study_fd_theta(args, hs=(1e-3, 3e-4)):
             "adjoint_pass_s": dt, "particle_steps_per_s": n ** 3 * nsteps / dt, "fd": fd}
 
 
+# kernel families of each stage of the hot path (the paint includes the drift
+# and kick fused into its binning)
+STAGES = {
+    "paint": ("bin", "scatter", "paint_tiles", "halo_add"),
+    "fft": ("fft_r2c_z", "fft_lines", "fft_poisson", "fft_c2r_z"),
+    "gather": ("gather",),
+}
+
+
+def family_table(plan, families, passes=1):
+    """Per-family time, launches, algorithmic and method bytes since the last
+    timing_enable, per pass, with the rates against the HBM peak."""
+    out = {}
+    for name, kid in families.items():
+        ms, nl, by, mby = plan.timing_read(kid, method=True)
+        if not nl:
+            continue
+        gbs = (by / 1e9) / (ms / 1e3)
+        mgbs = (mby / 1e9) / (ms / 1e3)
+        out[name] = {"ms_per_step": ms / passes, "launches_per_step": nl / passes, "avg_launch_ms": ms / nl,
+                     "algorithmic_bytes_per_step": by / passes, "method_bytes_per_step": mby / passes,
+                     "algorithmic_GBps": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS,
+                     "method_GBps": mgbs, "frac_method": mgbs / HBM_PEAK_GBS}
+    return out
+
+
+def stage_table(kernels):
+    """The paint, FFT and gather stages (sums of their families)."""
+    out = {}
+    for st, fams in STAGES.items():
+        ms = sum(kernels[f]["ms_per_step"] for f in fams if f in kernels)
+        by = sum(kernels[f]["algorithmic_bytes_per_step"] for f in fams if f in kernels)
+        mby = sum(kernels[f]["method_bytes_per_step"] for f in fams if f in kernels)
+        if ms <= 0:
+            continue
+        out[st] = {"families": [f for f in fams if f in kernels], "ms_per_step": ms,
+                   "algorithmic_GBps": by / 1e9 / (ms / 1e3), "frac": by / 1e9 / (ms / 1e3) / HBM_PEAK_GBS,
+                   "method_GBps": mby / 1e9 / (ms / 1e3), "frac_method": mby / 1e9 / (ms / 1e3) / HBM_PEAK_GBS}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-warmup-child", dest="warmup_child", action="store_false",
-                    help="skip the child process of the HBM warm-up (for a run whose previous process already "
-                         "cycled the memory, e.g. under a profiler)")
-    ap.add_argument("--hbm-warmup", type=int, default=1024, metavar="GIB",
-                    help="untimed setup: allocate and release up to GIB GiB (at most all but 8 GiB of the free "
-                         "device memory) before the plan and the state are allocated; 0: off")
+                    help="with --hbm-warmup: skip its child process (for a run whose previous process already "
+                         "cycled the memory)")
+    ap.add_argument("--hbm-warmup", type=int, default=0, metavar="GIB",
+                    help="untimed setup, off by default: allocate and release up to GIB GiB (at most all but "
+                         "8 GiB of the free device memory), first in a child process and then in this one, "
+                         "before the plan and the state are allocated")
     ap.add_argument("--workload", default="512", choices=sorted(WORKLOADS))
     ap.add_argument("--kernel", default="auto",
                     help="kernel family for the roofline object (default: the one with the most time)")
@@ -559,7 +638,7 @@ def main():
     ap.add_argument("--state-dtype", default="f64", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-ref", action="store_true",
-                    help="skip the all-FP64 reference pass used for the gradient rel-L2")
+                    help="skip the all-FP64 reference pass used for the errors against FP64")
     ap.add_argument("--study", choices=["precision", "force", "fd-theta", "checkpoints", "lightcone"],
                     help="print a study instead of the benchmark line: precision = FP32 / mixed / FP64 "
                          "reversibility, gradient error and memory vs steps; force = single force and VJP "
@@ -575,8 +654,7 @@ def main():
 
     if args.hbm_warmup > 0 and args.warmup_child and not args.study:
         # the same cycle first in a short child process, before this process
-        # touches the GPU: memory that an earlier process allocated and
-        # released runs faster than memory a process is the first to use
+        # touches the GPU
         t0 = time.perf_counter()
         rc = subprocess.run([sys.executable, "-c", "import bench; bench.hbm_warmup(%d)" % args.hbm_warmup],
                             cwd=os.path.dirname(os.path.abspath(__file__))).returncode
@@ -638,12 +716,7 @@ def main():
         torch.cuda.synchronize()
         log("warmup %d: %.3f s" % (w, time.perf_counter() - t0))
         if last:
-            for name, kid in families.items():
-                ms, nl, by = sim.plan.timing_read(kid)
-                if nl:
-                    gbs = (by / 1e9) / (ms / 1e3)
-                    kernels[name] = {"ms_per_step": ms, "launches_per_step": nl, "avg_launch_ms": ms / nl,
-                                     "algorithmic_GBps": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
+            kernels = family_table(sim.plan, families)
             sim.plan.timing_enable(())
     if args.kernel != "auto":
         top = args.kernel
@@ -657,12 +730,12 @@ def main():
     torch.cuda.reset_peak_memory_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    fam = {k: [0.0, 0, 0.0] for k in families}
+    fam = {}
     for k in range(args.steps):
         J, g, th = sim.value_and_grad(omega, cosmo, target, tabs)
         for name, kid in families.items():   # waits for this pass's timed kernels
             if kid in timed:
-                fam[name] = list(sim.plan.timing_read(kid))
+                fam[name] = sim.plan.timing_read(kid, method=True)
         log("step %d done (%.3f s elapsed)" % (k, time.perf_counter() - t0))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -670,16 +743,20 @@ def main():
     peak_mem = torch.cuda.max_memory_allocated()
     plan_ws = sim.plan.workspace_bytes((nm,) * 3, (n,) * 3, mdt, sdt)
     if not kernels:
-        for name, (ms, nl, by) in fam.items():
+        for name, (ms, nl, by, mby) in fam.items():
             if nl:
-                gbs = (by / 1e9) / (ms / 1e3)
+                gbs, mgbs = (by / 1e9) / (ms / 1e3), (mby / 1e9) / (ms / 1e3)
                 kernels[name] = {"ms_per_step": ms / args.steps, "launches_per_step": nl / args.steps,
-                                 "avg_launch_ms": ms / nl, "algorithmic_GBps": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
+                                 "avg_launch_ms": ms / nl, "algorithmic_bytes_per_step": by / args.steps,
+                                 "method_bytes_per_step": mby / args.steps, "algorithmic_GBps": gbs,
+                                 "frac_of_peak": gbs / HBM_PEAK_GBS, "method_GBps": mgbs,
+                                 "frac_method": mgbs / HBM_PEAK_GBS}
         top = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
-    kms, klaunch, kbytes = fam[top]
+    kms, klaunch, kbytes, kmbytes = fam[top]
     ms_per_step = 1000.0 * elapsed / args.steps
     value = n ** 3 * nsteps / (elapsed / args.steps)
     achieved = (kbytes / 1e9) / (kms / 1e3) if kms > 0 else None
+    achieved_m = (kmbytes / 1e9) / (kms / 1e3) if kms > 0 else None
     Jv = float(J.cpu()[0])
     thv = th.cpu().tolist()
     gn = float(torch.linalg.vector_norm(g.double()).cpu())
@@ -690,12 +767,16 @@ def main():
     stream_gbs = stream_bandwidth(sim.plan)
     log("stream kernels: read %.0f, copy %.0f, write %.0f GB/s" % (stream_gbs["read"], stream_gbs["copy"],
                                                                    stream_gbs["write"]))
+    # the whole pass's method bytes (last warmup pass) over the timed pass time
+    pass_method = sum(v["method_bytes_per_step"] for v in kernels.values())
+    pass_alg = sum(v["algorithmic_bytes_per_step"] for v in kernels.values())
     ref = None
     if not args.no_fp64_ref and (args.mesh_dtype, args.state_dtype) != ("f64", "f64"):
         g_keep, th_keep = g.double().clone(), th.clone()
-        del sim
+        s_fin, k_fin, P_fin = final_state_outputs(sim, omega, cosmo, tabs)
+        del sim, g
         torch.cuda.empty_cache()
-        ref = fp64_reference(args, target.double(), g_keep, th_keep)
+        ref = fp64_reference(args, target.double(), g_keep, th_keep, s_fin, (k_fin, P_fin))
 
     out = {
         "metric": "particle-steps/s for forward+adjoint at %d^3" % n,
@@ -722,10 +803,10 @@ def main():
             "peak_mem_gb": (peak_mem + plan_ws) / 1e9,
             "peak_mem_note": "torch allocator peak plus the plan's own workspace",
             "hbm_warmup_gib": warm_gib,
-            "hbm_warmup_child": bool(args.warmup_child and args.hbm_warmup > 0),
-            "hbm_warmup_note": "untimed setup step: device memory allocated and released, first in a child "
-                               "process and then in this one, before the plan and the state; the timed work is "
-                               "unchanged",
+            "process": "cold: the plan and the state are the first device memory this process and the GPU's "
+                       "last process allocated" if not warm_gib else
+                       "after an untimed HBM warm-up (%d GiB allocated and released%s)"
+                       % (warm_gib, ", first in a child process" if args.warmup_child else ""),
         },
         "roofline": {
             "bound": "hbm",
@@ -735,10 +816,21 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": measured_traffic(top),
+            "traffic": measured_traffic(top, args.workload),
             "launches": klaunch,
             "avg_launch_ms": kms / klaunch if klaunch else None,
             "algorithmic_bytes_per_launch": kbytes / klaunch if klaunch else None,
+            "method_bytes_per_launch": kmbytes / klaunch if klaunch else None,
+            "achieved_method": achieved_m,
+            "frac_method": (achieved_m / HBM_PEAK_GBS) if achieved_m else None,
+            "bytes_note": "achieved/frac: algorithmic bytes (the implementation's intermediates included: sort "
+                          "keys, CIC records, lists, halos, FFT inter-pass spectra); achieved_method/frac_method: "
+                          "the method's own state and field traffic only (pm_timing_read)",
+            "stages": stage_table(kernels),
+            "pass": {"ms": ms_per_step, "algorithmic_bytes": pass_alg, "method_bytes": pass_method,
+                     "frac": pass_alg / 1e9 / (ms_per_step / 1e3) / HBM_PEAK_GBS,
+                     "frac_method": pass_method / 1e9 / (ms_per_step / 1e3) / HBM_PEAK_GBS,
+                     "method_bytes_per_particle_step": pass_method / (n ** 3 * nsteps)},
             "device_copy_GBps": copy_gbs,
             "frac_of_copy": (achieved / copy_gbs) if achieved else None,
             "stream_GBps": stream_gbs,

@@ -441,9 +441,18 @@ int pm_stream(pm_plan plan, int mode, const void* src, void* dst, int64_t nbytes
  * off); each launch is bracketed by HIP events on the stream it runs on.
  * pm_timing_read(plan, PM_K_*, ...) synchronises that family's events and
  * returns, since the last pm_timing_enable, the summed milliseconds, the
- * number of launches and the summed algorithmic bytes (the HBM traffic each
- * launch must at least move: inputs read once, outputs written once).  At
- * most 1024 launches per family are recorded between two reads; launches
+ * number of launches and two byte counts (any output may be NULL):
+ *   total_bytes        algorithmic bytes: every array the launch touches
+ *                      read or written once, the implementation's own
+ *                      intermediates included (sort keys, CIC records,
+ *                      particle lists, halo faces, the spectra between the
+ *                      passes of a 3-D FFT);
+ *   total_method_bytes what the method itself must move: the particle state
+ *                      and mesh fields of the operation read or written once,
+ *                      each 3-D FFT as one read of its input and one write of
+ *                      its output (charged to its first and last pass), no
+ *                      intermediates.
+ * At most 1024 launches per family are recorded between two reads; launches
  * beyond that are counted and reported as a PM_EINVAL error by the read. */
 #define PM_K_BIN         1   /* paint: drift + tile binning                  */
 #define PM_K_FFT_R2C_Z   2   /* real-to-complex pass along z                 */
@@ -456,7 +465,8 @@ int pm_stream(pm_plan plan, int mode, const void* src, void* dst, int64_t nbytes
 #define PM_K_HALO        9   /* paint: halo faces into the mesh              */
 #define PM_K_LIGHTCONE  10   /* light-cone observation, its VJP and bump      */
 int pm_timing_enable(pm_plan plan, unsigned mask);
-int pm_timing_read(pm_plan plan, int kernel, double* total_ms, int64_t* launches, double* total_bytes);
+int pm_timing_read(pm_plan plan, int kernel, double* total_ms, int64_t* launches, double* total_bytes,
+                   double* total_method_bytes);
 
 #ifdef __cplusplus
 }

@@ -136,7 +136,7 @@ _PROTOS = {
     "pm_stream": (c_int, [c_vp, c_int, c_vp, c_vp, c_i64, c_vp]),
     "pm_check_finite": (c_int, [c_vp, c_vp, c_i64, c_int, c_vp, c_vp]),
     "pm_timing_enable": (c_int, [c_vp, ctypes.c_uint]),
-    "pm_timing_read": (c_int, [c_vp, c_int, P(c_dbl), P(c_i64), P(c_dbl)]),
+    "pm_timing_read": (c_int, [c_vp, c_int, P(c_dbl), P(c_i64), P(c_dbl), P(c_dbl)]),
 }
 
 EXPORTED = tuple(_PROTOS.keys())

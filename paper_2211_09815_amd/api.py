@@ -452,11 +452,14 @@ class Plan:
             mask |= 1 << int(k)
         self._c(lib().pm_timing_enable(self._h, mask))
 
-    def timing_read(self, kernel):
+    def timing_read(self, kernel, method=False):
         """(total milliseconds, launches, total algorithmic bytes) of one
-        PM_K_* family since timing_enable."""
+        PM_K_* family since timing_enable; with method=True a fourth value,
+        the total method bytes (pm_timing_read)."""
         ms = ctypes.c_double()
         n = ctypes.c_int64()
         b = ctypes.c_double()
-        self._c(lib().pm_timing_read(self._h, int(kernel), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
-        return ms.value, n.value, b.value
+        mb = ctypes.c_double()
+        self._c(lib().pm_timing_read(self._h, int(kernel), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b),
+                                     ctypes.byref(mb)))
+        return (ms.value, n.value, b.value, mb.value) if method else (ms.value, n.value, b.value)

@@ -34,7 +34,7 @@ void timing_begin(Plan* p, int kernel, hipStream_t s) {
   (void)hipEventRecord(f.ev[f.nev], s);
 }
 
-void timing_end(Plan* p, int kernel, hipStream_t s, double bytes) {
+void timing_end(Plan* p, int kernel, hipStream_t s, double bytes, double method_bytes) {
   Timing& t = p->timing;
   if (!t.created || kernel <= 0 || kernel >= kTimingFamilies || !(t.mask & (1u << kernel))) return;
   TimingFamily& f = t.fam[kernel];
@@ -44,6 +44,7 @@ void timing_end(Plan* p, int kernel, hipStream_t s, double bytes) {
   }
   (void)hipEventRecord(f.ev[f.nev + 1], s);
   f.bytes[f.nev / 2] = bytes;
+  f.method_bytes[f.nev / 2] = method_bytes;
   f.nev += 2;
 }
 
@@ -871,13 +872,15 @@ int pm_timing_enable(pm_plan h, unsigned mask) {
     f.nev = 0;
     f.total_ms = 0.0;
     f.total_bytes = 0.0;
+    f.total_method_bytes = 0.0;
     f.launches = 0;
     f.dropped = 0;
   }
   return PM_OK;
 }
 
-int pm_timing_read(pm_plan h, int kernel, double* total_ms, int64_t* launches, double* total_bytes) {
+int pm_timing_read(pm_plan h, int kernel, double* total_ms, int64_t* launches, double* total_bytes,
+                   double* total_method_bytes) {
   CHECK_PLAN(h);
   if (kernel <= 0 || kernel >= kTimingFamilies) return set_error(p, PM_EINVAL, "unknown kernel family %d", kernel);
   TimingFamily& f = p->timing.fam[kernel];
@@ -887,12 +890,14 @@ int pm_timing_read(pm_plan h, int kernel, double* total_ms, int64_t* launches, d
     PM_HIP_CHECK(p, hipEventElapsedTime(&ms, f.ev[i], f.ev[i + 1]));
     f.total_ms += ms;
     f.total_bytes += f.bytes[i / 2];
+    f.total_method_bytes += f.method_bytes[i / 2];
     f.launches += 1;
   }
   f.nev = 0;
   if (total_ms) *total_ms = f.total_ms;
   if (launches) *launches = f.launches;
   if (total_bytes) *total_bytes = f.total_bytes;
+  if (total_method_bytes) *total_method_bytes = f.total_method_bytes;
   if (f.dropped) return set_error(p, PM_EINVAL, "%lld launches were not recorded (read more often)",
                                   static_cast<long long>(f.dropped));
   return PM_OK;

@@ -318,7 +318,8 @@ int x_fused_pass(Plan* p, const FftShape& s, SpecOp op, const Ptrs4& in, const P
     hipLaunchKernelGGL(kern, dim3(unsigned(ntiles)), dim3(kFT), lds, st, in, out, s.n1, s.n2, nh, coef, tw);
     return PM_OK;
   });
-  timing_end(p, PM_K_FFT_POISSON, st, double(nin + nout) * double(ncols) * double(s.n0) * sizeof(cplx<T>));
+  // method bytes: none (the spectra along x are intermediates of the 3-D transforms)
+  timing_end(p, PM_K_FFT_POISSON, st, double(nin + nout) * double(ncols) * double(s.n0) * sizeof(cplx<T>), 0.0);
   PM_HIP_CHECK(p, hipGetLastError());
   return PM_OK;
 }

@@ -83,7 +83,8 @@ int lines_pass(Plan* p, const Ptrs4& arrs, int batch, bool inv, int M, int64_t l
     hipLaunchKernelGGL(kern, grid, dim3(kFT), lds, st, arrs, ls, ncols, ostride, tw);
     return PM_OK;
   });
-  timing_end(p, PM_K_FFT_LINES, st, 2.0 * double(batch) * double(ncols) * double(nouter) * M * sizeof(cplx<T>));
+  timing_end(p, PM_K_FFT_LINES, st, 2.0 * double(batch) * double(ncols) * double(nouter) * M * sizeof(cplx<T>),
+             0.0);   // method bytes: an inner pass moves only intermediates
   PM_HIP_CHECK(p, hipGetLastError());
   return PM_OK;
 }

@@ -181,10 +181,11 @@ int r2c_z_pass(Plan* p, const FftShape& s, const Ptrs4& in, const Ptrs4& out, in
     return PM_OK;
   });
   // lines read and half spectra written (+ one halo value per tile boundary)
+  // method bytes: the 3-D R2C's real input read and half spectrum written
   const double fold_bytes = fold ? double(s.n2 >> zf->ltz) * sizeof(T) : 0.0;
-  timing_end(p, PM_K_FFT_R2C_Z, st,
-             double(batch) * double(nlines) *
-                 (double(s.n2) * sizeof(T) + double(nh) * sizeof(cplx<T>) + fold_bytes));
+  const double io = double(s.n2) * sizeof(T) + double(nh) * sizeof(cplx<T>);
+  timing_end(p, PM_K_FFT_R2C_Z, st, double(batch) * double(nlines) * (io + fold_bytes),
+             double(batch) * double(nlines) * io);
   PM_HIP_CHECK(p, hipGetLastError());
   return PM_OK;
 }
@@ -205,8 +206,9 @@ int c2r_z_pass(Plan* p, const FftShape& s, const Ptrs4& in, const Ptrs4& out, in
     hipLaunchKernelGGL((k_fft_c2r_z<T, LOGM>), grid, dim3(kFT), lds, st, in, out, nlines, scale, tw);
     return PM_OK;
   });
-  timing_end(p, PM_K_FFT_C2R_Z, st,
-             double(batch) * double(nlines) * (double(s.n2) * sizeof(T) + double(nh) * sizeof(cplx<T>)));
+  // method bytes: the 3-D C2R's half spectrum read and real output written
+  const double io = double(batch) * double(nlines) * (double(s.n2) * sizeof(T) + double(nh) * sizeof(cplx<T>));
+  timing_end(p, PM_K_FFT_C2R_Z, st, io, io);
   PM_HIP_CHECK(p, hipGetLastError());
   return PM_OK;
 }

@@ -353,7 +353,7 @@ extern "C" int pm_lightcone(pm_plan h, const pm_lc_step* st, const void* s0, con
                        static_cast<const float*>(s0), static_cast<const float*>(p0), static_cast<const float*>(s1),
                        static_cast<const float*>(p1), static_cast<float*>(obs), obs_step, p->partials);
   PM_HIP_CHECK(p, hipGetLastError());
-  timing_end(p, PM_K_LIGHTCONE, stream, 6.0 * double(p->nptcl) * sb);
+  timing_end(p, PM_K_LIGHTCONE, stream, 6.0 * double(p->nptcl) * sb, 6.0 * double(p->nptcl) * sb);
   const double f[4] = {1.0, 0.0, 0.0, 0.0};
   return reduce_partials(p, blocks, f, count, true, stream);
 }
@@ -382,7 +382,7 @@ extern "C" int pm_lightcone_vjp(pm_plan h, const pm_lc_step* st, const void* s0,
   else PM_LC_VJP(float, float);
 #undef PM_LC_VJP
   PM_HIP_CHECK(p, hipGetLastError());
-  timing_end(p, PM_K_LIGHTCONE, stream, 4.0 * double(p->nptcl));
+  timing_end(p, PM_K_LIGHTCONE, stream, 4.0 * double(p->nptcl), 4.0 * double(p->nptcl));
   const double f[4] = {1.0, 0.0, 0.0, 0.0};
   return reduce_partials(p, blocks, f, theta_bar, true, stream);
 }
@@ -411,7 +411,8 @@ extern "C" int pm_adj_bump(pm_plan h, void* xi, void* pi, const void* x_bar, con
                        static_cast<const float*>(c), float(Kb), static_cast<const float*>(acc), omega_m_bar, n3,
                        p->partials);
   PM_HIP_CHECK(p, hipGetLastError());
-  timing_end(p, PM_K_LIGHTCONE, stream, double(n3) * mb * (6.0 + (c ? 1.0 : 0.0) + (acc ? 1.0 : 0.0)));
+  const double bump_bytes = double(n3) * mb * (6.0 + (c ? 1.0 : 0.0) + (acc ? 1.0 : 0.0));
+  timing_end(p, PM_K_LIGHTCONE, stream, bump_bytes, bump_bytes);
   const double f[4] = {acc ? dKb : 0.0, omega_m_bar ? Kb : 0.0, 0.0, 0.0};
   if (f[0] == 0.0 && f[1] == 0.0) return PM_OK;
   return reduce_partials(p, blocks, f, theta_bar, true, stream);

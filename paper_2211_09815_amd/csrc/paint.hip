@@ -573,11 +573,12 @@ int bin_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
     // s (or s_set) read (+ p read, s write; adjoint: xi read, pi read/write),
     // key write; a pending kick reads a (and alpha) and writes p (and xi)
     const double N = double(g.N), sb = sizeof(S), mb = sizeof(T);
-    double bytes = 3 * N * sb + 8 * N + (b.rec ? 16 * N : 0.0);   // + the CIC records
-    if (mode == DRIFT_FWD) bytes += 6 * N * sb;
-    if (adj) bytes += 6 * N * sb + 9 * N * mb;
-    if (kick) bytes += 3 * N * (mb + sb) + (adj ? 6 * N * mb : 0.0);
-    timing_end(p, PM_K_BIN, st, bytes);
+    double method = 3 * N * sb;
+    if (mode == DRIFT_FWD) method += 6 * N * sb;
+    if (adj) method += 6 * N * sb + 9 * N * mb;
+    if (kick) method += 3 * N * (mb + sb) + (adj ? 6 * N * mb : 0.0);
+    // the implementation adds the (tile, rank) keys and the CIC records
+    timing_end(p, PM_K_BIN, st, method + 8 * N + (b.rec ? 16 * N : 0.0), method);
   }
   const int64_t nt = g.ntiles;
   const int nsb = int((nt + 4 * kThreads - 1) / (4 * kThreads));
@@ -588,7 +589,7 @@ int bin_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
   timing_begin(p, PM_K_SCATTER, st);
   hipLaunchKernelGGL(k_scatter, dim3(pblocks), block, 0, st, static_cast<const uint2*>(p->bin_keys), p->bin_offs,
                      p->bin_list, g.N);
-  timing_end(p, PM_K_SCATTER, st, 12.0 * double(g.N));  // key read, list write
+  timing_end(p, PM_K_SCATTER, st, 12.0 * double(g.N), 0.0);  // key read, list write: intermediates only
   PM_HIP_CHECK(p, hipGetLastError());
   return PM_OK;
 }
@@ -620,6 +621,9 @@ int paint_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
   // weights read, core and halo faces written
   const double pos_bytes = p->bin_rec ? 16 * N : 3 * N * sb;
   const double tile_bytes = 4 * N + pos_bytes + double(nch - in.unit) * N * mb + core_bytes + halo_bytes;
+  // method: the painted mesh written, and the weights read unless the fused
+  // adjoint drift has just read them (the positions are charged to the bin)
+  const double tile_method = core_bytes + (adj ? 0.0 : double(nch - in.unit) * N * mb);
   // halo: halo faces read (but the z faces when deferred), the lower-face
   // core cells read and written
   const int zc = g.tx * g.ty;
@@ -630,11 +634,11 @@ int paint_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
   timing_begin(p, PM_K_PAINT_TILES, st);                                                                   \
   hipLaunchKernelGGL((k_paint_tiles<S, T, NCH, UNIT>), tg, dim3(kPaintThreads), 0, st, g, s, w, p->bin_offs,    \
                      p->bin_list, mesh, halo, wglob, static_cast<const float4*>(p->bin_rec));              \
-  timing_end(p, PM_K_PAINT_TILES, st, tile_bytes);                                                         \
+  timing_end(p, PM_K_PAINT_TILES, st, tile_bytes, tile_method);                                            \
   timing_begin(p, PM_K_HALO, st);                                                                          \
   if (in.defer_z) hipLaunchKernelGGL((k_halo_add<T, NCH, true>), tg, block, 0, st, g, mesh, halo);         \
   else hipLaunchKernelGGL((k_halo_add<T, NCH, false>), tg, block, 0, st, g, mesh, halo);                   \
-  timing_end(p, PM_K_HALO, st, hadd_bytes)
+  timing_end(p, PM_K_HALO, st, hadd_bytes, 0.0)
   if (in.unit) {
     switch (nch) {
       case 1: PM_TILES(1, true); break;

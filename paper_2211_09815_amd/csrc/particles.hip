@@ -297,14 +297,18 @@ int gather_typed(Plan* p, GatherMode mode, const GatherArgs& in, hipStream_t st)
   {
     // list, positions (the CIC records with FP32 meshes, else s) and the
     // gathered mesh fields once, plus the per-mode particle traffic
+    // (method bytes: the positions as the state stores them, 3 N s_b, in
+    // place of the list and the records)
     const double N = double(p->nptcl), sb = sizeof(S), mb = sizeof(T);
-    double bytes = 4 * N + (p->bin_rec ? 16 * N : 3 * N * sb) + double(in.nf) * double(p->ncell) * mb;
-    if (mode == GATHER_PLAIN) bytes += double(in.nf) * N * mb;
-    if (mode == GATHER_KICK_FWD) bytes += 6 * N * sb + (in.acc ? 3 * N * mb : 0.0);
-    if (mode == GATHER_VJP) bytes += 6 * N * mb + (in.acc ? 3 * N * mb : 0.0);
-    if (mode == GATHER_KICK_ADJ) bytes += 6 * N * sb + 9 * N * mb + (in.acc_in ? 3 * N * mb : 0.0);
-    if (mode == GATHER_MSE) bytes += 3 * N * mb;
-    timing_end(p, PM_K_GATHER, st, bytes);
+    double part = 0.0;
+    if (mode == GATHER_PLAIN) part = double(in.nf) * N * mb;
+    if (mode == GATHER_KICK_FWD) part = 6 * N * sb + (in.acc ? 3 * N * mb : 0.0);
+    if (mode == GATHER_VJP) part = 6 * N * mb + (in.acc ? 3 * N * mb : 0.0);
+    if (mode == GATHER_KICK_ADJ) part = 6 * N * sb + 9 * N * mb + (in.acc_in ? 3 * N * mb : 0.0);
+    if (mode == GATHER_MSE) part = 3 * N * mb;
+    const double fields = double(in.nf) * double(p->ncell) * mb;
+    timing_end(p, PM_K_GATHER, st, 4 * N + (p->bin_rec ? 16 * N : 3 * N * sb) + fields + part,
+               3 * N * sb + fields + part);
   }
   PM_HIP_CHECK(p, hipGetLastError());
   return PM_OK;

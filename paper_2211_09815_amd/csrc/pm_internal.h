@@ -50,9 +50,11 @@ constexpr int kTimingSlots = 1024;     // launches recorded per family between r
 struct TimingFamily {
   hipEvent_t ev[2 * kTimingSlots] = {};   // created by pm_timing_enable (families 1..9)
   double bytes[kTimingSlots];
+  double method_bytes[kTimingSlots];
   int nev = 0;
   double total_ms = 0.0;
   double total_bytes = 0.0;
+  double total_method_bytes = 0.0;
   int64_t launches = 0;
   int64_t dropped = 0;
 };
@@ -111,10 +113,16 @@ int set_error(Plan* p, int code, const char* fmt, ...);
       return pmx::set_error((plan), PM_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
   } while (0)
 
-// kernel-launch bracketing for the timing facility; `bytes` is the
-// algorithmic HBM traffic of the launch (what the operation must move)
+// kernel-launch bracketing for the timing facility.  `bytes` is the launch's
+// algorithmic HBM traffic: every array it touches read or written once,
+// including the implementation's own intermediate data (sort keys, CIC
+// records, particle lists, halo faces).  `method_bytes` is the part the
+// method itself needs: the particle state and mesh fields of the operation
+// read or written once, with each 3-D FFT charged as one read and one write
+// of its input and output (to its first and last pass), and nothing for the
+// intermediates.
 void timing_begin(Plan* p, int kernel, hipStream_t s);
-void timing_end(Plan* p, int kernel, hipStream_t s, double bytes);
+void timing_end(Plan* p, int kernel, hipStream_t s, double bytes, double method_bytes);
 
 inline int ilog2(int64_t v) { int l = 0; while ((int64_t(1) << l) < v) ++l; return l; }
 __host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }

@@ -258,3 +258,32 @@ def test_force_momentum_conservation_and_zero_self_force(mdt, tol):
         a1 = host(one.force(d, 0.45))
         # a neighbour one cell away pulls with ~1e2 here; float32 FFT noise is ~1e-4 of that
         assert np.abs(a1).max() < (1e-10 if mdt == torch.float64 else 1e-3)
+
+
+def test_timing_method_bytes_of_a_force():
+    # the method bytes of one pm_force: positions read once (bin, FP64
+    # state), the painted mesh written, one R2C and three C2R charged at one
+    # read and one write of their inputs and outputs, the gather's positions,
+    # three fields and three acceleration components; the intermediates
+    # (keys, records, lists, halos, inter-pass spectra) count nothing.  The
+    # algorithmic bytes can be below the method bytes: the gather reads a
+    # 16-byte CIC record and a 4-byte list entry instead of 24-byte FP64
+    # positions
+    from paper_2211_09815_amd import _lib
+    announce("timing method bytes")
+    mesh, ptcl = (32, 32, 32), (16, 16, 16)
+    plan = _plan(mesh, ptcl, torch.float32, torch.float64)
+    q, s = _particles(ptcl, 2.0, 59, 1.0)
+    s_dev = dev(soa(s), torch.float64)
+    plan.timing_enable(_lib.KERNEL_FAMILIES.values())
+    plan.force(s_dev, 0.3)
+    N, Nc, Ns = 16 ** 3, 32 ** 3, 32 * 32 * 17
+    expect = {"bin": 3 * N * 8, "scatter": 0, "paint_tiles": Nc * 4, "halo_add": 0, "fft_r2c_z": Nc * 4 + Ns * 8,
+              "fft_lines": 0, "fft_poisson": 0, "fft_c2r_z": 3 * (Ns * 8 + Nc * 4),
+              "gather": 3 * N * 8 + 3 * Nc * 4 + 3 * N * 4}
+    for name, kid in _lib.KERNEL_FAMILIES.items():
+        ms, nl, by, mby = plan.timing_read(kid, method=True)
+        if name in expect:
+            assert nl >= 1, name
+            assert mby == expect[name], name
+    plan.timing_enable(())
