@@ -341,6 +341,16 @@ int pm_plan_create(const pm_config* cfg, pm_plan* out) {
   p->nptcl = int64_t(p->np[0]) * p->np[1] * p->np[2];
   p->real_bytes = s.rb;
   tile_dims(p->n, p->tile, p->ntiles, p->halo_cells);
+  // The tile offsets are scanned in blocks of 4 kThreads tiles whose sums one
+  // workgroup scans again, so at most (4 kThreads)^2 tiles; and the CIC
+  // record packs each base-node coordinate in 10 bits (tiles.h).  Both hold
+  // for every mesh validate_cfg admits (sides <= 1024, tiles >= 8x8x16 cells
+  // when the mesh is that large); refuse anything else before allocating.
+  if ((p->ntiles + 4 * kThreads - 1) / (4 * kThreads) > 4 * kThreads || p->n[0] > 1024 || p->n[1] > 1024 ||
+      p->n[2] > 1024) {
+    delete p;
+    return set_error(nullptr, PM_EUNSUPPORTED, "tile count or mesh side beyond the binning's limits");
+  }
   void* mb = nullptr;
   void* sb = nullptr;
   void* bb = nullptr;

@@ -91,19 +91,35 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_tiles(GatherP<S, T> a
       }
     };
     load(beg);
-    // the tile's box of every field, (lx, ly) rows of ez cells
-    const unsigned mez = 0xffffffffu / unsigned(ez) + 1u, mey = 0xffffffffu / unsigned(ey) + 1u;
-    const unsigned mbox = 0xffffffffu / unsigned(nbox) + 1u;
-    for (int i = tid; i < NF * nbox; i += kGatherThreads) {
-      const int c = fdiv_small(i, mbox);
-      const int r = i - c * nbox;
-      const int lxy = fdiv_small(r, mez);
-      const int lz = r - lxy * ez;
-      const int lx = fdiv_small(lxy, mey);
-      const int ly = lxy - lx * ey;
-      const int64_t cell = (int64_t((o0 + lx) & (g.n0 - 1)) * g.n1 + ((o1 + ly) & (g.n1 - 1))) * g.n2 +
-                           ((o2 + lz) & (g.n2 - 1));
-      box[c * kBoxMax + r] = a.mesh[c * g.ncell + cell];
+    // the tile's box of every field, (lx, ly) rows of ez cells.  Every load
+    // of a thread is issued before the first LDS store, so the box costs one
+    // memory round trip, not one per element.
+    {
+      constexpr int ITER = (NF * kBoxMax + kGatherThreads - 1) / kGatherThreads;
+      const unsigned mez = 0xffffffffu / unsigned(ez) + 1u, mey = 0xffffffffu / unsigned(ey) + 1u;
+      const unsigned mbox = 0xffffffffu / unsigned(nbox) + 1u;
+      T bv[ITER];
+      int slot[ITER];
+#pragma unroll
+      for (int it = 0; it < ITER; ++it) {
+        const int i = tid + it * kGatherThreads;
+        slot[it] = -1;
+        if (i < NF * nbox) {
+          const int c = fdiv_small(i, mbox);
+          const int r = i - c * nbox;
+          const int lxy = fdiv_small(r, mez);
+          const int lz = r - lxy * ez;
+          const int lx = fdiv_small(lxy, mey);
+          const int ly = lxy - lx * ey;
+          const int64_t cell = (int64_t((o0 + lx) & (g.n0 - 1)) * g.n1 + ((o1 + ly) & (g.n1 - 1))) * g.n2 +
+                               ((o2 + lz) & (g.n2 - 1));
+          bv[it] = a.mesh[c * g.ncell + cell];
+          slot[it] = c * kBoxMax + r;
+        }
+      }
+#pragma unroll
+      for (int it = 0; it < ITER; ++it)
+        if (slot[it] >= 0) box[slot[it]] = bv[it];
     }
     __syncthreads();
     for (unsigned c0 = beg;;) {

@@ -82,7 +82,10 @@ __device__ __forceinline__ int fdiv_small(int r, unsigned m) { return int(__umul
 // by the paint and the gather instead of the displacement: the base node
 // (floor of the FP64 position, wrapped; 10 bits per axis, meshes up to 1024)
 // and the in-cell fractions rounded to float, i.e. exactly the values those
-// kernels would form from the FP64 position themselves.
+// kernels would form from the FP64 position themselves.  The 10-bit fields
+// and the two-level scan of the tile offsets (at most (4 kThreads)^2 tiles)
+// tie the mesh to sides <= 1024 with tiles of at least 8x8x16 cells;
+// pm_plan_create refuses any plan beyond them.
 template <typename T> constexpr bool kUseRec = sizeof(T) == 4;
 
 __device__ __forceinline__ unsigned pack_cell(int b0, int b1, int b2) {

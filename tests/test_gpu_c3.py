@@ -7,7 +7,10 @@ any size.
 
 The displacements come from the oracle's 2LPT (rounded to float32, as the
 golden script does), so both sides see identical positions.  Tolerances: the
-stated 1e-5 relative L2 on a single force, 2e-5 on the VJP outputs.
+stated 1e-5 relative L2 on a single force, 2e-5 on the VJP outputs, and,
+beside each norm, a per-particle bound of 2e-5 (4e-5 for the VJP) of the
+output's RMS: one particle wrong by more than that (for instance at a tile
+halo) fails even where it would hide in the norm over 4096 samples.
 """
 import json
 import os
@@ -46,7 +49,9 @@ def test_c3_force_vs_oracle(case):
     announce("c3 force")
     a = host(plan.force(s_dev, om))
     idx = np.asarray(gold["sample_idx"])
-    assert rel_l2(a[:, idx].T, gold["acc_sample"]) < 1e-5
+    ref = np.asarray(gold["acc_sample"])
+    assert rel_l2(a[:, idx].T, ref) < 1e-5
+    assert np.abs(a[:, idx].T - ref).max() < 2e-5 * np.sqrt(np.mean(ref * ref))
     # momentum conservation of the mesh force, and the overall scale
     assert np.abs(a.sum(1)).max() < 1e-5 * gold["acc_rms"] * a.shape[1] ** 0.5
     assert np.sqrt(np.mean(a * a)) == pytest.approx(gold["acc_rms"], rel=1e-5)
@@ -57,8 +62,12 @@ def test_c3_force_vjp_vs_oracle(case):
     announce("c3 force vjp")
     xbar, ombar, acc = plan.force_vjp(s_dev, cot, om)
     idx = np.asarray(gold["sample_idx"])
-    assert rel_l2(host(xbar)[:, idx].T, gold["xbar_sample"]) < 2e-5
-    assert rel_l2(host(acc)[:, idx].T, gold["acc_sample"]) < 1e-5
+    xb_ref, a_ref = np.asarray(gold["xbar_sample"]), np.asarray(gold["acc_sample"])
+    xb, a = host(xbar)[:, idx].T, host(acc)[:, idx].T
+    assert rel_l2(xb, xb_ref) < 2e-5
+    assert rel_l2(a, a_ref) < 1e-5
+    assert np.abs(xb - xb_ref).max() < 4e-5 * np.sqrt(np.mean(xb_ref * xb_ref))
+    assert np.abs(a - a_ref).max() < 2e-5 * np.sqrt(np.mean(a_ref * a_ref))
     assert host(ombar)[0] == pytest.approx(1.5 * gold["coef_bar"], rel=2e-5)
 
 

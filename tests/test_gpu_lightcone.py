@@ -264,6 +264,16 @@ def test_end_to_end_fp32_mesh_vs_oracle(sdt):
     same = ostep == step_ref
     assert same.mean() > 0.999                     # crossings at a step boundary may move by one step
     assert rel_l2(obs.T[same], obs_ref[same]) < 1e-5
+    # every particle whose step differs crossed within rounding of the
+    # boundary between the two steps, on both sides: one step apart, and
+    # both observed scale factors within 1e-3 of a step of that boundary
+    grid = cfg.a_grid()
+    da = grid[1] - grid[0]
+    for i in np.nonzero(~same)[0]:
+        assert ostep[i] > 0 and abs(int(ostep[i]) - int(step_ref[i])) == 1, i
+        a_b = grid[min(int(ostep[i]), int(step_ref[i]))]
+        assert abs(obs[6, i] - a_b) < 1e-3 * da, (i, obs[6, i], a_b)
+        assert abs(obs_ref[i, 6] - a_b) < 1e-3 * da, (i, obs_ref[i, 6], a_b)
     assert rel_l2(g, g_ref) < 1e-3
     np.testing.assert_allclose(th, th_ref, rtol=1e-3)
 
