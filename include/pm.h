@@ -44,12 +44,13 @@
  *    Scalars reported on the device (J, omega_m_bar, theta_bar) are ready after
  *    the stream is synchronised.  A plan is not thread-safe; calls made with
  *    one plan on different streams must be ordered by the caller.
- *  - Determinism: the paint sums each mesh tile in 64-bit fixed point with
- *    a per-tile binary scale, so painted meshes, forces and every particle
- *    output are bitwise reproducible (GPU float atomics would not be; the
- *    paper's Table rep discusses that effect).  Only the FP64 per-tile
- *    partial sums behind theta_bar depend on the order of particles within
- *    a tile, at the 1e-15 relative level.
+ *  - Determinism: with cfg.deterministic = 1 the paint sums each mesh tile
+ *    in 64-bit fixed point with a per-tile binary scale, so painted meshes,
+ *    forces and every particle output are bitwise reproducible (GPU float
+ *    atomics are not; the paper's Table rep discusses that effect).  Only
+ *    the FP64 per-tile partial sums behind theta_bar depend on the order of
+ *    particles within a tile, at the 1e-15 relative level.  With
+ *    cfg.deterministic = 0 the paint uses floating-point LDS atomics.
  */
 #ifndef PM_H
 #define PM_H
@@ -85,9 +86,13 @@ typedef struct {
     double  lattice_offset; /* offset of the lattice in mesh cells (all axes)  */
     int32_t mesh_dtype;     /* PM_F32 or PM_F64: mesh, FFT, force, adjoint     */
     int32_t state_dtype;    /* PM_F32 or PM_F64: s and p accumulators          */
-    int32_t deterministic;  /* accepted for compatibility: the paint always    */
-                            /* sums in 64-bit fixed point, so every mesh and   */
-                            /* particle output is bitwise reproducible         */
+    int32_t deterministic;  /* 1: the paint sums each tile in 64-bit fixed     */
+                            /* point (integer LDS atomics, associative), so    */
+                            /* every mesh and particle output is bitwise       */
+                            /* reproducible; 0: it sums in the mesh type with  */
+                            /* floating-point LDS atomics, whose order and so  */
+                            /* rounding change from run to run (Table rep of   */
+                            /* the paper discusses that effect)                */
 } pm_config;
 
 /* Creates a plan on the current HIP device and allocates its scratch.

@@ -90,10 +90,12 @@ def ic_struct(icd):
 
 
 class Plan:
-    """A libpm plan: mesh/lattice geometry, precision and device scratch."""
+    """A libpm plan: mesh/lattice geometry, precision and device scratch.
+    deterministic=True (default): the fixed-point paint, bitwise
+    reproducible; False: floating-point LDS atomics (see pm_config)."""
 
     def __init__(self, mesh, ptcl, box=(1.0, 1.0, 1.0), lattice_offset=0.0, mesh_dtype=torch.float32,
-                 state_dtype=torch.float64, deterministic=False):
+                 state_dtype=torch.float64, deterministic=True):
         mesh = tuple(int(m) for m in (mesh if np.iterable(mesh) else (mesh,) * 3))
         ptcl = tuple(int(m) for m in (ptcl if np.iterable(ptcl) else (ptcl,) * 3))
         box = tuple(float(b) for b in (box if np.iterable(box) else (box,) * 3))

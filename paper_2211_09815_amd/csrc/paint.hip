@@ -290,7 +290,12 @@ constexpr int kPaintThreads = 512;  // threads per tile workgroup of the paint
 // before any is used.  A tile whose particles fit in one chunk takes the
 // per-channel bound max|w| from the registers; larger tiles (the common case
 // with three or more channels) read their weights once more for it.
-template <typename S, typename T, int NCH, bool UNIT>
+// FIXED: the 64-bit fixed-point sums described above (bitwise reproducible).
+// Otherwise the box holds mesh-type sums updated with floating-point LDS
+// atomics (ds_add_f32 / ds_add_f64), whose order, and so whose rounding,
+// changes from run to run: the non-deterministic paint that plain GPU codes
+// use, kept for comparison.
+template <typename S, typename T, int NCH, bool UNIT, bool FIXED>
 __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const S* __restrict__ s,
                                                           const T* __restrict__ w, const unsigned* __restrict__ offs,
                                                           const unsigned* __restrict__ list, T* __restrict__ mesh,
@@ -306,11 +311,11 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
   constexpr unsigned CHUNK = P * kPaintThreads;
   constexpr unsigned NONE = 0xffffffffu;
   __shared__ unsigned long long box[NCH * kBoxMax];
+  T* const fbox = reinterpret_cast<T*>(box);   // the box as mesh-type sums (!FIXED)
   __shared__ double wmax[kPaintThreads / 64][NCH];
   __shared__ double scale[NCH], inv_scale[NCH];
   const int64_t tile = tile_order(g, xcd_tile(blockIdx.x, int64_t(gridDim.x)));
-  const int ex = g.tx + 1, ey = g.ty + 1, ez = g.tz + 1;
-  const int nbox = ex * ey * ez;
+  const int ey = g.ty + 1, ez = g.tz + 1;
   int o0, o1, o2;
   tile_origin(g, tile, o0, o1, o2);
   const unsigned beg = offs[tile], fin = offs[tile + 1];
@@ -340,10 +345,28 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
       for (int c = 0; c < NW; ++c) ws[k][c] = w[c * g.N + nn[k]];
     }
   };
+  // Each lane visits the 8 CIC corners of its particles in the order
+  // j XOR (lane mod 8): lanes whose particles share a cell then add to
+  // different cells in the same LDS atomic instruction instead of
+  // serialising on one address (the integer sums do not depend on the
+  // order).  The flips and the box offsets of the 8 corners depend only on
+  // the lane, so they are formed once.
+  const int flx = (tid >> 2) & 1, fly = (tid >> 1) & 1, flz = tid & 1;
+  int coff[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    coff[j] = (((j >> 2) ^ flx) * ey + (((j >> 1) & 1) ^ fly)) * ez + ((j & 1) ^ flz);
   auto paint = [&]() {
     double sc[NCH];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) sc[c] = scale[c];
+    // the scale folded into the geometric weights: channel 0's, or 1 when
+    // that is 0 (an all-zero weighted channel 0); a power of two either
+    // way, so the fold and the ratios below are exact.  A unit-mass channel
+    // 0 of a painted tile always has a nonzero scale, so its contribution is
+    // the folded weight itself.
+    const double fs = sc[0] != 0.0 ? sc[0] : 1.0;
+    const double inv_fs = 1.0 / fs;
 #pragma unroll
     for (int k = 0; k < P; ++k) {
       if (nn[k] == NONE) continue;
@@ -365,32 +388,50 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
         d1 = T(x1 - f1);
         d2 = T(x2 - f2);
       }
-      const T ux0 = T(1) - d0, uy0 = T(1) - d1, uz0 = T(1) - d2;
+      // The corner weight is the readout's own product (wx wy) wz in the
+      // mesh type, so that paint and readout share their weights exactly
+      // (momentum conservation and adjointness hold to rounding).  The
+      // folded binary scale fs rides on the x weights, which is exact; each
+      // channel then takes its weight times its scale over fs.  Per axis, a
+      // is the weight of the first corner the lane visits along that axis
+      // and b of the second.
+      const T s0 = FIXED ? T(fs) : T(1);
+      const T xa = (flx ? d0 : T(1) - d0) * s0, xb = (flx ? T(1) - d0 : d0) * s0;
+      const T ya = fly ? d1 : T(1) - d1, yb = fly ? T(1) - d1 : d1;
+      const T za = flz ? d2 : T(1) - d2, zb = flz ? T(1) - d2 : d2;
+      const T wxy[4] = {xa * ya, xa * yb, xb * ya, xb * yb};
       double wc[NCH];
 #pragma unroll
       for (int c = 0; c < NCH; ++c)
-        wc[c] = ((UNIT && c == 0) ? 1.0 : double(ws[k][c - (UNIT ? 1 : 0)])) * sc[c];
-      // The 8 corners in an order rotated by the lane: lanes whose particles
-      // share a cell then add to different cells in the same LDS atomic
-      // instruction instead of serialising on one address.  The integer sums
-      // do not depend on the order.
-      const int rot = tid & 7;
+        wc[c] = ((UNIT && c == 0) ? 1.0 : double(ws[k][c - (UNIT ? 1 : 0)])) * (sc[c] * inv_fs);
+      const int r0 = (l0 * ey + l1) * ez + l2;
+      if constexpr (!FIXED) {
+        T wt[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) wt[c] = (UNIT && c == 0) ? T(1) : ws[k][c - (UNIT ? 1 : 0)];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const T wg = wxy[j >> 1] * ((j & 1) ? zb : za);
+          const int r = r0 + coff[j];
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) atomicAdd(&fbox[c * kBoxMax + r], (UNIT && c == 0) ? wg : wg * wt[c]);
+        }
+        continue;
+      }
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const int cn = (j + rot) & 7;
-        const int i0 = cn >> 2, i1 = (cn >> 1) & 1, i2 = cn & 1;
-        const T wxy = (i0 ? d0 : ux0) * (i1 ? d1 : uy0);
-        const double ww = double(wxy * (i2 ? d2 : uz0));
-        const int r = ((l0 + i0) * ey + (l1 + i1)) * ez + l2 + i2;
+        const double ww = double(wxy[j >> 1] * ((j & 1) ? zb : za));
+        const int r = r0 + coff[j];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
           long long q;
           if constexpr (F32) {
-            // |ww wc| < 2^51: round to the nearest integer (ties to even)
-            // in the low mantissa bits of 1.5 * 2^52 + ww wc
-            q = __double_as_longlong(fma(ww, wc[c], 6755399441055744.0)) - 0x4338000000000000ll;
+            // |w| < 2^51: round to the nearest integer (ties to even) in the
+            // low mantissa bits of 1.5 * 2^52 + w
+            const double v = (UNIT && c == 0) ? ww + 6755399441055744.0 : fma(ww, wc[c], 6755399441055744.0);
+            q = __double_as_longlong(v) - 0x4338000000000000ll;
           } else {
-            q = __double2ll_rn(ww * wc[c]);
+            q = __double2ll_rn((UNIT && c == 0) ? ww : ww * wc[c]);
           }
           atomicAdd(&box[c * kBoxMax + r], (unsigned long long)q);
         }
@@ -400,12 +441,10 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
 
   const bool one_chunk = fin - beg <= CHUNK;
   if (one_chunk) load(beg);
-  for (int i = tid; i < NCH * nbox; i += kPaintThreads) {
-    const int c = i / nbox;
-    box[c * kBoxMax + (i - c * nbox)] = 0ull;
-  }
+  // clear every channel's whole box slot (no index arithmetic per cell)
+  for (int i = tid; i < NCH * kBoxMax; i += kPaintThreads) box[i] = 0ull;
   // per-channel bound of any cell sum: count * max|w| (unit mass: count)
-  if (NW > 0) {
+  if (FIXED && NW > 0) {
     double m[NCH];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) m[c] = 0.0;
@@ -437,7 +476,7 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
       for (int c = 0; c < NCH; ++c) wmax[tid >> 6][c] = m[c];
   }
   __syncthreads();
-  if (tid < NCH) {
+  if (FIXED && tid < NCH) {
     const int c = tid;
     double mx = 1.0;
     if (!(UNIT && c == 0)) {
@@ -476,8 +515,9 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
     const int lz = r & (g.tz - 1);
     const int ly = (r >> g.ltz) & (g.ty - 1);
     const int lx = r >> (g.ltz + g.lty);
+    const int b = c * kBoxMax + (lx * ey + ly) * ez + lz;
     mesh[c * g.ncell + (int64_t(o0 + lx) * g.n1 + (o1 + ly)) * g.n2 + (o2 + lz)] =
-        T(double(static_cast<long long>(box[c * kBoxMax + (lx * ey + ly) * ez + lz])) * inv_scale[c]);
+        FIXED ? T(double(static_cast<long long>(box[b])) * inv_scale[c]) : fbox[b];
   }
   // halo faces: X (lx = tx, all ly, lz), Y (ly = ty, lx < tx), Z (lz = tz, lx < tx, ly < ty)
   const int fx = ey * ez, fy = g.tx * ez;
@@ -489,8 +529,9 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
     if (h < fx) { lx = g.tx; ly = fdiv_small(h, mez); lz = h - ly * ez; }
     else if (h < fx + fy) { const int k = h - fx; lx = fdiv_small(k, mez); ly = g.ty; lz = k - lx * ez; }
     else { const int k = h - fx - fy; lx = k >> g.lty; ly = k & (g.ty - 1); lz = g.tz; }
+    const int b = c * kBoxMax + (lx * ey + ly) * ez + lz;
     halo[(int64_t(c) * g.ntiles + tile) * g.hc + h] =
-        T(double(static_cast<long long>(box[c * kBoxMax + (lx * ey + ly) * ez + lz])) * inv_scale[c]);
+        FIXED ? T(double(static_cast<long long>(box[b])) * inv_scale[c]) : fbox[b];
   }
 }
 
@@ -606,8 +647,11 @@ int paint_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
   // per-channel maxima the drift left in the block partials
   const bool adj = mode == DRIFT_ADJ || mode == DRIFT_SET;
   const T* w = static_cast<const T*>(adj ? in.pi : in.w);
+  // the fixed-point (bitwise reproducible) paint unless the plan asks for
+  // floating-point LDS atomics
+  const bool fixed = p->cfg.deterministic != 0;
   const double* wglob = nullptr;
-  if (adj && in.nw == 3) {
+  if (fixed && adj && in.nw == 3) {
     hipLaunchKernelGGL(k_wmax, dim3(1), block, 0, st, in.partials, blocks_for_particles(p), p->scalars);
     wglob = p->scalars;
   }
@@ -632,8 +676,12 @@ int paint_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
   const double hadd_bytes = halo_bytes * (in.defer_z ? double(g.hc - zc) / g.hc : 1.0) + 2.0 * lower * core_bytes;
 #define PM_TILES(NCH, UNIT)                                                                                \
   timing_begin(p, PM_K_PAINT_TILES, st);                                                                   \
-  hipLaunchKernelGGL((k_paint_tiles<S, T, NCH, UNIT>), tg, dim3(kPaintThreads), 0, st, g, s, w, p->bin_offs,    \
-                     p->bin_list, mesh, halo, wglob, static_cast<const float4*>(p->bin_rec));              \
+  if (fixed)                                                                                               \
+    hipLaunchKernelGGL((k_paint_tiles<S, T, NCH, UNIT, true>), tg, dim3(kPaintThreads), 0, st, g, s, w,    \
+                       p->bin_offs, p->bin_list, mesh, halo, wglob, static_cast<const float4*>(p->bin_rec)); \
+  else                                                                                                     \
+    hipLaunchKernelGGL((k_paint_tiles<S, T, NCH, UNIT, false>), tg, dim3(kPaintThreads), 0, st, g, s, w,   \
+                       p->bin_offs, p->bin_list, mesh, halo, wglob, static_cast<const float4*>(p->bin_rec)); \
   timing_end(p, PM_K_PAINT_TILES, st, tile_bytes, tile_method);                                            \
   timing_begin(p, PM_K_HALO, st);                                                                          \
   if (in.defer_z) hipLaunchKernelGGL((k_halo_add<T, NCH, true>), tg, block, 0, st, g, mesh, halo);         \

@@ -13,6 +13,8 @@
 // record instead of the displacement.  Reductions that feed gradients (pi.a, (delta - target)^2) are
 // written as per-workgroup FP64 partial sums and combined in a fixed order,
 // so they are deterministic.
+#include <type_traits>
+
 #include "tiles.h"
 
 namespace pmx {
@@ -40,9 +42,105 @@ struct GatherP {
   const unsigned* list;
   double* partials;  // per tile, slot 1: sum cot.a
   const float4* rec; // FP32 meshes: the binning's CIC records
+  bool vec_box;      // the box rows can be read as 16-byte vectors (see load_box)
 };
 
 constexpr int kGatherThreads = 512;  // threads per tile workgroup of the gather
+
+// The tile's box of NF fields into LDS, [c][lx][ly][lz] with rows of
+// ez = tz + 1 cells.  With VEC (tz a multiple of the 16-byte vector and the
+// fields 16-byte aligned) the tz core cells of a row, which start on a
+// multiple of tz and never wrap, are read as 16-byte vectors and the last
+// cell (z wrapped) on its own; otherwise one cell at a time.  Every load of a
+// thread is issued before its first LDS store, so the box costs one memory
+// round trip.
+template <typename T, int NF>
+__device__ __forceinline__ void load_box(const TileGeo& g, const T* __restrict__ mesh, T* box, int o0, int o1,
+                                         int o2, bool vec) {
+  const int tid = threadIdx.x;
+  const int ex = g.tx + 1, ey = g.ty + 1, ez = g.tz + 1;
+  const int nrow = ex * ey;                      // rows per field
+  const unsigned mrow = 0xffffffffu / unsigned(nrow) + 1u, mey = 0xffffffffu / unsigned(ey) + 1u;
+  auto row_base = [&](int row, int& slot) -> int64_t {
+    const int c = fdiv_small(row, mrow);
+    const int rr = row - c * nrow;
+    const int lx = fdiv_small(rr, mey);
+    const int ly = rr - lx * ey;
+    slot = c * kBoxMax + rr * ez;
+    return int64_t(c) * g.ncell + (int64_t((o0 + lx) & (g.n0 - 1)) * g.n1 + ((o1 + ly) & (g.n1 - 1))) * g.n2;
+  };
+  constexpr int VW = 16 / sizeof(T);             // cells per 16-byte vector
+  using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+  constexpr int kRowsMax = 9 * 9;                // rows of the largest box
+  if (vec) {
+    const int lvr = g.ltz - ilog2c(VW);          // log2 of vectors per row core
+    constexpr int ITV = (NF * kRowsMax * (16 / VW) + kGatherThreads - 1) / kGatherThreads;
+    constexpr int ITT = (NF * kRowsMax + kGatherThreads - 1) / kGatherThreads;
+    V vv[ITV];
+    T tv[ITT];
+    int vslot[ITV], tslot[ITT];
+#pragma unroll
+    for (int it = 0; it < ITV; ++it) {
+      const int v = tid + it * kGatherThreads;
+      vslot[it] = -1;
+      if (v < (NF * nrow) << lvr) {
+        const int row = v >> lvr, q = v & ((1 << lvr) - 1);
+        int slot;
+        const int64_t base = row_base(row, slot);
+        vv[it] = *reinterpret_cast<const V*>(mesh + base + o2 + q * VW);
+        vslot[it] = slot + q * VW;
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < ITT; ++it) {
+      const int row = tid + it * kGatherThreads;
+      tslot[it] = -1;
+      if (row < NF * nrow) {
+        int slot;
+        const int64_t base = row_base(row, slot);
+        tv[it] = mesh[base + ((o2 + g.tz) & (g.n2 - 1))];
+        tslot[it] = slot + g.tz;
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < ITV; ++it)
+      if (vslot[it] >= 0) {
+        const T* e = reinterpret_cast<const T*>(&vv[it]);
+#pragma unroll
+        for (int k = 0; k < VW; ++k) box[vslot[it] + k] = e[k];
+      }
+#pragma unroll
+    for (int it = 0; it < ITT; ++it)
+      if (tslot[it] >= 0) box[tslot[it]] = tv[it];
+    return;
+  }
+  constexpr int ITER = (NF * kBoxMax + kGatherThreads - 1) / kGatherThreads;
+  const int nbox = nrow * ez;
+  const unsigned mez = 0xffffffffu / unsigned(ez) + 1u;
+  const unsigned mbox = 0xffffffffu / unsigned(nbox) + 1u;
+  T bv[ITER];
+  int slot[ITER];
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int i = tid + it * kGatherThreads;
+    slot[it] = -1;
+    if (i < NF * nbox) {
+      const int c = fdiv_small(i, mbox);
+      const int r = i - c * nbox;
+      const int lxy = fdiv_small(r, mez);
+      const int lz = r - lxy * ez;
+      const int lx = fdiv_small(lxy, mey);
+      const int ly = lxy - lx * ey;
+      const int64_t cell = (int64_t((o0 + lx) & (g.n0 - 1)) * g.n1 + ((o1 + ly) & (g.n1 - 1))) * g.n2 +
+                           ((o2 + lz) & (g.n2 - 1));
+      bv[it] = mesh[c * g.ncell + cell];
+      slot[it] = c * kBoxMax + r;
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < ITER; ++it)
+    if (slot[it] >= 0) box[slot[it]] = bv[it];
+}
 
 template <typename S, typename T, int MODE, int NF>
 __global__ __launch_bounds__(kGatherThreads) void k_gather_tiles(GatherP<S, T> a) {
@@ -56,8 +154,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_tiles(GatherP<S, T> a
   const TileGeo& g = a.g;
   __shared__ T box[NF * kBoxMax];
   const int64_t tile = tile_order(g, xcd_tile(blockIdx.x, int64_t(gridDim.x)));
-  const int ex = g.tx + 1, ey = g.ty + 1, ez = g.tz + 1;
-  const int nbox = ex * ey * ez;
+  const int ey = g.ty + 1, ez = g.tz + 1;
   int o0, o1, o2;
   tile_origin(g, tile, o0, o1, o2);
   const unsigned beg = a.offs[tile], fin = a.offs[tile + 1];
@@ -91,36 +188,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_tiles(GatherP<S, T> a
       }
     };
     load(beg);
-    // the tile's box of every field, (lx, ly) rows of ez cells.  Every load
-    // of a thread is issued before the first LDS store, so the box costs one
-    // memory round trip, not one per element.
-    {
-      constexpr int ITER = (NF * kBoxMax + kGatherThreads - 1) / kGatherThreads;
-      const unsigned mez = 0xffffffffu / unsigned(ez) + 1u, mey = 0xffffffffu / unsigned(ey) + 1u;
-      const unsigned mbox = 0xffffffffu / unsigned(nbox) + 1u;
-      T bv[ITER];
-      int slot[ITER];
-#pragma unroll
-      for (int it = 0; it < ITER; ++it) {
-        const int i = tid + it * kGatherThreads;
-        slot[it] = -1;
-        if (i < NF * nbox) {
-          const int c = fdiv_small(i, mbox);
-          const int r = i - c * nbox;
-          const int lxy = fdiv_small(r, mez);
-          const int lz = r - lxy * ez;
-          const int lx = fdiv_small(lxy, mey);
-          const int ly = lxy - lx * ey;
-          const int64_t cell = (int64_t((o0 + lx) & (g.n0 - 1)) * g.n1 + ((o1 + ly) & (g.n1 - 1))) * g.n2 +
-                               ((o2 + lz) & (g.n2 - 1));
-          bv[it] = a.mesh[c * g.ncell + cell];
-          slot[it] = c * kBoxMax + r;
-        }
-      }
-#pragma unroll
-      for (int it = 0; it < ITER; ++it)
-        if (slot[it] >= 0) box[slot[it]] = bv[it];
-    }
+    load_box<T, NF>(g, a.mesh, box, o0, o1, o2, a.vec_box);
     __syncthreads();
     for (unsigned c0 = beg;;) {
 #pragma unroll
@@ -292,6 +360,10 @@ int gather_typed(Plan* p, GatherMode mode, const GatherArgs& in, hipStream_t st)
   a.list = p->bin_list;
   a.partials = p->tile_partials;
   a.rec = static_cast<const float4*>(p->bin_rec);
+  // vector box rows need the row cores to hold whole 16-byte vectors and the
+  // fields (each ncell long, so all of them) to start 16-byte aligned
+  a.vec_box = (p->tile[2] * sizeof(T)) % 16 == 0 && (reinterpret_cast<uintptr_t>(in.mesh) & 15) == 0 &&
+              (p->ncell * sizeof(T)) % 16 == 0;
   const dim3 grid(unsigned(p->ntiles)), block(kGatherThreads);
   timing_begin(p, PM_K_GATHER, st);
 #define PM_GATHER(MODE, NF) hipLaunchKernelGGL((k_gather_tiles<S, T, MODE, NF>), grid, block, 0, st, a)

@@ -27,6 +27,8 @@ class SimConfig:
     # steps j (1..n_steps) whose forward state (s_j, p_{j-1/2}) is saved for
     # the piecewise reverse pass (Sec. 3.5); empty: plain reverse integration
     checkpoint_steps: tuple = ()
+    # fixed-point paint (bitwise reproducible) or floating-point LDS atomics
+    deterministic: bool = True
 
     @property
     def n_particles(self):
@@ -41,7 +43,8 @@ class Simulation:
     def __init__(self, cfg: SimConfig):
         self.cfg = cfg
         self.plan = api.Plan(cfg.n_mesh, cfg.n_ptcl, box=cfg.box, lattice_offset=cfg.lattice_offset,
-                             mesh_dtype=cfg.mesh_dtype, state_dtype=cfg.state_dtype)
+                             mesh_dtype=cfg.mesh_dtype, state_dtype=cfg.state_dtype,
+                             deterministic=cfg.deterministic)
         dev = self.plan.device
         n = cfg.n_particles
         self.s = torch.zeros((3, n), dtype=self.plan.sdt, device=dev)

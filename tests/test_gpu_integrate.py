@@ -414,3 +414,23 @@ def test_pass_is_reproducible_run_to_run():
     r2 = [t.clone() for t in sim.value_and_grad(omega, cosmo, target)]
     assert torch.equal(r1[0], r2[0]) and torch.equal(r1[1], r2[1])
     np.testing.assert_allclose(host(r1[2]), host(r2[2]), rtol=1e-13)
+
+
+@pytest.mark.parametrize("mdt,tol", [(torch.float64, 1e-8), (torch.float32, 1e-3)])
+def test_float_atomic_paint_end_to_end_vs_oracle(mdt, tol):
+    # the whole pass (2LPT, forward, objective, reverse-time adjoint, 2LPT
+    # VJP) with the floating-point-atomic paint against the oracle's
+    # stored-trajectory gradient
+    from paper_2211_09815_amd.simulate import SimConfig, Simulation
+    announce("float-atomic paint end to end %s" % mdt)
+    n, nm, box, steps, a0 = 8, 16, 32.0, 3, 1.0 / 16
+    ocfg = osim.SimConfig(n, nm, box, a0, 1.0, steps)
+    omega = inputs.white_noise(n, inputs.SEED_RUN)
+    target = osim.final_density(inputs.white_noise(n, inputs.SEED_TARGET), ocfg)
+    J_ref, g_ref, t_ref = osim.value_and_grad(omega, ocfg, target, mode="stored")
+    api = _api()
+    sim = Simulation(SimConfig(n, nm, box, a0, 1.0, steps, mdt, torch.float64, deterministic=False))
+    J, g, t = sim.value_and_grad(dev(omega, mdt), api.Cosmology(), dev(target, mdt))
+    assert float(J.cpu()[0]) == pytest.approx(J_ref, rel=tol)
+    assert rel_l2(host(g), g_ref) < tol
+    np.testing.assert_allclose(host(t), t_ref, rtol=tol)

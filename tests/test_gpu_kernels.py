@@ -291,3 +291,28 @@ def test_timing_method_bytes_of_a_force():
             assert nl >= 1, name
             assert mby == expect[name], name
     plan.timing_enable(())
+
+
+@pytest.mark.parametrize("mdt,tol", [(torch.float32, 2e-7), (torch.float64, 1e-13)])
+def test_float_atomic_paint_vs_oracle(mdt, tol):
+    # pm_config.deterministic = 0: the tile sums use floating-point LDS
+    # atomics instead of 64-bit fixed point; the results follow the oracle to
+    # the mesh type's rounding, like the fixed-point paint's
+    announce("float-atomic paint %s" % mdt)
+    mesh, ptcl = (32, 32, 32), (32, 32, 32)
+    plan = _plan(mesh, ptcl, mdt, torch.float64, deterministic=False)
+    q, s = _particles(ptcl, 1.0, 84, 2.0)
+    s_dev = dev(soa(s), torch.float64)
+    assert rel_l2(host(plan.paint(s_dev))[0], opm.paint(q + s, mesh)) < tol
+    w = inputs.normal((3, len(q)), 85)
+    m3 = host(plan.paint(s_dev, dev(w, mdt)))
+    for c in range(3):
+        assert rel_l2(m3[c], opm.paint(q + s, mesh, w[c])) < 10 * tol
+    ftol = 1e-5 if mdt == torch.float32 else 1e-12
+    a = aos(host(plan.force(s_dev, 0.3)))
+    assert rel_l2(a, opm.force(q + s, mesh, len(q), 0.45)) < ftol
+    abar = inputs.normal((len(q), 3), 86)
+    xbar, ombar, _ = plan.force_vjp(s_dev, dev(soa(abar), mdt), 0.3)
+    xb_ref, cb_ref, _ = opm.force_vjp(q + s, abar, mesh, len(q), 0.45)
+    assert rel_l2(aos(host(xbar)), xb_ref) < 2 * ftol
+    assert abs(host(ombar)[0] - 1.5 * cb_ref) < 2 * ftol * abs(1.5 * cb_ref)
