@@ -706,7 +706,10 @@ int pm_run_fwd_ckpt(pm_plan h, pm_state* stt, const pm_step_coef* coefs, int n, 
     if (int rc = check_step(p, &coefs[i], "coefs[i]")) return rc;
   if (int rc = check_omega_m(p, omega_m)) return rc;
   if (int rc = set_device(p)) return rc;
-  // a_0 = F(x_0); the kick p_0 + a_0 Ka_1 is left pending
+  // a_0 = F(x_0); the kick p_0 + a_0 Ka_1 is left pending.  Each gather
+  // writes a in the tile order of its bins (contiguous per tile) into the
+  // plan's spare [3][N] buffer, and the next drift reads it back through the
+  // bins; the last kick writes a_n to st->acc in lattice order.
   PaintArgs pa{};
   pa.s = stt->s;
   pa.unit = 1;
@@ -716,7 +719,8 @@ int pm_run_fwd_ckpt(pm_plan h, pm_state* stt, const pm_step_coef* coefs, int n, 
   ga.s = stt->s;
   ga.mesh = p->mesh[0];
   ga.nf = 3;
-  ga.out = stt->acc;
+  ga.out = p->kick_al;
+  ga.sorted_out = true;
   ga.binned = true;
   if (int rc = gather_launch(p, GATHER_PLAIN, ga, st)) return rc;
   double Kp = coefs[0].Ka;
@@ -727,7 +731,8 @@ int pm_run_fwd_ckpt(pm_plan h, pm_state* stt, const pm_step_coef* coefs, int n, 
     pb.unit = 1;
     pb.mesh = p->mesh[0];
     pb.D = coefs[i].D;
-    pb.kick_a = stt->acc;
+    pb.kick_a = p->kick_al;
+    pb.kick_sorted = true;
     pb.Kp = Kp;
     if (int rc = paint_force_fields(p, DRIFT_FWD, pb, omega_m, st)) return rc;
     // the drift has applied the kick and moved the particles: (s_{i+1}, p_{i+1/2})
@@ -739,7 +744,7 @@ int pm_run_fwd_ckpt(pm_plan h, pm_state* stt, const pm_step_coef* coefs, int n, 
     if (int rc = gather_launch(p, GATHER_PLAIN, ga, st)) return rc;   // a_{i+1}
     Kp = coefs[i].Kb + (i + 1 < n ? coefs[i + 1].Ka : 0.0);
   }
-  return kick_flush(p, stt->p, stt->acc, Kp, false, nullptr, nullptr, 0.0, st);
+  return kick_flush(p, stt->p, p->kick_al, Kp, false, nullptr, nullptr, 0.0, stt->acc, st);
 }
 
 int pm_run_adj_ckpt(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* coefs, int n, double omega_m,
@@ -780,13 +785,15 @@ int pm_run_adj_ckpt(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* c
     if (pending) {
       pa.kick_a = stt->acc;
       pa.kick_al = p->kick_al;
+      pa.kick_sorted = true;
       pa.Kp = Kp;
       pa.Kx = Kx;
     }
     if (int rc = paint_vjp_fields(p, s_set ? DRIFT_SET : DRIFT_ADJ, pa, omega_m, st)) return rc;
     const double K = cur->Ka + (prev ? prev->Kb : 0.0);
     const double dK = cur->dKa + (prev ? prev->dKb : 0.0);
-    // a and alpha at x_i, pi.a partials; the kick p -= a K, xi += alpha K is left pending
+    // a and alpha at x_i, pi.a partials; the kick p -= a K, xi += alpha K is
+    // left pending, with a and alpha in the tile order of the bins
     GatherArgs ga{};
     ga.s = stt->s;
     ga.mesh = p->mesh[0];
@@ -794,6 +801,7 @@ int pm_run_adj_ckpt(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* c
     ga.out = p->kick_al;
     ga.acc = stt->acc;
     ga.cot = adj->pi;
+    ga.sorted_out = true;
     ga.binned = true;
     if (int rc = gather_launch(p, GATHER_VJP, ga, st)) return rc;
     const double fd[4] = {cur->dD, 0.0, 0.0, 0.0};
@@ -809,7 +817,7 @@ int pm_run_adj_ckpt(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* c
       Kp = 0.0;
     }
   }
-  if (defer && pending) return kick_flush(p, stt->p, stt->acc, Kp, true, adj->xi, p->kick_al, Kx, st);
+  if (defer && pending) return kick_flush(p, stt->p, stt->acc, Kp, true, adj->xi, p->kick_al, Kx, nullptr, st);
   return PM_OK;
 }
 

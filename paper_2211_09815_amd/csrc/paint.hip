@@ -50,6 +50,10 @@ struct BinP {
   const T* kal;
   S Kp;
   T Kx;
+  // ka / kal in the tile order of the previous binning: particle n's values
+  // at offs[key.x] + key.y of its previous key (read before it is replaced)
+  bool kick_sorted;
+  const unsigned* offs;   // the previous binning's tile offsets
   float4* rec;        // FP32 meshes: per-particle CIC record (see tiles.h)
 };
 
@@ -79,6 +83,12 @@ __global__ __launch_bounds__(kThreads) void k_bin(BinP<S, T> a) {
       const int64_t n = base + threadIdx.x + u * kThreads;
       valid[u] = n < end;
       if (!valid[u]) continue;
+      // where the pending kick of particle n is stored
+      int64_t kq = n;
+      if (KICK && a.kick_sorted) {
+        const uint2 kp = a.keys[n];
+        kq = int64_t(a.offs[kp.x]) + kp.y;
+      }
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) {
         sv[u][ax] = (MODE == DRIFT_SET ? a.s_set : a.s)[ax * g.N + n];
@@ -87,8 +97,8 @@ __global__ __launch_bounds__(kThreads) void k_bin(BinP<S, T> a) {
           xv[u][ax] = a.xi[ax * g.N + n];
           piv[u][ax] = a.pi[ax * g.N + n];
         }
-        if (KICK) kav[u][ax] = a.ka[ax * g.N + n];
-        if (KICK && ADJ) kalv[u][ax] = a.kal[ax * g.N + n];
+        if (KICK) kav[u][ax] = a.ka[ax * g.N + kq];
+        if (KICK && ADJ) kalv[u][ax] = a.kal[ax * g.N + kq];
       }
     }
 #pragma unroll
@@ -600,6 +610,8 @@ int bin_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
   b.kal = static_cast<const T*>(in.kick_al);
   b.Kp = S(in.Kp);
   b.Kx = T(in.Kx);
+  b.kick_sorted = in.kick_sorted;
+  b.offs = p->bin_offs;
   b.rec = static_cast<float4*>(p->bin_rec);
   const bool kick = in.kick_a != nullptr;
   const bool adj = mode == DRIFT_ADJ || mode == DRIFT_SET;
@@ -618,8 +630,10 @@ int bin_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
     if (mode == DRIFT_FWD) method += 6 * N * sb;
     if (adj) method += 6 * N * sb + 9 * N * mb;
     if (kick) method += 3 * N * (mb + sb) + (adj ? 6 * N * mb : 0.0);
-    // the implementation adds the (tile, rank) keys and the CIC records
-    timing_end(p, PM_K_BIN, st, method + 8 * N + (b.rec ? 16 * N : 0.0), method);
+    // the implementation adds the (tile, rank) keys (also read, for a kick
+    // stored in tile order) and the CIC records
+    timing_end(p, PM_K_BIN, st, method + 8 * N + (kick && in.kick_sorted ? 8 * N : 0.0) + (b.rec ? 16 * N : 0.0),
+               method);
   }
   const int64_t nt = g.ntiles;
   const int nsb = int((nt + 4 * kThreads - 1) / (4 * kThreads));

@@ -43,6 +43,7 @@ struct GatherP {
   double* partials;  // per tile, slot 1: sum cot.a
   const float4* rec; // FP32 meshes: the binning's CIC records
   bool vec_box;      // the box rows can be read as 16-byte vectors (see load_box)
+  bool sorted;       // PLAIN / VJP outputs at the list position (GatherArgs::sorted_out)
 };
 
 constexpr int kGatherThreads = 512;  // threads per tile workgroup of the gather
@@ -195,6 +196,9 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_tiles(GatherP<S, T> a
       for (int k = 0; k < P; ++k) {
         if (nn[k] == NONE) continue;
         const int64_t n = nn[k];
+        // where this particle's PLAIN / VJP outputs go: its lattice index, or
+        // its position in the tile lists (contiguous per tile)
+        const int64_t o = a.sorted ? int64_t(c0) + tid + k * kGatherThreads : n;
         int l0, l1, l2;
         T d0, d1, d2;
         if constexpr (REC) {
@@ -249,7 +253,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_tiles(GatherP<S, T> a
             }
         if (MODE == GATHER_PLAIN) {
 #pragma unroll
-          for (int c = 0; c < NF; ++c) a.out[c * g.N + n] = v[c];
+          for (int c = 0; c < NF; ++c) a.out[c * g.N + o] = v[c];
         } else if (KICKF) {
 #pragma unroll
           for (int ax = 0; ax < 3; ++ax) {
@@ -260,8 +264,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_tiles(GatherP<S, T> a
         } else if (MODE == GATHER_VJP) {
 #pragma unroll
           for (int ax = 0; ax < 3; ++ax) {
-            a.out[ax * g.N + n] = dv[ax];
-            if (a.acc) a.acc[ax * g.N + n] = v[ax];
+            a.out[ax * g.N + o] = dv[ax];
+            if (a.acc) a.acc[ax * g.N + o] = v[ax];
             ca += double(cot[ax]) * double(v[ax]);
           }
         } else if (KICKA) {
@@ -360,6 +364,7 @@ int gather_typed(Plan* p, GatherMode mode, const GatherArgs& in, hipStream_t st)
   a.list = p->bin_list;
   a.partials = p->tile_partials;
   a.rec = static_cast<const float4*>(p->bin_rec);
+  a.sorted = in.sorted_out;
   // vector box rows need the row cores to hold whole 16-byte vectors and the
   // fields (each ncell long, so all of them) to start 16-byte aligned
   a.vec_box = (p->tile[2] * sizeof(T)) % 16 == 0 && (reinterpret_cast<uintptr_t>(in.mesh) & 15) == 0 &&
@@ -405,38 +410,53 @@ int gather_typed(Plan* p, GatherMode mode, const GatherArgs& in, hipStream_t st)
 }  // namespace
 
 // p += a Kp (or -=, adjoint) and xi += alpha Kx: a kick left pending by the
-// last gather of a native loop, with the fused multiply-adds of the drift
+// last gather of a native loop, with the fused multiply-adds of the drift.
+// a and al are in the tile order of the last binning: particle n's values
+// sit at offs[key.x] + key.y.  acc_out (forward, optional) receives a in
+// lattice order.
 template <typename S, typename T, bool ADJ>
 __global__ __launch_bounds__(kThreads) void k_kick_flush(S* __restrict__ p, const T* __restrict__ a, S Kp,
                                                          T* __restrict__ xi, const T* __restrict__ al, T Kx,
-                                                         int64_t n3) {
+                                                         const uint2* __restrict__ keys,
+                                                         const unsigned* __restrict__ offs, T* __restrict__ acc_out,
+                                                         int64_t N) {
   const int64_t stride = int64_t(gridDim.x) * kThreads;
-  for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n3; i += stride) {
-    p[i] = fma(ADJ ? -S(a[i]) : S(a[i]), Kp, p[i]);
-    if (ADJ) xi[i] = fma(al[i], Kx, xi[i]);
+  for (int64_t n = int64_t(blockIdx.x) * kThreads + threadIdx.x; n < N; n += stride) {
+    const uint2 key = keys[n];
+    const int64_t q = int64_t(offs[key.x]) + key.y;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const T av = a[ax * N + q];
+      p[ax * N + n] = fma(ADJ ? -S(av) : S(av), Kp, p[ax * N + n]);
+      if (ADJ) xi[ax * N + n] = fma(al[ax * N + q], Kx, xi[ax * N + n]);
+      if (acc_out) acc_out[ax * N + n] = av;
+    }
   }
 }
 
 template <typename S, typename T>
 void kick_flush_typed(Plan* p, void* ps, const void* a, double Kp, bool adjoint, void* xi, const void* al,
-                      double Kx, hipStream_t st) {
-  const int64_t n3 = 3 * p->nptcl;
-  const int64_t need = (n3 + kThreads - 1) / kThreads;
+                      double Kx, void* acc_out, hipStream_t st) {
+  const int64_t N = p->nptcl;
+  const int64_t need = (N + kThreads - 1) / kThreads;
   const int blocks = int(need < 4096 ? need : 4096);
+  const uint2* keys = static_cast<const uint2*>(p->bin_keys);
   if (adjoint)
     hipLaunchKernelGGL((k_kick_flush<S, T, true>), dim3(blocks), dim3(kThreads), 0, st, static_cast<S*>(ps),
-                       static_cast<const T*>(a), S(Kp), static_cast<T*>(xi), static_cast<const T*>(al), T(Kx), n3);
+                       static_cast<const T*>(a), S(Kp), static_cast<T*>(xi), static_cast<const T*>(al), T(Kx), keys,
+                       p->bin_offs, static_cast<T*>(acc_out), N);
   else
     hipLaunchKernelGGL((k_kick_flush<S, T, false>), dim3(blocks), dim3(kThreads), 0, st, static_cast<S*>(ps),
-                       static_cast<const T*>(a), S(Kp), static_cast<T*>(xi), static_cast<const T*>(al), T(Kx), n3);
+                       static_cast<const T*>(a), S(Kp), static_cast<T*>(xi), static_cast<const T*>(al), T(Kx), keys,
+                       p->bin_offs, static_cast<T*>(acc_out), N);
 }
 
 int kick_flush(Plan* p, void* ps, const void* a, double Kp, bool adjoint, void* xi, const void* al, double Kx,
-               hipStream_t st) {
+               void* acc_out, hipStream_t st) {
   const bool s64 = p->cfg.state_dtype == PM_F64, m64 = p->cfg.mesh_dtype == PM_F64;
-  if (m64) kick_flush_typed<double, double>(p, ps, a, Kp, adjoint, xi, al, Kx, st);
-  else if (s64) kick_flush_typed<double, float>(p, ps, a, Kp, adjoint, xi, al, Kx, st);
-  else kick_flush_typed<float, float>(p, ps, a, Kp, adjoint, xi, al, Kx, st);
+  if (m64) kick_flush_typed<double, double>(p, ps, a, Kp, adjoint, xi, al, Kx, acc_out, st);
+  else if (s64) kick_flush_typed<double, float>(p, ps, a, Kp, adjoint, xi, al, Kx, acc_out, st);
+  else kick_flush_typed<float, float>(p, ps, a, Kp, adjoint, xi, al, Kx, acc_out, st);
   PM_HIP_CHECK(p, hipGetLastError());
   return PM_OK;
 }

@@ -216,10 +216,16 @@ struct PaintArgs {
   const void* kick_a;   // [3][N] mesh dtype a
   const void* kick_al;  // [3][N] mesh dtype alpha (adjoint)
   double Kp, Kx;
+  // the pending a (and alpha) are in the tile order of the previous binning
+  // (the gather wrote them at each particle's list position): particle n's
+  // values are at offs[key.x] + key.y of its previous (tile, rank) key
+  bool kick_sorted;
 };
-// apply a pending kick without a drift (the end of a native loop)
+// apply a pending kick without a drift (the end of a native loop); a and al
+// are in the tile order of the last binning (see PaintArgs::kick_sorted);
+// acc_out (optional): a in lattice order
 int kick_flush(Plan* p, void* pstate, const void* a, double Kp, bool adjoint, void* xi, const void* al, double Kx,
-               hipStream_t st);
+               void* acc_out, hipStream_t st);
 int paint_launch(Plan* p, DriftMode mode, const PaintArgs& a, hipStream_t st);
 // tile binning only (drift + bins + per-tile lists), as done by paint_launch
 int bin_launch(Plan* p, DriftMode mode, const PaintArgs& a, hipStream_t st);
@@ -246,6 +252,10 @@ struct GatherArgs {
   const void* cot;      // cotangent [3][N] (abar or pi)
   const void* acc_in;   // cached accelerations for the adjoint kick (optional)
   bool binned;          // the plan's tile bins already match s (set after a paint of s)
+  // PLAIN and VJP: write out (and acc) at each particle's position in the
+  // tile lists instead of its lattice index (contiguous per tile), for a
+  // consumer that looks them up through the bins (PaintArgs::kick_sorted)
+  bool sorted_out;
   double K;
   double* partials;     // per-block partial of cot . a
 };
