@@ -50,8 +50,10 @@ struct BinP {
   const T* kal;
   S Kp;
   T Kx;
-  // ka / kal in the tile order of the previous binning: particle n's values
-  // at offs[key.x] + key.y of its previous key (read before it is replaced)
+  // ka / kal in the tile order of the previous binning, particle-major:
+  // particle n's values at 3 (offs[key.x] + key.y) + ax of its previous key
+  // (read before it is replaced); else [3][N] at ax N + n (selects k_bin's
+  // KICK = 2 over 1)
   bool kick_sorted;
   const unsigned* offs;   // the previous binning's tile offsets
   float4* rec;        // FP32 meshes: per-particle CIC record (see tiles.h)
@@ -61,7 +63,11 @@ struct BinP {
 // a wavefront that share a tile form a group; the group leaders then issue
 // their count atomics together (one instruction, one round trip), and every
 // lane takes its rank from its leader's result.
-template <typename S, typename T, int MODE, bool KICK>
+// KICK: 0 none; 1 a pending kick in lattice order ([3][N]); 2 in the tile
+// order of the previous binning (BinP::kick_sorted), looked up through the
+// previous keys: those loads go first, then the state's, and the dependent
+// ones last, so that their round trips overlap the state's.
+template <typename S, typename T, int MODE, int KICK>
 __global__ __launch_bounds__(kThreads) void k_bin(BinP<S, T> a) {
   static_assert(!KICK || MODE != DRIFT_NONE, "a pending kick comes with a drift");
   constexpr bool ADJ = MODE == DRIFT_ADJ || MODE == DRIFT_SET;
@@ -75,19 +81,29 @@ __global__ __launch_bounds__(kThreads) void k_bin(BinP<S, T> a) {
   auto fold = [](double m, double a) { return (a > m || a != a) ? a : m; };
   for (int64_t base = start; base < end; base += U * kThreads) {
     S sv[U][3], pv[U][3];
-    T xv[U][3], piv[U][3], kav[U][KICK ? 3 : 1], kalv[U][KICK && ADJ ? 3 : 1];
+    T xv[U][3], piv[U][3], kav[U][KICK != 0 ? 3 : 1], kalv[U][KICK != 0 && ADJ ? 3 : 1];
     bool valid[U];
     int tile[U];
+    uint2 kp[U];
+    // the kick lookups are issued for every lane, past the end with the
+    // chunk's last particle, so that no load sits under a branch (a branch
+    // makes the compiler wait for all loads in flight at its join)
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t n = base + threadIdx.x + u * kThreads;
       valid[u] = n < end;
+      if (KICK == 2) kp[u] = a.keys[valid[u] ? n : end - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t n = base + threadIdx.x + u * kThreads;
       if (!valid[u]) continue;
-      // where the pending kick of particle n is stored
-      int64_t kq = n;
-      if (KICK && a.kick_sorted) {
-        const uint2 kp = a.keys[n];
-        kq = int64_t(a.offs[kp.x]) + kp.y;
+      if (KICK == 1) {
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          kav[u][ax] = a.ka[ax * g.N + n];
+          if (ADJ) kalv[u][ax] = a.kal[ax * g.N + n];
+        }
       }
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) {
@@ -97,8 +113,25 @@ __global__ __launch_bounds__(kThreads) void k_bin(BinP<S, T> a) {
           xv[u][ax] = a.xi[ax * g.N + n];
           piv[u][ax] = a.pi[ax * g.N + n];
         }
-        if (KICK) kav[u][ax] = a.ka[ax * g.N + kq];
-        if (KICK && ADJ) kalv[u][ax] = a.kal[ax * g.N + kq];
+      }
+    }
+    if constexpr (KICK == 2) {
+      // the pending kick of particle n, particle-major at its previous
+      // (tile, rank) position
+      unsigned ob[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) ob[u] = a.offs[kp[u].x];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t kq = int64_t(ob[u]) + kp[u].y;
+        const Comp3<T> k3 = reinterpret_cast<const Comp3<T>*>(a.ka)[kq];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) kav[u][ax] = k3.c[ax];
+        if (ADJ) {
+          const Comp3<T> l3 = reinterpret_cast<const Comp3<T>*>(a.kal)[kq];
+#pragma unroll
+          for (int ax = 0; ax < 3; ++ax) kalv[u][ax] = l3.c[ax];
+        }
       }
     }
 #pragma unroll
@@ -106,7 +139,7 @@ __global__ __launch_bounds__(kThreads) void k_bin(BinP<S, T> a) {
       tile[u] = 0;
       if (!valid[u]) continue;
       const int64_t n = base + threadIdx.x + u * kThreads;
-      if constexpr (KICK) {
+      if constexpr (KICK != 0) {
         // the same fused multiply-adds as the gather's immediate kicks
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
@@ -617,10 +650,17 @@ int bin_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
   const bool adj = mode == DRIFT_ADJ || mode == DRIFT_SET;
   timing_begin(p, PM_K_BIN, st);
 #define PM_BIN(MODE, KICK) hipLaunchKernelGGL((k_bin<S, T, MODE, KICK>), dim3(pblocks), block, 0, st, b)
-  if (mode == DRIFT_FWD) { if (kick) PM_BIN(DRIFT_FWD, true); else PM_BIN(DRIFT_FWD, false); }
-  else if (mode == DRIFT_ADJ) { if (kick) PM_BIN(DRIFT_ADJ, true); else PM_BIN(DRIFT_ADJ, false); }
-  else if (mode == DRIFT_SET) { if (kick) PM_BIN(DRIFT_SET, true); else PM_BIN(DRIFT_SET, false); }
-  else PM_BIN(DRIFT_NONE, false);
+#define PM_BIN_K(MODE)                     \
+  do {                                     \
+    if (!kick) PM_BIN(MODE, 0);            \
+    else if (in.kick_sorted) PM_BIN(MODE, 2); \
+    else PM_BIN(MODE, 1);                  \
+  } while (0)
+  if (mode == DRIFT_FWD) PM_BIN_K(DRIFT_FWD);
+  else if (mode == DRIFT_ADJ) PM_BIN_K(DRIFT_ADJ);
+  else if (mode == DRIFT_SET) PM_BIN_K(DRIFT_SET);
+  else PM_BIN(DRIFT_NONE, 0);
+#undef PM_BIN_K
 #undef PM_BIN
   {
     // s (or s_set) read (+ p read, s write; adjoint: xi read, pi read/write),

@@ -43,7 +43,7 @@ struct GatherP {
   double* partials;  // per tile, slot 1: sum cot.a
   const float4* rec; // FP32 meshes: the binning's CIC records
   bool vec_box;      // the box rows can be read as 16-byte vectors (see load_box)
-  bool sorted;       // PLAIN / VJP outputs at the list position (GatherArgs::sorted_out)
+  bool sorted;       // PLAIN / VJP outputs particle-major at the list position (GatherArgs::sorted_out)
 };
 
 constexpr int kGatherThreads = 512;  // threads per tile workgroup of the gather
@@ -144,7 +144,8 @@ __device__ __forceinline__ void load_box(const TileGeo& g, const T* __restrict__
 }
 
 template <typename S, typename T, int MODE, int NF>
-__global__ __launch_bounds__(kGatherThreads) void k_gather_tiles(GatherP<S, T> a) {
+// the VJP gather keeps three workgroups per CU (six waves per SIMD)
+__global__ __launch_bounds__(kGatherThreads, MODE == GATHER_VJP ? 6 : 1) void k_gather_tiles(GatherP<S, T> a) {
   // particles per thread per chunk: one for the adjoint modes, whose register
   // use would otherwise hold the CU to two workgroups
   constexpr int P = (MODE == GATHER_KICK_ADJ || MODE == GATHER_VJP ? 512 : 1024) / kGatherThreads;
@@ -196,8 +197,9 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_tiles(GatherP<S, T> a
       for (int k = 0; k < P; ++k) {
         if (nn[k] == NONE) continue;
         const int64_t n = nn[k];
-        // where this particle's PLAIN / VJP outputs go: its lattice index, or
-        // its position in the tile lists (contiguous per tile)
+        // where this particle's PLAIN / VJP outputs go: its lattice index
+        // ([c][N]), or its position in the tile lists, particle-major
+        // ([pos][3], contiguous per tile)
         const int64_t o = a.sorted ? int64_t(c0) + tid + k * kGatherThreads : n;
         int l0, l1, l2;
         T d0, d1, d2;
@@ -252,8 +254,15 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_tiles(GatherP<S, T> a
               }
             }
         if (MODE == GATHER_PLAIN) {
+          if (NF == 3 && a.sorted) {
+            Comp3<T> r;
 #pragma unroll
-          for (int c = 0; c < NF; ++c) a.out[c * g.N + o] = v[c];
+            for (int c = 0; c < 3; ++c) r.c[c] = v[c];
+            reinterpret_cast<Comp3<T>*>(a.out)[o] = r;
+          } else {
+#pragma unroll
+            for (int c = 0; c < NF; ++c) a.out[c * g.N + o] = v[c];
+          }
         } else if (KICKF) {
 #pragma unroll
           for (int ax = 0; ax < 3; ++ax) {
@@ -263,10 +272,22 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_tiles(GatherP<S, T> a
           }
         } else if (MODE == GATHER_VJP) {
 #pragma unroll
-          for (int ax = 0; ax < 3; ++ax) {
-            a.out[ax * g.N + o] = dv[ax];
-            if (a.acc) a.acc[ax * g.N + o] = v[ax];
-            ca += double(cot[ax]) * double(v[ax]);
+          for (int ax = 0; ax < 3; ++ax) ca += double(cot[ax]) * double(v[ax]);
+          if (a.sorted) {
+            Comp3<T> r, q;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+              r.c[ax] = dv[ax];
+              q.c[ax] = v[ax];
+            }
+            reinterpret_cast<Comp3<T>*>(a.out)[o] = r;
+            if (a.acc) reinterpret_cast<Comp3<T>*>(a.acc)[o] = q;
+          } else {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+              a.out[ax * g.N + o] = dv[ax];
+              if (a.acc) a.acc[ax * g.N + o] = v[ax];
+            }
           }
         } else if (KICKA) {
           if (a.acc_in) {
@@ -349,6 +370,8 @@ __global__ __launch_bounds__(kThreads) void k_reduce_stage(const double* stage, 
 
 template <typename S, typename T>
 int gather_typed(Plan* p, GatherMode mode, const GatherArgs& in, hipStream_t st) {
+  if (in.sorted_out && !((mode == GATHER_PLAIN && in.nf == 3) || mode == GATHER_VJP))
+    return set_error(p, PM_EINVAL, "tile-order outputs are three components per particle");
   GatherP<S, T> a;
   a.g = tile_geo(p);
   a.s = static_cast<const S*>(in.s);
@@ -411,9 +434,9 @@ int gather_typed(Plan* p, GatherMode mode, const GatherArgs& in, hipStream_t st)
 
 // p += a Kp (or -=, adjoint) and xi += alpha Kx: a kick left pending by the
 // last gather of a native loop, with the fused multiply-adds of the drift.
-// a and al are in the tile order of the last binning: particle n's values
-// sit at offs[key.x] + key.y.  acc_out (forward, optional) receives a in
-// lattice order.
+// a and al are particle-major in the tile order of the last binning:
+// particle n's values sit at 3 (offs[key.x] + key.y) + 0..2.  acc_out
+// (forward, optional) receives a in lattice order.
 template <typename S, typename T, bool ADJ>
 __global__ __launch_bounds__(kThreads) void k_kick_flush(S* __restrict__ p, const T* __restrict__ a, S Kp,
                                                          T* __restrict__ xi, const T* __restrict__ al, T Kx,
@@ -424,11 +447,14 @@ __global__ __launch_bounds__(kThreads) void k_kick_flush(S* __restrict__ p, cons
   for (int64_t n = int64_t(blockIdx.x) * kThreads + threadIdx.x; n < N; n += stride) {
     const uint2 key = keys[n];
     const int64_t q = int64_t(offs[key.x]) + key.y;
+    const Comp3<T> a3 = reinterpret_cast<const Comp3<T>*>(a)[q];
+    Comp3<T> l3{};
+    if (ADJ) l3 = reinterpret_cast<const Comp3<T>*>(al)[q];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const T av = a[ax * N + q];
+      const T av = a3.c[ax];
       p[ax * N + n] = fma(ADJ ? -S(av) : S(av), Kp, p[ax * N + n]);
-      if (ADJ) xi[ax * N + n] = fma(al[ax * N + q], Kx, xi[ax * N + n]);
+      if (ADJ) xi[ax * N + n] = fma(l3.c[ax], Kx, xi[ax * N + n]);
       if (acc_out) acc_out[ax * N + n] = av;
     }
   }

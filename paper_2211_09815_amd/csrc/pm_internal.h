@@ -217,12 +217,14 @@ struct PaintArgs {
   const void* kick_al;  // [3][N] mesh dtype alpha (adjoint)
   double Kp, Kx;
   // the pending a (and alpha) are in the tile order of the previous binning
-  // (the gather wrote them at each particle's list position): particle n's
-  // values are at offs[key.x] + key.y of its previous (tile, rank) key
+  // (the gather wrote them at each particle's list position), particle-major:
+  // particle n's three values are at 3 (offs[key.x] + key.y) + 0..2 of its
+  // previous (tile, rank) key
   bool kick_sorted;
 };
 // apply a pending kick without a drift (the end of a native loop); a and al
-// are in the tile order of the last binning (see PaintArgs::kick_sorted);
+// are particle-major in the tile order of the last binning (see
+// PaintArgs::kick_sorted);
 // acc_out (optional): a in lattice order
 int kick_flush(Plan* p, void* pstate, const void* a, double Kp, bool adjoint, void* xi, const void* al, double Kx,
                void* acc_out, hipStream_t st);
@@ -252,9 +254,10 @@ struct GatherArgs {
   const void* cot;      // cotangent [3][N] (abar or pi)
   const void* acc_in;   // cached accelerations for the adjoint kick (optional)
   bool binned;          // the plan's tile bins already match s (set after a paint of s)
-  // PLAIN and VJP: write out (and acc) at each particle's position in the
-  // tile lists instead of its lattice index (contiguous per tile), for a
-  // consumer that looks them up through the bins (PaintArgs::kick_sorted)
+  // PLAIN (nf = 3) and VJP: write out (and acc) at each particle's position
+  // in the tile lists instead of its lattice index, particle-major ([pos][3],
+  // contiguous per tile), for a consumer that looks them up through the bins
+  // (PaintArgs::kick_sorted)
   bool sorted_out;
   double K;
   double* partials;     // per-block partial of cot . a

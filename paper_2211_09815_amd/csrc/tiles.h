@@ -88,6 +88,14 @@ __device__ __forceinline__ int fdiv_small(int r, unsigned m) { return int(__umul
 // pm_plan_create refuses any plan beyond them.
 template <typename T> constexpr bool kUseRec = sizeof(T) == 4;
 
+// three components of one particle, stored particle-major (the pending kicks
+// in tile order): one 12- or 24-byte access per lane instead of three strided
+// ones
+template <typename T>
+struct Comp3 {
+  T c[3];
+};
+
 __device__ __forceinline__ unsigned pack_cell(int b0, int b1, int b2) {
   return (unsigned(b0) << 20) | (unsigned(b1) << 10) | unsigned(b2);
 }
