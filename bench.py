@@ -460,6 +460,84 @@ def study_force(args, reps=10):
             "kernel_families": fams, "peak_GBps": HBM_PEAK_GBS}
 
 
+def study_cpu_oracle(args, reps=3, n=256, nm=512):
+    """The FP64 oracle (numpy, as it stands) on the host, stage by stage, at
+    the single-force shape: 256^3 particles displaced by the oracle's 2LPT at
+    a = 0.5 on a 512^3 mesh in a 512 Mpc/h box, Gaussian cotangent.  Each
+    stage is timed `reps` times after a warm-up (median).  Beside it, the FFT
+    stages with scipy.fft on every host core (a library FFT, not the oracle).
+    The whole 512^3 pass per particle-step is then extrapolated: the mesh
+    stages of one force and one force VJP as measured, their particle stages
+    scaled by 8 (512^3 particles), over 512^3 particle-steps.  Needs no GPU."""
+    import numpy as np
+    import scipy.fft
+
+    from oracle import cosmology, lpt, pm, simulate
+    from paper_2211_09815_amd import inputs
+    box = float(nm)
+    shape = (nm, nm, nm)
+    cfg = simulate.SimConfig(n, nm, box, 0.5, 1.0, 1)
+    omega = inputs.white_noise(n, inputs.SEED_RUN)
+    t0 = time.perf_counter()
+    s0, _ = lpt.lpt(omega, cfg.box, cfg.cosmo, 0.5, cfg.r)
+    t_lpt = time.perf_counter() - t0
+    x = simulate.lattice(cfg) + s0
+    N = n ** 3
+    coef = 1.5 * cfg.cosmo.omega_m
+    abar = inputs.normal((N, 3), inputs.SEED_COTANGENT)
+    workers = os.cpu_count() or 1
+
+    def timed(fn):
+        fn()
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts))
+
+    delta = pm.density_contrast(x, shape, N)
+    dk = np.fft.rfftn(delta)
+    gk = pm.poisson_gradient(dk, shape, coef)
+    g = [np.fft.irfftn(gj, s=shape, axes=(0, 1, 2)) for gj in gk]
+    rows = {
+        "paint (density contrast)": timed(lambda: pm.density_contrast(x, shape, N)),
+        "r2c (numpy, 1 core)": timed(lambda: np.fft.rfftn(delta)),
+        "poisson gradient": timed(lambda: pm.poisson_gradient(dk, shape, coef)),
+        "3x c2r (numpy, 1 core)": timed(lambda: [np.fft.irfftn(gj, s=shape, axes=(0, 1, 2)) for gj in gk]),
+        "readout (3 fields)": timed(lambda: [pm.readout(x, gj) for gj in g]),
+        "force": timed(lambda: pm.force(x, shape, N, coef)),
+        "force VJP": timed(lambda: pm.force_vjp(x, abar, shape, N, coef)),
+    }
+    lib = {
+        "r2c (scipy.fft, %d workers)" % workers: timed(lambda: scipy.fft.rfftn(delta, workers=workers)),
+        "3x c2r (scipy.fft, %d workers)" % workers:
+            timed(lambda: [scipy.fft.irfftn(gj, s=shape, axes=(0, 1, 2), workers=workers) for gj in gk]),
+    }
+    # mesh and particle parts of the force and of the VJP (the VJP runs one
+    # r2c and three c2r for the force, three r2c and one c2r for the
+    # cotangent fields, and the multipliers twice)
+    t_fft1 = rows["r2c (numpy, 1 core)"]
+    t_c2r = rows["3x c2r (numpy, 1 core)"] / 3
+    t_mul = rows["poisson gradient"]
+    mesh_force = t_fft1 + t_mul + 3 * t_c2r
+    mesh_vjp = 4 * t_fft1 + 2 * t_mul + 4 * t_c2r
+    part_force = max(rows["force"] - mesh_force, 0.0)
+    part_vjp = max(rows["force VJP"] - mesh_vjp, 0.0)
+    n4 = 512
+    scale = (n4 / n) ** 3
+    t_step = mesh_force + scale * part_force + mesh_vjp + scale * part_vjp
+    return {"study": "cpu-oracle", "workload": "%d^3 particles (oracle 2LPT at a=0.5), %d^3 FP64 mesh, "
+            "%g Mpc/h; cotangent seed %d" % (n, nm, box, inputs.SEED_COTANGENT), "reps": reps, "lpt_s": t_lpt,
+            "oracle_stage_s": rows, "library_fft_s": lib, "host_cpus": workers,
+            "oracle_cores": 1,
+            "extrapolated_512": {
+                "s_per_step": t_step, "particle_steps_per_s": n4 ** 3 / t_step,
+                "note": "extrapolated, not measured: one force (forward) and one force VJP (adjoint) per "
+                        "step at 512^3 particles on a 512^3 mesh; mesh stages as measured at 512^3, "
+                        "particle stages x8 from 256^3"}}
+
+
 def study_paint_modes(args):
     """The fixed-point paint against the floating-point-atomic one, and the
     precision modes against each other (Sec. 4.1, Tables rep and rev): per
@@ -712,20 +790,26 @@ def main():
     ap.add_argument("--no-fp64-ref", action="store_true",
                     help="skip the all-FP64 reference pass used for the errors against FP64")
     ap.add_argument("--study", choices=["precision", "force", "fd-theta", "checkpoints", "lightcone",
-                                        "paint-modes"],
+                                        "paint-modes", "cpu-oracle"],
                     help="print a study instead of the benchmark line: precision = FP32 / mixed / FP64 "
                          "reversibility, gradient error and memory vs steps; force = single force and VJP "
                          "per stage at 256^3 particles on a 512^3 mesh; fd-theta = dJ/dtheta against central "
                          "differences; checkpoints = piecewise reverse from forward checkpoints; "
                          "lightcone = light-cone observation and its gradient; paint-modes = fixed-point vs "
                          "float-atomic paint and precision modes: speed, reproducibility, reversibility, "
-                         "gradient error, fastest mode per error target")
+                         "gradient error, fastest mode per error target; cpu-oracle = the FP64 oracle on the "
+                         "host per stage at the single-force shape, and the 512^3 rate extrapolated from it "
+                         "(no GPU)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the mesh would shard as slabs with all-to-all transposes; not built)", file=sys.stderr)
         sys.exit(2)
+
+    if args.study == "cpu-oracle":
+        print(json.dumps(study_cpu_oracle(args)), flush=True)
+        return
 
     if args.hbm_warmup > 0 and args.warmup_child and not args.study:
         # the same cycle first in a short child process, before this process
