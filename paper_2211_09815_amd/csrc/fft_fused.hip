@@ -39,6 +39,13 @@ __device__ __forceinline__ KCol<T> kcol(int64_t col, int n1, int n2, int nh) {
   return r;
 }
 
+// Elements per thread of the fused pass.  FP32 up to 512-point columns takes
+// 8 instead of the other passes' 16: the pass keeps the forward spectrum in
+// registers through the first inverse transform, which at 16 elements per
+// thread spills past the 128 VGPRs of two workgroups per CU; at 8 the tile
+// holds 8 columns (64-byte row runs) and three workgroups fit.
+constexpr int x_ept(bool f32, int logm) { return f32 && logm <= 9 ? 8 : (f32 ? 16 : 8); }
+
 // T_j = i k_j coef / k^2, zero at k = 0 and on the Nyquist plane of j.
 // GRAD3:  out_j = T_j in_0,                                j = 0..2
 // ADJ4:   out_3 = -sum_j T_j in_{1+j},  out_j = T_j in_0,  j = 0..2
@@ -50,10 +57,10 @@ template <typename T, int LOGM, int OP>
 __global__ __launch_bounds__(kFT, 4) void k_fft_x_fused(Ptrs4 ins, Ptrs4 outs, int n1, int n2, int nh, T coef,
                                                         const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
-  constexpr int EPT = Cfg<T>::EPT;
+  constexpr int EPT = x_ept(sizeof(T) == 4, LOGM);
   constexpr int LRMAX = EPT >= 16 ? 4 : 3;
   constexpr int M = 1 << LOGM;  // = n0
-  constexpr int LOGW = tile_log2<T>() - LOGM;
+  constexpr int LOGW = ilog2c(kFT * EPT) - LOGM;
   constexpr int W = 1 << LOGW;
   constexpr int S = RegPlan<LOGM, LRMAX, false>::S;
   // forward stages larger radix first, inverse stages in the reverse order,
@@ -303,10 +310,10 @@ int x_fused_pass(Plan* p, const FftShape& s, SpecOp op, const Ptrs4& in, const P
   const int nh = s.n2 / 2 + 1;
   const int logM = ilog2(s.n0);
   if (logM < 2 || logM > 10) return set_error(p, PM_EUNSUPPORTED, "FFT length %d is not supported", s.n0);
-  const int logW = tile_log2<T>() - logM;
+  const int logW = ilog2(kFT * x_ept(sizeof(T) == 4, logM)) - logM;
   const int64_t ncols = int64_t(s.n1) * nh;
   const int64_t ntiles = (ncols + (int64_t(1) << logW) - 1) >> logW;
-  const size_t lds = lds_bytes<T>(logM, logM);
+  const size_t lds = size_t((1 << logM) + (1 << logM) * ((1 << logW) + 1)) * sizeof(cplx<T>);
   const cplx<T>* tw = static_cast<const cplx<T>*>(p->tw);
   const int nin = op == SPEC_GRAD3 ? 1 : 4;
   const int nout = op == SPEC_GRAD3 ? 3 : 4;

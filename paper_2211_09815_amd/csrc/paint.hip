@@ -598,14 +598,18 @@ __global__ __launch_bounds__(kThreads) void k_halo_add(TileGeo g, T* __restrict_
     if (i < nA) { lx = 0; ly = i / g.tz; lz = i % g.tz; }
     else if (i < nA + nB) { const int k = i - nA; lx = 1 + k / g.tz; ly = 0; lz = k % g.tz; }
     else { const int k = i - nA - nB; lx = 1 + k / (g.ty - 1); ly = 1 + k % (g.ty - 1); lz = 0; }
-    T add[NCH];
+    const int64_t cell = (int64_t(t0 * g.tx + lx) * g.n1 + (t1 * g.ty + ly)) * g.n2 + (t2 * g.tz + lz);
+    // every load is issued before any is used: the cell's own values, then
+    // the halo entry of each neighbour d (a neighbour that does not touch
+    // this cell reads its own first entry and contributes +0)
+    T own[NCH], hv[7][NCH];
+    bool use[7];
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) add[c] = T(0);
+    for (int c = 0; c < NCH; ++c) own[c] = mesh[c * g.ncell + cell];
 #pragma unroll
     for (int d = 1; d < 8; ++d) {
       const int dx = d >> 2, dy = (d >> 1) & 1, dz = d & 1;
-      if ((dx && lx) || (dy && ly) || (dz && lz)) continue;
-      if (DEFER && d == 1) continue;
+      use[d - 1] = !((dx && lx) || (dy && ly) || (dz && lz)) && !(DEFER && d == 1);
       const int u0 = (t0 - dx + g.ntx) % g.ntx, u1 = (t1 - dy + g.nty) % g.nty, u2 = (t2 - dz + g.ntz) % g.ntz;
       const int64_t u = (int64_t(u0) * g.nty + u1) * g.ntz + u2;
       const int e1 = dy ? g.ty : ly, e2 = dz ? g.tz : lz;
@@ -613,12 +617,17 @@ __global__ __launch_bounds__(kThreads) void k_halo_add(TileGeo g, T* __restrict_
       if (dx) h = e1 * ez + e2;
       else if (dy) h = fx + lx * ez + e2;
       else h = fx + fy + lx * g.ty + ly;
+      if (!use[d - 1]) h = 0;
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) add[c] += halo[(int64_t(c) * g.ntiles + u) * g.hc + h];
+      for (int c = 0; c < NCH; ++c) hv[d - 1][c] = halo[(int64_t(c) * g.ntiles + u) * g.hc + h];
     }
-    const int64_t cell = (int64_t(t0 * g.tx + lx) * g.n1 + (t1 * g.ty + ly)) * g.n2 + (t2 * g.tz + lz);
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) mesh[c * g.ncell + cell] += add[c];
+    for (int c = 0; c < NCH; ++c) {
+      T add = T(0);
+#pragma unroll
+      for (int d = 0; d < 7; ++d) add += use[d] ? hv[d][c] : T(0);
+      mesh[c * g.ncell + cell] = own[c] + add;
+    }
   }
 }
 
