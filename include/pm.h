@@ -37,9 +37,10 @@
  *    host-struct arguments are DEVICE pointers on the plan's device.  The
  *    plan owns only its scratch (meshes, spectra, twiddles, reduction space,
  *    one [3][N_p] mesh-dtype array for the native adjoint loop),
- *    allocated once in pm_plan_create, plus the 2LPT lattice scratch that
- *    the first pm_lpt / pm_lpt_vjp call allocates; pm_workspace_bytes
- *    reports both.  The other calls allocate nothing.
+ *    allocated once in pm_plan_create, plus the 2LPT lattice scratch:
+ *    with cfg.lpt_scratch = 1 pm_plan_create allocates it too, and then no
+ *    call allocates; with 0 the first pm_lpt / pm_lpt_vjp call does.
+ *    pm_workspace_bytes reports both.  The other calls allocate nothing.
  *  - Streams: every call is asynchronous on the given stream (0 = default).
  *    Scalars reported on the device (J, omega_m_bar, theta_bar) are ready after
  *    the stream is synchronised.  A plan is not thread-safe; calls made with
@@ -93,18 +94,25 @@ typedef struct {
                             /* floating-point LDS atomics, whose order and so  */
                             /* rounding change from run to run (Table rep of   */
                             /* the paper discusses that effect)                */
+    int32_t lpt_scratch;    /* 1: pm_plan_create also allocates the 2LPT       */
+                            /* lattice scratch (ptcl must then be a power-of-  */
+                            /* two cube in 4..1024 and box a positive cube),   */
+                            /* so pm_lpt and pm_lpt_vjp allocate nothing; 0:   */
+                            /* the first of those calls allocates it           */
 } pm_config;
 
 /* Creates a plan on the current HIP device and allocates its scratch.
- * Errors: PM_EINVAL (NULL), PM_ESHAPE (mesh not a power of two in 4..1024,
- * a ptcl side outside 1..65536, more than 2^31 particles), PM_EUNSUPPORTED
+ * Errors: PM_EINVAL (NULL, a flag other than 0 or 1), PM_ESHAPE (mesh not a
+ * power of two in 4..1024, a ptcl side outside 1..65536, more than 2^31
+ * particles, lpt_scratch with a lattice 2LPT cannot use), PM_EUNSUPPORTED
  * (mesh_dtype F32 with state_dtype F64 is allowed; mesh F64 with state F32
  * is not), PM_ENOMEM, PM_EDEVICE. */
 int pm_plan_create(const pm_config* cfg, pm_plan* out);
 int pm_plan_destroy(pm_plan plan);
 /* Bytes of device scratch a plan for cfg holds (0 if invalid): what
  * pm_plan_create allocates, plus, for a cubic lattice, the 2LPT lattice
- * scratch that the first pm_lpt / pm_lpt_vjp call allocates. */
+ * scratch (allocated by pm_plan_create with cfg.lpt_scratch = 1, else by
+ * the first pm_lpt / pm_lpt_vjp call). */
 size_t pm_workspace_bytes(const pm_config* cfg);
 const char* pm_last_error(pm_plan plan);
 const char* pm_strerror(int code);

@@ -92,15 +92,22 @@ def ic_struct(icd):
 class Plan:
     """A libpm plan: mesh/lattice geometry, precision and device scratch.
     deterministic=True (default): the fixed-point paint, bitwise
-    reproducible; False: floating-point LDS atomics (see pm_config)."""
+    reproducible; False: floating-point LDS atomics (see pm_config).
+    lpt_scratch (default: whenever the lattice and box allow 2LPT): the plan
+    allocates the 2LPT lattice scratch up front, so no later call allocates."""
 
     def __init__(self, mesh, ptcl, box=(1.0, 1.0, 1.0), lattice_offset=0.0, mesh_dtype=torch.float32,
-                 state_dtype=torch.float64, deterministic=True):
+                 state_dtype=torch.float64, deterministic=True, lpt_scratch=None):
         mesh = tuple(int(m) for m in (mesh if np.iterable(mesh) else (mesh,) * 3))
         ptcl = tuple(int(m) for m in (ptcl if np.iterable(ptcl) else (ptcl,) * 3))
         box = tuple(float(b) for b in (box if np.iterable(box) else (box,) * 3))
+        if lpt_scratch is None:
+            n = ptcl[0]
+            lpt_scratch = (ptcl == (n, n, n) and 4 <= n <= 1024 and n & (n - 1) == 0 and box[0] > 0
+                           and box == (box[0],) * 3)
         self.cfg = PmConfig((ctypes.c_int32 * 3)(*mesh), (ctypes.c_int32 * 3)(*ptcl), (ctypes.c_double * 3)(*box),
-                            float(lattice_offset), _code(mesh_dtype), _code(state_dtype), int(bool(deterministic)))
+                            float(lattice_offset), _code(mesh_dtype), _code(state_dtype), int(bool(deterministic)),
+                            int(bool(lpt_scratch)))
         self.mesh = mesh
         self.ptcl = ptcl
         self.box = box

@@ -69,6 +69,18 @@ int validate_cfg(const pm_config* c, std::string& why) {
     return PM_EUNSUPPORTED;
   }
   if (c->deterministic != 0 && c->deterministic != 1) { why = "deterministic must be 0 or 1"; return PM_EINVAL; }
+  if (c->lpt_scratch != 0 && c->lpt_scratch != 1) { why = "lpt_scratch must be 0 or 1"; return PM_EINVAL; }
+  if (c->lpt_scratch) {
+    const int n = c->ptcl[0];
+    if (c->ptcl[1] != n || c->ptcl[2] != n || !pow2_in(n, 4, 1024)) {
+      why = "lpt_scratch needs a cubic power-of-two particle lattice in [4, 1024]";
+      return PM_ESHAPE;
+    }
+    if (!(c->box[0] > 0.0) || c->box[1] != c->box[0] || c->box[2] != c->box[0]) {
+      why = "lpt_scratch needs a cubic box of positive size";
+      return PM_EINVAL;
+    }
+  }
   const int64_t np = int64_t(c->ptcl[0]) * c->ptcl[1] * c->ptcl[2];
   if (np > (int64_t(1) << 31)) { why = "at most 2^31 particles"; return PM_ESHAPE; }
   if (!std::isfinite(c->lattice_offset)) { why = "lattice_offset must be finite"; return PM_EINVAL; }
@@ -427,6 +439,15 @@ int pm_plan_create(const pm_config* cfg, pm_plan* out) {
     (void)hipFree(p->kick_al);
     delete p;
     return set_error(nullptr, PM_EDEVICE, "plan initialisation failed");
+  }
+  if (p->cfg.lpt_scratch) {
+    // the 2LPT lattice scratch now (validate_cfg checked the lattice), so
+    // that pm_lpt / pm_lpt_vjp allocate nothing
+    if (int rc = ensure_lattice(p)) {
+      const std::string why = p->err;
+      (void)pm_plan_destroy(reinterpret_cast<pm_plan>(p));
+      return set_error(nullptr, rc, "%s", why.c_str());
+    }
   }
   *out = reinterpret_cast<pm_plan>(p);
   return PM_OK;

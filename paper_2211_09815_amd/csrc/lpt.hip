@@ -218,6 +218,8 @@ int grid_for(int64_t work) {
   return int(need < 2048 ? (need < 1 ? 1 : need) : 2048);
 }
 
+}  // namespace
+
 int check_lattice(Plan* p) {
   const int n = p->np[0];
   if (p->np[1] != n || p->np[2] != n || n < 4 || n > 1024 || (n & (n - 1)))
@@ -255,6 +257,8 @@ int ensure_lattice(Plan* p) {
   p->lpt_ready = true;
   return PM_OK;
 }
+
+namespace {
 
 template <typename T>
 struct Lat {

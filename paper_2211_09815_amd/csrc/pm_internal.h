@@ -283,6 +283,10 @@ int blocks_for_particles(const Plan* p);
 // ---------------------------------------------------------------------------
 // initial conditions (lpt.hip)
 // ---------------------------------------------------------------------------
+// 2LPT lattice: shape check, and the scratch allocated once (pm_plan_create
+// with lpt_scratch, else the first 2LPT call)
+int check_lattice(Plan* p);
+int ensure_lattice(Plan* p);
 int lpt_forward(Plan* p, const void* omega, const pm_cosmo* c, const pm_ic_coef* ic, pm_state* st,
                 hipStream_t s);
 int lpt_backward(Plan* p, const void* omega, const pm_cosmo* c, const pm_ic_coef* ic,

@@ -112,6 +112,38 @@ def test_lpt_vs_oracle(n, nm, mdt, sdt, tol):
     assert rel_l2(aos(host(st["p"])), p_ref) < tol
 
 
+def test_lpt_scratch_comes_with_the_plan():
+    # pm_config.lpt_scratch = 1 (the binding's default for a 2LPT lattice):
+    # the plan holds the 2LPT lattice scratch from its creation, so pm_lpt
+    # allocates no device memory; with 0 the first pm_lpt call allocates it
+    announce("lpt scratch from the plan")
+    api = _api()
+    n, box = 64, 256.0
+    cfg = osim.SimConfig(n, n, box, 1 / 16, 1.0, 1)
+    cos = api.Cosmology()
+    _, ic = api.tables(cos, cfg.a_grid())
+    om = dev(inputs.white_noise(n, 0), torch.float32)
+
+    def run(plan):
+        st = plan.new_state(torch.zeros((3, n ** 3), dtype=torch.float64, device="cuda"),
+                            torch.zeros((3, n ** 3), dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        plan.lpt(om, cos, ic, st)
+        torch.cuda.synchronize()
+        return free0 - torch.cuda.mem_get_info()[0], host(st["s"])
+
+    lazy = api.Plan(n, n, box=box, mesh_dtype=torch.float32, state_dtype=torch.float64, lpt_scratch=False)
+    assert lazy.cfg.lpt_scratch == 0
+    took_lazy, s_lazy = run(lazy)
+    assert took_lazy >= 12 * n ** 3 * 4          # 12 FP32 lattice fields, allocated by the call
+    plan = api.Plan(n, n, box=box, mesh_dtype=torch.float32, state_dtype=torch.float64)
+    assert plan.cfg.lpt_scratch == 1
+    took, s = run(plan)
+    assert took == 0
+    assert np.array_equal(s, s_lazy)
+
+
 @pytest.mark.parametrize("n,nm", [(16, 32), (16, 16)])   # the second shares the plan's meshes as scratch
 @pytest.mark.parametrize("mdt,tol", [(torch.float64, 1e-10), (torch.float32, 2e-5)])
 def test_lpt_vjp_vs_oracle(n, nm, mdt, tol):
