@@ -65,19 +65,19 @@ __device__ void amp_at(const AmpP& ap, int x, int y, int z, double& A, double& d
   dA = A * (0.5 * ap.dA / ap.A + T.d / T.v);
 }
 
-// out = [out +] M(k) [A(k)] in, M conj'ed if CONJ; each workgroup takes
-// kMulRows consecutive (x, y) rows of the half spectrum
-constexpr int kMulRows = 8;
+// out = [out +] M(k) [A(k)] in, M conj'ed if CONJ; one thread per mode of
+// the half spectrum, in index order
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_mul(const Cx<T>* __restrict__ in, Cx<T>* __restrict__ out, int n,
                                                   int logn, int kind, int use_amp, int conj, int accumulate, AmpP ap) {
   const int nh = n / 2 + 1;
   const double dk = 6.283185307179586476925286766559 / n;
-  const int rows = n * n;
-  for (int row = blockIdx.x * kMulRows; row < (blockIdx.x + 1) * kMulRows && row < rows; ++row)
-  for (int z = threadIdx.x; z < nh; z += kThreads) {
-    const int y = row & (n - 1), x = row >> logn;
-    const int64_t idx = int64_t(row) * nh + z;
+  const int64_t nmodes = int64_t(n) * n * nh;   // < 2^31 for n <= 1024
+  const int64_t idx = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx < nmodes) {
+    const unsigned ui = unsigned(idx), row = ui / unsigned(nh);
+    const int z = int(ui - row * unsigned(nh));
+    const int y = int(row) & (n - 1), x = int(row) >> logn;
     const int f[3] = {x < n / 2 ? x : x - n, y < n / 2 ? y : y - n, z};
     const bool nyq[3] = {2 * x == n, 2 * y == n, 2 * z == n};
     double k[3];
@@ -295,8 +295,8 @@ AmpP amp_params(const Plan* p, const pm_cosmo* c, const pm_ic_coef* ic) {
 template <typename T>
 int mul(Plan* p, const Lat<T>& L, const Cx<T>* in, Cx<T>* out, int kind, bool amp, bool conj, bool acc,
         const AmpP& ap, hipStream_t st) {
-  const unsigned rows = unsigned(L.n) * unsigned(L.n);
-  hipLaunchKernelGGL((k_mul<T>), dim3((rows + kMulRows - 1) / kMulRows), dim3(kThreads), 0, st, in, out, L.n,
+  const int64_t nmodes = int64_t(L.n) * L.n * (L.n / 2 + 1);
+  hipLaunchKernelGGL((k_mul<T>), dim3(unsigned((nmodes + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, in, out, L.n,
                      ilog2(L.n), kind, amp ? 1 : 0, conj ? 1 : 0, acc ? 1 : 0, ap);
   PM_HIP_CHECK(p, hipGetLastError());
   return PM_OK;
