@@ -107,7 +107,8 @@ Sizes sizes_of(const pm_config* c) {
   s.tw_bytes = size_t(kTwiddleSize) * 2 * s.rb;
   s.part_bytes = size_t(kMaxPartials) * 4 * sizeof(double);
   s.scal_bytes = size_t(kScalars) * sizeof(double);
-  // alpha of the adjoint kick a native loop leaves pending: [3][N] mesh dtype
+  // a or alpha of the kick a native loop leaves pending: 3 N mesh-dtype values
+  // (particle-major in tile order)
   s.kick_bytes = size_t(3) * size_t(int64_t(c->ptcl[0]) * c->ptcl[1] * c->ptcl[2]) * s.rb;
   int tile[3];
   tile_dims(c->mesh, tile, s.ntiles, s.halo_cells);
@@ -729,7 +730,7 @@ int pm_run_fwd_ckpt(pm_plan h, pm_state* stt, const pm_step_coef* coefs, int n, 
   if (int rc = set_device(p)) return rc;
   // a_0 = F(x_0); the kick p_0 + a_0 Ka_1 is left pending.  Each gather
   // writes a in the tile order of its bins (contiguous per tile) into the
-  // plan's spare [3][N] buffer, and the next drift reads it back through the
+  // plan's spare 3 N buffer (particle-major), and the next drift reads it back through the
   // bins; the last kick writes a_n to st->acc in lattice order.
   PaintArgs pa{};
   pa.s = stt->s;

@@ -81,7 +81,7 @@ struct Plan {
   void* tw = nullptr;                                      // twiddles (mesh dtype complex)
   double* partials = nullptr;                              // [kMaxPartials * 4]
   double* scalars = nullptr;                               // [kScalars] device scalars
-  void* kick_al = nullptr;                                 // [3][N] mesh dtype, pending alpha
+  void* kick_al = nullptr;                                 // 3 N mesh dtype: the pending a or alpha of a native loop
   // paint binning (paint.hip): tiles of tile[0] x tile[1] x tile[2] cells
   int tile[3] = {8, 8, 32};
   int64_t ntiles = 0;
@@ -213,8 +213,8 @@ struct PaintArgs {
   // kick left pending by the previous gather, applied by the drift before it
   // moves the particles: p += a Kp (forward), p -= a Kp and xi += alpha Kx
   // (adjoint); kick_a null: none
-  const void* kick_a;   // [3][N] mesh dtype a
-  const void* kick_al;  // [3][N] mesh dtype alpha (adjoint)
+  const void* kick_a;   // 3 N mesh dtype a ([3][N], or [pos][3] with kick_sorted)
+  const void* kick_al;  // 3 N mesh dtype alpha (adjoint), same layout
   double Kp, Kx;
   // the pending a (and alpha) are in the tile order of the previous binning
   // (the gather wrote them at each particle's list position), particle-major:
@@ -247,7 +247,7 @@ struct GatherArgs {
   const void* s;        // [3][N] state
   const void* mesh;     // [nf][ncell]
   int nf;
-  void* out;            // plain: [nf][N]; VJP/MSE: xbar [3][N]
+  void* out;            // plain: [nf][N]; VJP/MSE: xbar [3][N]; sorted_out: [pos][3]
   void* acc;            // acceleration out (optional)
   void* p;              // kick target
   void* xi;             // adjoint kick target
