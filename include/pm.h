@@ -237,6 +237,16 @@ int pm_run_fwd(pm_plan plan, pm_state* st, const pm_step_coef* coefs, int n, dou
 int pm_run_adj(pm_plan plan, pm_state* st, pm_adj* adj, const pm_step_coef* coefs, int n,
                double omega_m, double* theta_bar, hipStream_t stream);
 
+/* The reverse loop resumed from the point where pm_step_adj(n) would
+ * continue, (s_n, p_{n-1/2}), (xi_{n-1/2}, pi_n), after pm_adj_init or any
+ * pm_step_adj call: n reverse steps n..1 (coefs[0..n-1]), bitwise the same
+ * as those n pm_step_adj calls.  For drivers that interleave their own work
+ * with the last reverse steps (the light-cone gradient adds its bumps there)
+ * and run the rest natively.  st->acc, if given, is scratch as in pm_run_adj.
+ * Errors as pm_step_adj. */
+int pm_run_adj_from(pm_plan plan, pm_state* st, pm_adj* adj, const pm_step_coef* coefs, int n,
+                    double omega_m, double* theta_bar, hipStream_t stream);
+
 /* ---- piecewise reverse from forward checkpoints (Sec. 3.5) ---------------- */
 /* Where the reverse-time integration drifts too far from the forward
  * trajectory (long or strongly nonlinear runs, FP32 state), the backward
@@ -395,6 +405,17 @@ int pm_lightcone_tables(const pm_cosmo* cosmo, const double* a_grid, int n, doub
 int pm_lightcone(pm_plan plan, const pm_lc_step* st, const void* s0, const void* p0,
                  const void* s1, const void* p1, void* obs, int32_t* obs_step,
                  double* count, hipStream_t stream);
+
+/* *r_max (device double) = the largest comoving distance |q + disp -
+ * observer| over the particles, in mesh cells, with the unwrapped positions
+ * of the observation (disp: [3][N_p] state dtype; observer: host double[3]).
+ * The light front only moves inward, at the speed of light, so a particle
+ * outside it stays outside: once every particle is inside the front of
+ * a_m (r_max < chi(a_m)), none has crossed in steps 1..m, and a driver may
+ * run those steps without observing them.  NaN if a distance is.  Errors:
+ * PM_EINVAL for NULL or non-finite arguments. */
+int pm_lightcone_reach(pm_plan plan, const void* disp, const double* observer, double* r_max,
+                       hipStream_t stream);
 
 /* Transpose of pm_lightcone for the particles with obs_step[n] == st->step,
  * given the cotangent obs_bar ([7][N_p] mesh dtype) of (x^, p^, a^): adds

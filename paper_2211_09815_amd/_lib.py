@@ -116,6 +116,7 @@ _PROTOS = {
     "pm_step_adj": (c_int, [c_vp, P(PmState), P(PmAdj), P(PmStepCoef), P(PmStepCoef), c_dbl, c_vp, c_vp]),
     "pm_run_fwd": (c_int, [c_vp, P(PmState), P(PmStepCoef), c_int, c_dbl, c_vp]),
     "pm_run_adj": (c_int, [c_vp, P(PmState), P(PmAdj), P(PmStepCoef), c_int, c_dbl, c_vp, c_vp]),
+    "pm_run_adj_from": (c_int, [c_vp, P(PmState), P(PmAdj), P(PmStepCoef), c_int, c_dbl, c_vp, c_vp]),
     "pm_run_fwd_ckpt": (c_int, [c_vp, P(PmState), P(PmStepCoef), c_int, c_dbl, P(PmCheckpoints), c_vp]),
     "pm_run_adj_ckpt": (c_int, [c_vp, P(PmState), P(PmAdj), P(PmStepCoef), c_int, c_dbl, P(PmCheckpoints), c_vp,
                                 c_vp]),
@@ -125,6 +126,7 @@ _PROTOS = {
     "pm_lpt": (c_int, [c_vp, c_vp, P(PmCosmo), P(PmIcCoef), P(PmState), c_vp]),
     "pm_lpt_vjp": (c_int, [c_vp, c_vp, P(PmCosmo), P(PmIcCoef), P(PmAdj), c_vp, c_vp, c_vp]),
     "pm_lightcone_tables": (c_int, [P(PmCosmo), P(c_dbl), c_int, c_dbl, P(PmLcCoef)]),
+    "pm_lightcone_reach": (c_int, [c_vp, c_vp, P(c_dbl), c_vp, c_vp]),
     "pm_lightcone": (c_int, [c_vp, P(PmLcStep), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "pm_lightcone_vjp": (c_int, [c_vp, P(PmLcStep), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                                  c_vp, c_vp]),

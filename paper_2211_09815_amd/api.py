@@ -290,6 +290,14 @@ class Plan:
         self._c(lib().pm_run_adj(self._h, ctypes.byref(self._st(state)), ctypes.byref(self._adj(adj)), arr, n,
                                  float(omega_m), _ptr(theta_bar), _stream()))
 
+    def run_adj_from(self, state, adj, coefs, omega_m, theta_bar):
+        """pm_run_adj_from: the reverse steps len(coefs)..1 from where the
+        step calls left off (no pm_adj_init)."""
+        self._t(theta_bar, torch.float64, 2, "theta_bar")
+        arr, n = self._coef_array(coefs)
+        self._c(lib().pm_run_adj_from(self._h, ctypes.byref(self._st(state)), ctypes.byref(self._adj(adj)), arr,
+                                      n, float(omega_m), _ptr(theta_bar), _stream()))
+
     def new_checkpoints(self, steps):
         """Buffers for forward checkpoints at the given steps (1..n): a dict
         with "step" (sorted list), "s" and "p" (lists of [3, N_p] tensors)."""
@@ -352,6 +360,17 @@ class Plan:
 
     def _mesh3(self, t, name):
         return self._t(t, self.mdt, 3 * self.n_particles, name) if t is not None else None
+
+    def lightcone_reach(self, disp, observer, out=None):
+        """pm_lightcone_reach: the largest |q + disp - observer| over the
+        particles (mesh cells), a device FP64 scalar."""
+        self._state3(disp, "disp")
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=self.device)
+        self._t(out, torch.float64, 1, "r_max")
+        obs = (ctypes.c_double * 3)(*[float(v) for v in observer])
+        self._c(lib().pm_lightcone_reach(self._h, _ptr(disp), obs, _ptr(out), _stream()))
+        return out
 
     def lightcone(self, step, s0, p0, s1, p1, obs, obs_step, count):
         """pm_lightcone: record the particles that cross the light front in

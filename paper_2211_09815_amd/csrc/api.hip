@@ -769,16 +769,13 @@ int pm_run_fwd_ckpt(pm_plan h, pm_state* stt, const pm_step_coef* coefs, int n, 
   return kick_flush(p, stt->p, p->kick_al, Kp, false, nullptr, nullptr, 0.0, stt->acc, st);
 }
 
-int pm_run_adj_ckpt(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* coefs, int n, double omega_m,
-                    const pm_checkpoints* ck, double* theta_bar, hipStream_t st) {
-  CHECK_PLAN(h);
-  if (!coefs || n < 1) return set_error(p, PM_EINVAL, "need n >= 1 step coefficients");
-  if (int rc = check_checkpoints(p, ck, n)) return rc;
-  for (int i = 0; i < n; ++i)
-    if (int rc = check_step(p, &coefs[i], "coefs[i]")) return rc;
-  if (int rc = pm_adj_init(h, stt, adj, &coefs[n - 1], omega_m, theta_bar, st)) return rc;
-  const int kn = checkpoint_index(ck, n);
-  if (kn >= 0) PM_HIP_CHECK(p, hipMemcpyAsync(stt->p, ck->p[kn], state_bytes(p), hipMemcpyDeviceToDevice, st));
+namespace {
+
+// reverse steps n..1 of the native loop from (s_n, p_{n-1/2}), (xi_{n-1/2},
+// pi_n): what pm_run_adj_ckpt runs after pm_adj_init, and pm_run_adj_from
+// from wherever the step calls left off
+int run_adj_steps(Plan* p, pm_state* stt, pm_adj* adj, const pm_step_coef* coefs, int n, double omega_m,
+                  const pm_checkpoints* ck, double* theta_bar, hipStream_t st) {
   const bool defer = stt->acc != nullptr;
   bool pending = false;
   double Kp = 0.0, Kx = 0.0;
@@ -841,6 +838,32 @@ int pm_run_adj_ckpt(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* c
   }
   if (defer && pending) return kick_flush(p, stt->p, stt->acc, Kp, true, adj->xi, p->kick_al, Kx, nullptr, st);
   return PM_OK;
+}
+
+}  // namespace
+
+int pm_run_adj_ckpt(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* coefs, int n, double omega_m,
+                    const pm_checkpoints* ck, double* theta_bar, hipStream_t st) {
+  CHECK_PLAN(h);
+  if (!coefs || n < 1) return set_error(p, PM_EINVAL, "need n >= 1 step coefficients");
+  if (int rc = check_checkpoints(p, ck, n)) return rc;
+  for (int i = 0; i < n; ++i)
+    if (int rc = check_step(p, &coefs[i], "coefs[i]")) return rc;
+  if (int rc = pm_adj_init(h, stt, adj, &coefs[n - 1], omega_m, theta_bar, st)) return rc;
+  const int kn = checkpoint_index(ck, n);
+  if (kn >= 0) PM_HIP_CHECK(p, hipMemcpyAsync(stt->p, ck->p[kn], state_bytes(p), hipMemcpyDeviceToDevice, st));
+  return run_adj_steps(p, stt, adj, coefs, n, omega_m, ck, theta_bar, st);
+}
+
+int pm_run_adj_from(pm_plan h, pm_state* stt, pm_adj* adj, const pm_step_coef* coefs, int n, double omega_m,
+                    double* theta_bar, hipStream_t st) {
+  CHECK_PLAN(h);
+  if (!coefs || n < 1) return set_error(p, PM_EINVAL, "need n >= 1 step coefficients");
+  for (int i = 0; i < n; ++i)
+    if (int rc = check_step(p, &coefs[i], "coefs[i]")) return rc;
+  if (int rc = check_adj_args(p, stt, adj, &coefs[n - 1], nullptr, omega_m, theta_bar)) return rc;
+  if (int rc = set_device(p)) return rc;
+  return run_adj_steps(p, stt, adj, coefs, n, omega_m, nullptr, theta_bar, st);
 }
 
 int pm_density_mse(pm_plan h, const void* disp, const void* target, double* J, void* disp_bar, hipStream_t st) {

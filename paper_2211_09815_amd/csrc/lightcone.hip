@@ -303,6 +303,33 @@ int check_lc_step(Plan* p, const pm_lc_step* st) {
   return PM_OK;
 }
 
+// largest |q + s - X| over the particles: per-block maxima in part[b * 4],
+// then one workgroup folds them (NaN if any distance is NaN)
+template <typename S>
+__global__ __launch_bounds__(kThreads) void k_reach(TileGeo g, const S* __restrict__ s, double X0, double X1,
+                                                    double X2, double* part) {
+  auto fold = [](double m, double a) { return (a > m || a != a) ? a : m; };
+  double m = 0.0;
+  const int64_t stride = int64_t(gridDim.x) * kThreads;
+  for (int64_t n = int64_t(blockIdx.x) * kThreads + threadIdx.x; n < g.N; n += stride) {
+    double q[3];
+    lattice_pos(g, n, q);
+    const double d0 = q[0] + double(s[n]) - X0, d1 = q[1] + double(s[g.N + n]) - X1,
+                 d2 = q[2] + double(s[2 * g.N + n]) - X2;
+    m = fold(m, sqrt(fma(d0, d0, fma(d1, d1, d2 * d2))));
+  }
+  const double t = block_max_d(m);
+  if (threadIdx.x == 0) part[blockIdx.x * 4] = t;
+}
+
+__global__ __launch_bounds__(kThreads) void k_reach_fold(const double* part, int nblocks, double* out) {
+  auto fold = [](double m, double a) { return (a > m || a != a) ? a : m; };
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += kThreads) m = fold(m, part[b * 4]);
+  const double t = block_max_d(m);
+  if (threadIdx.x == 0) out[0] = t;
+}
+
 LcGeo lc_geo(const Plan* p, const pm_lc_step* st) {
   LcGeo L;
   L.g = tile_geo(p);
@@ -356,6 +383,28 @@ extern "C" int pm_lightcone(pm_plan h, const pm_lc_step* st, const void* s0, con
   timing_end(p, PM_K_LIGHTCONE, stream, 6.0 * double(p->nptcl) * sb, 6.0 * double(p->nptcl) * sb);
   const double f[4] = {1.0, 0.0, 0.0, 0.0};
   return reduce_partials(p, blocks, f, count, true, stream);
+}
+
+extern "C" int pm_lightcone_reach(pm_plan h, const void* disp, const double* observer, double* r_max,
+                                  hipStream_t stream) {
+  LC_PLAN(h);
+  if (int rc = lc_ptr(p, disp, "disp")) return rc;
+  if (int rc = lc_ptr(p, r_max, "r_max")) return rc;
+  if (!observer) return set_error(p, PM_EINVAL, "observer is NULL");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(observer[k])) return set_error(p, PM_EINVAL, "observer position is not finite");
+  if (int rc = lc_device(p)) return rc;
+  const TileGeo g = tile_geo(p);
+  const int blocks = elementwise_blocks(p->nptcl);
+  if (p->cfg.state_dtype == PM_F64)
+    hipLaunchKernelGGL(k_reach<double>, dim3(blocks), dim3(kThreads), 0, stream, g, static_cast<const double*>(disp),
+                       observer[0], observer[1], observer[2], p->partials);
+  else
+    hipLaunchKernelGGL(k_reach<float>, dim3(blocks), dim3(kThreads), 0, stream, g, static_cast<const float*>(disp),
+                       observer[0], observer[1], observer[2], p->partials);
+  hipLaunchKernelGGL(k_reach_fold, dim3(1), dim3(kThreads), 0, stream, p->partials, blocks, r_max);
+  PM_HIP_CHECK(p, hipGetLastError());
+  return PM_OK;
 }
 
 extern "C" int pm_lightcone_vjp(pm_plan h, const pm_lc_step* st, const void* s0, const void* p0, const void* s1,

@@ -5,7 +5,14 @@ objective on the observables by the adjoint with reverse-time integration
 Every numeric step runs in libpm (api.py); this module only sequences the
 calls and owns the buffers.
 
-Forward: the kicks are not merged, so that the state holds the integer-time
+Forward: the light front moves inward at the speed of light, so a particle
+outside it stays outside, and no particle crosses before the front has come
+within reach of one.  The steps before that run as the native loop
+(pm_run_fwd, merged kicks), up to the last step m whose front lies further
+from the observer than any lattice site plus a displacement margin; then
+pm_lightcone_reach checks that every particle is inside the front of a_m (if
+one is not, the forward pass starts again and observes every step).  From
+there the kicks are not merged, so that the state holds the integer-time
 momenta p_i that the Hermite splines need: pm_step_fwd(i) without a next step
 leaves (s_i, p_i, a_i), pm_lightcone observes step i from the saved (s_{i-1},
 p_{i-1}), and pm_kick applies the first half kick of step i + 1.
@@ -17,9 +24,10 @@ adjoint; pm_adj_bump adds both at t_k, right after pm_step_adj(k + 1) has
 brought the reverse integration to t_k.  The observation of step k needs the
 state at t_{k-1} before the reverse integration gets there, so one step ahead
 the driver reconstructs x_{k-1} (pm_drift) and a_{k-1} (pm_force).  Steps in
-which no particle crosses, and the steps next to them, skip all of this.  The
-gradient is the exact gradient of the discrete forward map, up to the
-reversibility of the reconstruction.
+which no particle crosses, and the steps next to them, skip all of this;
+below the first observed step the rest of the reverse pass is the native loop
+(pm_run_adj_from).  The gradient is the exact gradient of the discrete
+forward map, up to the reversibility of the reconstruction.
 """
 import numpy as np
 import torch
@@ -57,24 +65,51 @@ class LightCone:
     def _step(self, lc, cosmo, i):
         return api.lc_step(lc[i - 1], lc[i], cosmo.omega_m, self.observer, i)
 
-    def forward(self, omega, cosmo, tables=None):
+    def quiet_steps(self, lc, margin):
+        """The last step m < n whose light front (lc[m].chi, mesh cells) lies
+        further from the observer than every lattice site by more than
+        `margin` cells, or 0.  Host arithmetic on the lattice's extent."""
+        cfg = self.sim.cfg
+        r = cfg.n_mesh / cfg.n_ptcl
+        ends = np.array([cfg.lattice_offset, (cfg.n_ptcl - 1) * r + cfg.lattice_offset])
+        reach = np.sqrt(sum(np.max(np.abs(ends - x)) ** 2 for x in self.observer)) + margin
+        m = 0
+        for i in range(1, len(lc) - 1):
+            if lc[i].chi > reach:
+                m = i
+        return m
+
+    def forward(self, omega, cosmo, tables=None, margin=None):
         """2LPT, n KDK steps and the observation of every step.  Leaves
         (s_n, p_n, a_n) in the simulation and (x^, p^, a^) in self.obs;
-        returns the host array of particles observed per step (index 1..n)."""
+        returns the host array of particles observed per step (index 1..n).
+        The steps before the front can reach a particle (quiet_steps with a
+        displacement margin, default a quarter of the mesh side; checked)
+        run as the native loop without observation."""
         sim, plan = self.sim, self.sim.plan
         coefs, ic, lc = tables if tables is not None else self.tables(cosmo)
         n = len(coefs)
         om = cosmo.omega_m
         st = sim.state()
-        plan.lpt(omega, cosmo, ic, st)
         self.obs.zero_()
         self.obs_step.zero_()
         self.counts.zero_()
         s_prev, p_prev = self.x_tmp, self.p_tmp
+        m = self.quiet_steps(lc, sim.cfg.n_mesh / 4 if margin is None else margin)
+        plan.lpt(omega, cosmo, ic, st)
+        if m > 0:
+            plan.run_fwd(st, coefs[:m], om)                  # (s_m, p_m, a_m)
+            if not float(plan.lightcone_reach(sim.s, self.observer).item()) < lc[m].chi:
+                m = 0                                        # a particle is out already: observe every step
+                plan.lpt(omega, cosmo, ic, st)
+        self.native_steps = m
         s_prev.copy_(sim.s)
         p_prev.copy_(sim.p)
-        plan.fwd_init(st, coefs[0], om)
-        for i in range(1, n + 1):
+        if m > 0:
+            plan.kick(sim.p, sim.acc, coefs[m][0], out=sim.p)   # first half kick of step m + 1
+        else:
+            plan.fwd_init(st, coefs[0], om)
+        for i in range(m + 1, n + 1):
             plan.step_fwd(st, coefs[i - 1], None, om)
             plan.lightcone(self._step(lc, cosmo, i), s_prev, p_prev, sim.s, sim.p, self.obs, self.obs_step,
                            self.counts[i:i + 1])
@@ -107,6 +142,8 @@ class LightCone:
         for t in self.xb + self.pb:
             t.zero_()
         need = lambda k: cnt[k] > 0 or cnt[k + 1] > 0   # noqa: E731  cotangents on z_k
+        observed = [j for j in range(1, n + 1) if cnt[j] > 0]
+        first = observed[0] if observed else n + 1       # reverse steps below it are plain
         self.a[0].copy_(sim.acc)                         # a_n
         s, p = sim.s, sim.p
 
@@ -130,6 +167,10 @@ class LightCone:
         if init_ahead:
             self.a.reverse()
         for i in range(n, 0, -1):
+            if i < first:
+                # nothing observed in steps 1..i+1: the native reverse loop
+                plan.run_adj_from(st, adj, coefs[:i], om, thb)
+                break
             plan.step_adj(st, adj, coefs[i - 1], coefs[i - 2] if i > 1 else None, om, thb)
             k = i - 1
             if k == 0:

@@ -261,7 +261,8 @@ def test_adjoint_memory_is_flat_in_step_count():
 def test_native_loops_match_step_calls(mdt, sdt):
     # the native loops pm_run_fwd / pm_run_adj must leave exactly the state
     # that the sequence of step calls leaves (theta_bar up to the order of
-    # its FP64 partial sums)
+    # its FP64 partial sums); so must two step calls followed by
+    # pm_run_adj_from for the rest of the reverse pass
     api = _api()
     announce("native loops vs step calls %s/%s" % (mdt, sdt))
     n, nm, box, steps = 16, 32, 64.0, 6
@@ -272,9 +273,10 @@ def test_native_loops_match_step_calls(mdt, sdt):
     rows = np.concatenate([coefs, dcoefs], axis=1)
     plan = api.Plan(nm, n, box=box, mesh_dtype=mdt, state_dtype=sdt)
     res = []
-    for native in (True, False):
+    for mode in ("native", "steps", "resume"):
+        native = mode == "native"
         st = plan.new_state(dev(soa(s0), sdt), dev(soa(p0), sdt))
-        if native:
+        if mode != "steps":
             plan.run_fwd(st, rows, 0.3)
         else:
             plan.fwd_init(st, rows[0], 0.3)
@@ -287,12 +289,16 @@ def test_native_loops_match_step_calls(mdt, sdt):
             plan.run_adj(st, adj, rows, 0.3, tb)
         else:
             plan.adj_init(st, adj, rows[-1], 0.3, tb)
-            for i in range(steps - 1, -1, -1):
+            last = -1 if mode == "steps" else steps - 3
+            for i in range(steps - 1, last, -1):
                 plan.step_adj(st, adj, rows[i], rows[i - 1] if i > 0 else None, 0.3, tb)
+            if mode == "resume":
+                plan.run_adj_from(st, adj, rows[:steps - 2], 0.3, tb)
         res.append(fwd + (host(st["s"]), host(st["p"]), host(adj["xi"]), host(adj["pi"]), host(tb)))
-    for a, b in zip(res[0][:-1], res[1][:-1]):
-        np.testing.assert_array_equal(a, b)
-    np.testing.assert_allclose(res[0][-1], res[1][-1], rtol=1e-12)
+    for other in res[1:]:
+        for a, b in zip(res[0][:-1], other[:-1]):
+            np.testing.assert_array_equal(a, b)
+        np.testing.assert_allclose(res[0][-1], other[-1], rtol=1e-12)
 
 
 # ---- piecewise reverse from forward checkpoints (Sec. 3.5) --------------------

@@ -14,9 +14,10 @@ import torch
 
 from oracle import cosmology as ocos
 from oracle import lightcone as olc
+from oracle import pm as opm
 from oracle import simulate as osim
 from paper_2211_09815_amd import inputs
-from gpu_util import announce, dev, host, rel_l2
+from gpu_util import announce, dev, host, rel_l2, soa
 
 pytestmark = pytest.mark.gpu
 
@@ -276,6 +277,67 @@ def test_end_to_end_fp32_mesh_vs_oracle(sdt):
         assert abs(obs_ref[i, 6] - a_b) < 1e-3 * da, (i, obs_ref[i, 6], a_b)
     assert rel_l2(g, g_ref) < 1e-3
     np.testing.assert_allclose(th, th_ref, rtol=1e-3)
+
+
+def test_lightcone_reach_vs_numpy():
+    # pm_lightcone_reach: the largest |q + s - X| over the particles
+    api = _api()
+    announce("light-cone reach")
+    plan = api.Plan(16, 8, box=32.0, lattice_offset=0.25, mesh_dtype=torch.float32, state_dtype=torch.float64)
+    q = opm.lattice_positions((8, 8, 8), 2.0, 0.25)
+    s = inputs.normal(q.shape, 81, 3.0)
+    X = (-5.5, 7.25, 40.0)
+    got = float(plan.lightcone_reach(dev(soa(s), torch.float64), X).item())
+    assert got == pytest.approx(float(np.max(np.linalg.norm(q + s - np.array(X), axis=1))), rel=1e-15)
+
+
+@pytest.mark.parametrize("mdt", [torch.float64, torch.float32])
+def test_native_quiet_steps_match_observing_every_step(mdt):
+    # the steps before the front can reach a particle run as the native loop
+    # (merged kicks, no observation) and the reverse pass below the first
+    # observed step as pm_run_adj_from; against observing every step (margin
+    # so large that no step is quiet): the same crossing steps and, to the
+    # rounding of the merged kicks, the same observations and gradients.  A
+    # negative margin declares every step quiet, the reach check fails, and
+    # the pass starts again observing every step: bitwise the same as that
+    # (dJ/dtheta to the 1e-13 of its FP64 partial sums, whose order follows
+    # the tile lists)
+    api = _api()
+    from paper_2211_09815_amd.lightcone import LightCone
+    from paper_2211_09815_amd.simulate import SimConfig, Simulation
+    announce("light cone native quiet steps %s" % mdt)
+    cfg, X = _lightcone_setup(16, 16, 64.0, 12, 9)
+    sim = Simulation(SimConfig(16, 16, 64.0, cfg.a_start, cfg.a_end, 12, mdt, torch.float64))
+    lc = LightCone(sim, X)
+    cosmo = api.Cosmology()
+    tabs = lc.tables(cosmo)
+    om = dev(inputs.white_noise(16, 0), mdt)
+    w = dev(inputs.normal((7, 16 ** 3), inputs.SEED_COTANGENT), mdt)
+    runs = {}
+    for name, margin in (("quiet", None), ("all", 1.0e9), ("fallback", -1.0e9)):
+        counts = lc.forward(om, cosmo, tabs, margin=margin)
+        obs, ostep, native = host(lc.obs), lc.obs_step.cpu().numpy(), lc.native_steps
+        g, th = lc.gradient(om, cosmo, w, tabs)
+        runs[name] = (counts, obs, ostep, host(g), host(th), native)
+    assert runs["quiet"][5] > 0 and runs["all"][5] == 0 and runs["fallback"][5] == 0
+    q, a = runs["quiet"], runs["all"]
+    if mdt == torch.float64:
+        np.testing.assert_array_equal(q[0], a[0])
+        np.testing.assert_array_equal(q[2], a[2])
+        assert rel_l2(q[1], a[1]) < 1e-10
+        assert rel_l2(q[3], a[3]) < 1e-10
+        np.testing.assert_allclose(q[4], a[4], rtol=1e-10)
+    else:
+        # FP32 forces: the merged kicks move positions by an FP64 ulp, which
+        # can flip an FP32 rounding; a crossing at a step boundary may move
+        same = q[2] == a[2]
+        assert same.mean() > 0.999
+        assert rel_l2(q[1][:, same], a[1][:, same]) < 1e-5
+        assert rel_l2(q[3], a[3]) < 1e-3
+        np.testing.assert_allclose(q[4], a[4], rtol=1e-3)
+    for x, y in zip(runs["fallback"][:4], a[:4]):
+        np.testing.assert_array_equal(x, y)
+    np.testing.assert_allclose(runs["fallback"][4], a[4], rtol=1e-13)
 
 
 def test_no_particle_observed_gives_a_zero_gradient():
