@@ -777,6 +777,12 @@ namespace {
 int run_adj_steps(Plan* p, pm_state* stt, pm_adj* adj, const pm_step_coef* coefs, int n, double omega_m,
                   const pm_checkpoints* ck, double* theta_bar, hipStream_t st) {
   const bool defer = stt->acc != nullptr;
+  // the native loop keeps pi particle-major while it runs (the four-channel
+  // paint and the VJP gather read it through the tile lists), and gives it
+  // back as [3][N]
+  const bool pm = defer && pi_layout_fits(p);
+  if (pm)
+    if (int rc = pi_layout(p, adj->pi, true, st)) return rc;
   bool pending = false;
   double Kp = 0.0, Kx = 0.0;
   for (int i = n - 1; i >= 0; --i) {
@@ -801,6 +807,7 @@ int run_adj_steps(Plan* p, pm_state* stt, pm_adj* adj, const pm_step_coef* coefs
     pa.D = cur->D;
     pa.partials = p->partials;
     pa.s_set = s_set;
+    pa.pi_pm = pm;
     if (pending) {
       pa.kick_a = stt->acc;
       pa.kick_al = p->kick_al;
@@ -820,6 +827,7 @@ int run_adj_steps(Plan* p, pm_state* stt, pm_adj* adj, const pm_step_coef* coefs
     ga.out = p->kick_al;
     ga.acc = stt->acc;
     ga.cot = adj->pi;
+    ga.cot_pm = pm;
     ga.sorted_out = true;
     ga.binned = true;
     if (int rc = gather_launch(p, GATHER_VJP, ga, st)) return rc;
@@ -836,8 +844,9 @@ int run_adj_steps(Plan* p, pm_state* stt, pm_adj* adj, const pm_step_coef* coefs
       Kp = 0.0;
     }
   }
-  if (defer && pending) return kick_flush(p, stt->p, stt->acc, Kp, true, adj->xi, p->kick_al, Kx, nullptr, st);
-  return PM_OK;
+  if (defer && pending)
+    if (int rc = kick_flush(p, stt->p, stt->acc, Kp, true, adj->xi, p->kick_al, Kx, nullptr, st)) return rc;
+  return pm ? pi_layout(p, adj->pi, false, st) : PM_OK;
 }
 
 }  // namespace

@@ -67,10 +67,12 @@ struct BinP {
 // order of the previous binning (BinP::kick_sorted), looked up through the
 // previous keys: those loads go first, then the state's, and the dependent
 // ones last, so that their round trips overlap the state's.
-template <typename S, typename T, int MODE, int KICK>
+// PIPM: pi is particle-major, [N][3] (PaintArgs::pi_pm).
+template <typename S, typename T, int MODE, int KICK, bool PIPM = false>
 __global__ __launch_bounds__(kThreads) void k_bin(BinP<S, T> a) {
   static_assert(!KICK || MODE != DRIFT_NONE, "a pending kick comes with a drift");
   constexpr bool ADJ = MODE == DRIFT_ADJ || MODE == DRIFT_SET;
+  static_assert(!PIPM || ADJ, "a particle-major pi comes with the adjoint drift");
   constexpr int U = 4;
   const TileGeo& g = a.g;
   int64_t start, end;
@@ -111,7 +113,7 @@ __global__ __launch_bounds__(kThreads) void k_bin(BinP<S, T> a) {
         if (MODE != DRIFT_NONE) pv[u][ax] = a.p[ax * g.N + n];
         if (ADJ) {
           xv[u][ax] = a.xi[ax * g.N + n];
-          piv[u][ax] = a.pi[ax * g.N + n];
+          piv[u][ax] = a.pi[PIPM ? 3 * n + ax : ax * g.N + n];
         }
       }
     }
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(kThreads) void k_bin(BinP<S, T> a) {
           if (MODE == DRIFT_ADJ) sv[u][ax] = fma(-pv[u][ax], a.D, sv[u][ax]);
           a.s[ax * g.N + n] = sv[u][ax];
           const T pn = fma(xv[u][ax], T(a.D), piv[u][ax]);
-          a.pi[ax * g.N + n] = pn;
+          a.pi[PIPM ? 3 * n + ax : ax * g.N + n] = pn;
           pm[ax] = fold(pm[ax], fabs(double(pn)));
         }
       }
@@ -338,7 +340,8 @@ constexpr int kPaintThreads = 512;  // threads per tile workgroup of the paint
 // atomics (ds_add_f32 / ds_add_f64), whose order, and so whose rounding,
 // changes from run to run: the non-deterministic paint that plain GPU codes
 // use, kept for comparison.
-template <typename S, typename T, int NCH, bool UNIT, bool FIXED>
+// WPM: the weights are particle-major, [N][NW] (PaintArgs::pi_pm).
+template <typename S, typename T, int NCH, bool UNIT, bool FIXED, bool WPM = false>
 __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const S* __restrict__ s,
                                                           const T* __restrict__ w, const unsigned* __restrict__ offs,
                                                           const unsigned* __restrict__ list, T* __restrict__ mesh,
@@ -385,7 +388,7 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
         for (int ax = 0; ax < 3; ++ax) xs[k][ax] = s[ax * g.N + nn[k]];
       }
 #pragma unroll
-      for (int c = 0; c < NW; ++c) ws[k][c] = w[c * g.N + nn[k]];
+      for (int c = 0; c < NW; ++c) ws[k][c] = w[WPM ? int64_t(nn[k]) * NW + c : c * g.N + nn[k]];
     }
   };
   // Each lane visits the 8 CIC corners of its particles in the order
@@ -507,7 +510,7 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
       for (unsigned i = beg + tid; i < fin; i += kPaintThreads) {
         const unsigned n = list[i];
 #pragma unroll
-        for (int c = 0; c < NW; ++c) fold(c + (UNIT ? 1 : 0), fabs(double(w[c * g.N + n])));
+        for (int c = 0; c < NW; ++c) fold(c + (UNIT ? 1 : 0), fabs(double(w[WPM ? int64_t(n) * NW + c : c * g.N + n])));
       }
     }
 #pragma unroll
@@ -657,18 +660,29 @@ int bin_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
   b.rec = static_cast<float4*>(p->bin_rec);
   const bool kick = in.kick_a != nullptr;
   const bool adj = mode == DRIFT_ADJ || mode == DRIFT_SET;
+  // a particle-major pi is the native adjoint loop's: its kicks are pending
+  // in tile order, or there is none yet
+  if (in.pi_pm && (!adj || (kick && !in.kick_sorted)))
+    return set_error(p, PM_EINVAL, "particle-major pi needs the adjoint drift with tile-order kicks");
   timing_begin(p, PM_K_BIN, st);
-#define PM_BIN(MODE, KICK) hipLaunchKernelGGL((k_bin<S, T, MODE, KICK>), dim3(pblocks), block, 0, st, b)
-#define PM_BIN_K(MODE)                     \
-  do {                                     \
-    if (!kick) PM_BIN(MODE, 0);            \
-    else if (in.kick_sorted) PM_BIN(MODE, 2); \
-    else PM_BIN(MODE, 1);                  \
+#define PM_BIN(MODE, KICK, PM) hipLaunchKernelGGL((k_bin<S, T, MODE, KICK, PM>), dim3(pblocks), block, 0, st, b)
+#define PM_BIN_K(MODE)                      \
+  do {                                      \
+    if (!kick) PM_BIN(MODE, 0, false);      \
+    else if (in.kick_sorted) PM_BIN(MODE, 2, false); \
+    else PM_BIN(MODE, 1, false);            \
+  } while (0)
+#define PM_BIN_ADJ(MODE)                    \
+  do {                                      \
+    if (!in.pi_pm) PM_BIN_K(MODE);          \
+    else if (!kick) PM_BIN(MODE, 0, true);  \
+    else PM_BIN(MODE, 2, true);             \
   } while (0)
   if (mode == DRIFT_FWD) PM_BIN_K(DRIFT_FWD);
-  else if (mode == DRIFT_ADJ) PM_BIN_K(DRIFT_ADJ);
-  else if (mode == DRIFT_SET) PM_BIN_K(DRIFT_SET);
-  else PM_BIN(DRIFT_NONE, 0);
+  else if (mode == DRIFT_ADJ) PM_BIN_ADJ(DRIFT_ADJ);
+  else if (mode == DRIFT_SET) PM_BIN_ADJ(DRIFT_SET);
+  else PM_BIN(DRIFT_NONE, 0, false);
+#undef PM_BIN_ADJ
 #undef PM_BIN_K
 #undef PM_BIN
   {
@@ -704,6 +718,8 @@ int paint_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
   const int nch = in.unit + in.nw;
   const dim3 block(kThreads);
   const int64_t nt = g.ntiles;
+  if (in.pi_pm && !(in.unit && nch == 4 && (mode == DRIFT_ADJ || mode == DRIFT_SET)))
+    return set_error(p, PM_EINVAL, "particle-major weights are the adjoint drift's pi");
   if (int rc = bin_typed<S, T>(p, mode, in, st)) return rc;
   const S* s = static_cast<const S*>(in.s);
   // in the adjoint drift the weighted channels are the updated pi, whose
@@ -737,20 +753,23 @@ int paint_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
   const int nlow = g.ty * g.tz + (g.tx - 1) * g.tz + (in.defer_z ? 0 : (g.tx - 1) * (g.ty - 1));
   const double lower = double(nlow) / (g.tx * g.ty * g.tz);
   const double hadd_bytes = halo_bytes * (in.defer_z ? double(g.hc - zc) / g.hc : 1.0) + 2.0 * lower * core_bytes;
-#define PM_TILES(NCH, UNIT)                                                                                \
+#define PM_TILES_W(NCH, UNIT, WPM)                                                                         \
   timing_begin(p, PM_K_PAINT_TILES, st);                                                                   \
   if (fixed)                                                                                               \
-    hipLaunchKernelGGL((k_paint_tiles<S, T, NCH, UNIT, true>), tg, dim3(kPaintThreads), 0, st, g, s, w,    \
+    hipLaunchKernelGGL((k_paint_tiles<S, T, NCH, UNIT, true, WPM>), tg, dim3(kPaintThreads), 0, st, g, s, w, \
                        p->bin_offs, p->bin_list, mesh, halo, wglob, static_cast<const float4*>(p->bin_rec)); \
   else                                                                                                     \
-    hipLaunchKernelGGL((k_paint_tiles<S, T, NCH, UNIT, false>), tg, dim3(kPaintThreads), 0, st, g, s, w,   \
+    hipLaunchKernelGGL((k_paint_tiles<S, T, NCH, UNIT, false, WPM>), tg, dim3(kPaintThreads), 0, st, g, s, w, \
                        p->bin_offs, p->bin_list, mesh, halo, wglob, static_cast<const float4*>(p->bin_rec)); \
   timing_end(p, PM_K_PAINT_TILES, st, tile_bytes, tile_method);                                            \
   timing_begin(p, PM_K_HALO, st);                                                                          \
   if (in.defer_z) hipLaunchKernelGGL((k_halo_add<T, NCH, true>), tg, block, 0, st, g, mesh, halo);         \
   else hipLaunchKernelGGL((k_halo_add<T, NCH, false>), tg, block, 0, st, g, mesh, halo);                   \
   timing_end(p, PM_K_HALO, st, hadd_bytes, 0.0)
-  if (in.unit) {
+#define PM_TILES(NCH, UNIT) PM_TILES_W(NCH, UNIT, false)
+  if (in.pi_pm) {
+    PM_TILES_W(4, true, true);
+  } else if (in.unit) {
     switch (nch) {
       case 1: PM_TILES(1, true); break;
       case 2: PM_TILES(2, true); break;
@@ -766,6 +785,7 @@ int paint_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
     }
   }
 #undef PM_TILES
+#undef PM_TILES_W
   (void)sb;
   PM_HIP_CHECK(p, hipGetLastError());
   return PM_OK;

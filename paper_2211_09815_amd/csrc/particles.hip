@@ -143,7 +143,8 @@ __device__ __forceinline__ void load_box(const TileGeo& g, const T* __restrict__
     if (slot[it] >= 0) box[slot[it]] = bv[it];
 }
 
-template <typename S, typename T, int MODE, int NF>
+// CPM: the cotangent is particle-major, [N][3] (GatherArgs::cot_pm).
+template <typename S, typename T, int MODE, int NF, bool CPM = false>
 // the VJP gather keeps three workgroups per CU (six waves per SIMD)
 __global__ __launch_bounds__(kGatherThreads, MODE == GATHER_VJP ? 6 : 1) void k_gather_tiles(GatherP<S, T> a) {
   // particles per thread per chunk: one for the adjoint modes, whose register
@@ -184,7 +185,7 @@ __global__ __launch_bounds__(kGatherThreads, MODE == GATHER_VJP ? 6 : 1) void k_
         for (int ax = 0; ax < 3; ++ax) {
           if (!REC) xs[k][ax] = a.s[ax * g.N + n];
           if (KICKF || KICKA) ps[k][ax] = a.p[ax * g.N + n];
-          if (COT) cs[k][ax] = a.cot[ax * g.N + n];
+          if (COT) cs[k][ax] = a.cot[CPM ? 3 * n + ax : ax * g.N + n];
           if (KICKA) xis[k][ax] = a.xi[ax * g.N + n];
         }
       }
@@ -372,6 +373,7 @@ template <typename S, typename T>
 int gather_typed(Plan* p, GatherMode mode, const GatherArgs& in, hipStream_t st) {
   if (in.sorted_out && !((mode == GATHER_PLAIN && in.nf == 3) || mode == GATHER_VJP))
     return set_error(p, PM_EINVAL, "tile-order outputs are three components per particle");
+  if (in.cot_pm && mode != GATHER_VJP) return set_error(p, PM_EINVAL, "a particle-major cotangent is the VJP's");
   GatherP<S, T> a;
   a.g = tile_geo(p);
   a.s = static_cast<const S*>(in.s);
@@ -395,6 +397,7 @@ int gather_typed(Plan* p, GatherMode mode, const GatherArgs& in, hipStream_t st)
   const dim3 grid(unsigned(p->ntiles)), block(kGatherThreads);
   timing_begin(p, PM_K_GATHER, st);
 #define PM_GATHER(MODE, NF) hipLaunchKernelGGL((k_gather_tiles<S, T, MODE, NF>), grid, block, 0, st, a)
+#define PM_GATHER_CPM(MODE, NF) hipLaunchKernelGGL((k_gather_tiles<S, T, MODE, NF, true>), grid, block, 0, st, a)
   switch (mode) {
     case GATHER_PLAIN:
       switch (in.nf) {
@@ -405,10 +408,14 @@ int gather_typed(Plan* p, GatherMode mode, const GatherArgs& in, hipStream_t st)
       }
       break;
     case GATHER_KICK_FWD: PM_GATHER(GATHER_KICK_FWD, 3); break;
-    case GATHER_VJP: PM_GATHER(GATHER_VJP, 4); break;
+    case GATHER_VJP:
+      if (in.cot_pm) PM_GATHER_CPM(GATHER_VJP, 4);
+      else PM_GATHER(GATHER_VJP, 4);
+      break;
     case GATHER_KICK_ADJ: PM_GATHER(GATHER_KICK_ADJ, 4); break;
     case GATHER_MSE: PM_GATHER(GATHER_MSE, 1); break;
   }
+#undef PM_GATHER_CPM
 #undef PM_GATHER
   {
     // list, positions (the CIC records with FP32 meshes, else s) and the
@@ -483,6 +490,45 @@ int kick_flush(Plan* p, void* ps, const void* a, double Kp, bool adjoint, void* 
   if (m64) kick_flush_typed<double, double>(p, ps, a, Kp, adjoint, xi, al, Kx, acc_out, st);
   else if (s64) kick_flush_typed<double, float>(p, ps, a, Kp, adjoint, xi, al, Kx, acc_out, st);
   else kick_flush_typed<float, float>(p, ps, a, Kp, adjoint, xi, al, Kx, acc_out, st);
+  PM_HIP_CHECK(p, hipGetLastError());
+  return PM_OK;
+}
+
+// dst <- src with pi's layout changed: [3][N] to particle-major [N][3]
+// (TO_PM) or back
+template <typename T, bool TO_PM>
+__global__ __launch_bounds__(kThreads) void k_pi_layout(const T* __restrict__ src, T* __restrict__ dst, int64_t N) {
+  const int64_t stride = int64_t(gridDim.x) * kThreads;
+  for (int64_t n = int64_t(blockIdx.x) * kThreads + threadIdx.x; n < N; n += stride) {
+    T v[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) v[ax] = TO_PM ? src[ax * N + n] : src[3 * n + ax];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) (TO_PM ? dst[3 * n + ax] : dst[ax * N + n]) = v[ax];
+  }
+}
+
+template <typename T>
+void pi_layout_launch(const void* src, void* dst, int64_t N, bool to_pm, hipStream_t st) {
+  const int64_t need = (N + kThreads - 1) / kThreads;
+  const dim3 grid(unsigned(need < 4096 ? need : 4096)), block(kThreads);
+  const T* x = static_cast<const T*>(src);
+  T* y = static_cast<T*>(dst);
+  if (to_pm) hipLaunchKernelGGL((k_pi_layout<T, true>), grid, block, 0, st, x, y, N);
+  else hipLaunchKernelGGL((k_pi_layout<T, false>), grid, block, 0, st, x, y, N);
+}
+
+bool pi_layout_fits(const Plan* p) { return 3 * p->nptcl <= 4 * p->ncell; }
+
+int pi_layout(Plan* p, void* pi, bool to_pm, hipStream_t st) {
+  if (!pi_layout_fits(p)) return set_error(p, PM_EINVAL, "pi does not fit the mesh workspace");
+  const size_t rb = p->cfg.mesh_dtype == PM_F64 ? 8 : 4;
+  const int64_t N = p->nptcl;
+  // the plan's meshes are one allocation of 4 ncell values, free between steps
+  void* ws = p->mesh[0];
+  PM_HIP_CHECK(p, hipMemcpyAsync(ws, pi, size_t(3) * size_t(N) * rb, hipMemcpyDeviceToDevice, st));
+  if (rb == 8) pi_layout_launch<double>(ws, pi, N, to_pm, st);
+  else pi_layout_launch<float>(ws, pi, N, to_pm, st);
   PM_HIP_CHECK(p, hipGetLastError());
   return PM_OK;
 }

@@ -221,7 +221,17 @@ struct PaintArgs {
   // particle n's three values are at 3 (offs[key.x] + key.y) + 0..2 of its
   // previous (tile, rank) key
   bool kick_sorted;
+  // pi (adjoint drift, and the weights of its four-channel paint) is
+  // particle-major, [N][3], instead of [3][N]: the layout a native adjoint
+  // loop keeps it in, so that the paint reads one 12-byte run per particle
+  // through the lists instead of three scattered components
+  bool pi_pm;
 };
+// pi (mesh dtype) between [3][N] and particle-major [N][3] in place (to_pm:
+// to [N][3]), through the plan's mesh workspace of 4 ncell values, which
+// must hold 3 N of them (pi_layout_fits)
+bool pi_layout_fits(const Plan* p);
+int pi_layout(Plan* p, void* pi, bool to_pm, hipStream_t st);
 // apply a pending kick without a drift (the end of a native loop); a and al
 // are particle-major in the tile order of the last binning (see
 // PaintArgs::kick_sorted);
@@ -259,6 +269,8 @@ struct GatherArgs {
   // contiguous per tile), for a consumer that looks them up through the bins
   // (PaintArgs::kick_sorted)
   bool sorted_out;
+  // cot is particle-major, [N][3] (PaintArgs::pi_pm)
+  bool cot_pm;
   double K;
   double* partials;     // per-block partial of cot . a
 };

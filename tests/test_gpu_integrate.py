@@ -256,16 +256,19 @@ def test_adjoint_memory_is_flat_in_step_count():
     assert max(peaks) - min(peaks) == 0, peaks
 
 
-@pytest.mark.parametrize("mdt,sdt", [(torch.float32, torch.float64), (torch.float64, torch.float64),
-                                     (torch.float32, torch.float32)])
-def test_native_loops_match_step_calls(mdt, sdt):
+@pytest.mark.parametrize("mdt,sdt,nm", [(torch.float32, torch.float64, 32), (torch.float64, torch.float64, 32),
+                                        (torch.float32, torch.float32, 32), (torch.float32, torch.float64, 8),
+                                        (torch.float64, torch.float64, 8)])
+def test_native_loops_match_step_calls(mdt, sdt, nm):
     # the native loops pm_run_fwd / pm_run_adj must leave exactly the state
     # that the sequence of step calls leaves (theta_bar up to the order of
     # its FP64 partial sums); so must two step calls followed by
-    # pm_run_adj_from for the rest of the reverse pass
+    # pm_run_adj_from for the rest of the reverse pass.  On the 32^3 mesh the
+    # adjoint loop keeps pi particle-major (3 N values fit the plan's four
+    # meshes); on the 8^3 mesh they do not, and it keeps the [3][N] layout
     api = _api()
-    announce("native loops vs step calls %s/%s" % (mdt, sdt))
-    n, nm, box, steps = 16, 32, 64.0, 6
+    announce("native loops vs step calls %s/%s mesh %d" % (mdt, sdt, nm))
+    n, box, steps = 16, 64.0, 6
     cfg = osim.SimConfig(n, nm, box, 1 / 16, 1.0, steps)
     omega = inputs.white_noise(n, 0)
     s0, p0 = osim.initial_state(omega, cfg)
