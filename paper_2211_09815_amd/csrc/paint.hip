@@ -332,9 +332,11 @@ constexpr int kPaintThreads = 512;  // threads per tile workgroup of the paint
 
 // One workgroup per tile; weights: channel 0 unit mass if UNIT, then w[c].
 // Particles are taken in chunks of P per thread whose loads are all issued
-// before any is used.  A tile whose particles fit in one chunk takes the
-// per-channel bound max|w| from the registers; larger tiles (the common case
-// with three or more channels) read their weights once more for it.
+// before any is used; the first chunk's are issued before the box is
+// cleared.  A tile whose particles fit in one chunk takes the per-channel
+// bound max|w| from the registers; larger tiles (the common case with three or
+// more channels) take the weights' global maxima when the adjoint drift has
+// formed them, else read their weights once more for it.
 // FIXED: the 64-bit fixed-point sums described above (bitwise reproducible).
 // Otherwise the box holds mesh-type sums updated with floating-point LDS
 // atomics (ds_add_f32 / ds_add_f64), whose order, and so whose rounding,
@@ -485,8 +487,10 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
     }
   };
 
+  // the first chunk's loads are in flight while the box is cleared and the
+  // scales are set
   const bool one_chunk = fin - beg <= CHUNK;
-  if (one_chunk) load(beg);
+  load(beg);
   // clear every channel's whole box slot (no index arithmetic per cell)
   for (int i = tid; i < NCH * kBoxMax; i += kPaintThreads) box[i] = 0ull;
   // per-channel bound of any cell sum: count * max|w| (unit mass: count)
@@ -544,13 +548,11 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
     }
   }
   __syncthreads();
-  if (one_chunk) {
+  for (unsigned c0 = beg;;) {
     paint();
-  } else {
-    for (unsigned c0 = beg; c0 < fin; c0 += CHUNK) {
-      load(c0);
-      paint();
-    }
+    c0 += CHUNK;
+    if (c0 >= fin) break;
+    load(c0);
   }
   __syncthreads();
   // core: plain stores, rows of tz contiguous cells
