@@ -231,7 +231,10 @@ int pm_step_adj(pm_plan plan, pm_state* st, pm_adj* adj, const pm_step_coef* cur
  * result.  With st->acc given, the loops use it as scratch: each gather
  * stores a there and leaves its kick to the next step's drift (the plan's
  * workspace holds alpha for the adjoint).  After pm_run_fwd, acc holds a_n
- * as after the step calls; after pm_run_adj its contents are unspecified. */
+ * as after the step calls; after pm_run_adj its contents are unspecified.
+ * With st->acc given, pm_run_adj also holds adj->pi particle-major while it
+ * runs (whenever 3 N_p values fit the plan's four meshes) and returns it as
+ * [3][N_p]; if the call fails, pi's contents are unspecified. */
 int pm_run_fwd(pm_plan plan, pm_state* st, const pm_step_coef* coefs, int n, double omega_m,
                hipStream_t stream);
 int pm_run_adj(pm_plan plan, pm_state* st, pm_adj* adj, const pm_step_coef* coefs, int n,
@@ -242,8 +245,8 @@ int pm_run_adj(pm_plan plan, pm_state* st, pm_adj* adj, const pm_step_coef* coef
  * pm_step_adj call: n reverse steps n..1 (coefs[0..n-1]), bitwise the same
  * as those n pm_step_adj calls.  For drivers that interleave their own work
  * with the last reverse steps (the light-cone gradient adds its bumps there)
- * and run the rest natively.  st->acc, if given, is scratch as in pm_run_adj.
- * Errors as pm_step_adj. */
+ * and run the rest natively.  st->acc, if given, is scratch as in pm_run_adj,
+ * and pi is handled as there.  Errors as pm_step_adj. */
 int pm_run_adj_from(pm_plan plan, pm_state* st, pm_adj* adj, const pm_step_coef* coefs, int n,
                     double omega_m, double* theta_bar, hipStream_t stream);
 
