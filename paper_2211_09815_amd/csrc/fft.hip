@@ -17,11 +17,13 @@ using fftk::Ptrs4;
 
 namespace {
 
-// y pass: lines of n1 with stride nh, columns kz (nh), outer x (stride n1*nh)
+// y pass: lines of n1 with stride nh, columns kz (nh), outer x (stride n1*nh);
+// array dual (>= 0) also to dual_out, then times ky in place
 template <typename T>
-int y_pass(Plan* p, const FftShape& s, const Ptrs4& a, int batch, bool inv, hipStream_t st) {
+int y_pass(Plan* p, const FftShape& s, const Ptrs4& a, int batch, bool inv, hipStream_t st, int dual = -1,
+           void* dual_out = nullptr) {
   const int nh = s.n2 / 2 + 1;
-  return fftk::lines_pass<T>(p, a, batch, inv, s.n1, nh, nh, int64_t(s.n1) * nh, s.n0, st);
+  return fftk::lines_pass<T>(p, a, batch, inv, s.n1, nh, nh, int64_t(s.n1) * nh, s.n0, st, dual, dual_out);
 }
 
 // x pass: lines of n0 with stride n1*nh over the flattened (y, kz) plane
@@ -75,7 +77,10 @@ int fft_spectral_op(Plan* p, const FftShape& s, SpecOp op, T* const* reals, cplx
   if (rc) return rc;
   // outputs in place: GRAD3 g_j -> specs[j]; ADJ4 g_0 -> specs[0],
   // g_1 -> specs[2], g_2 -> specs[3], rhobar -> specs[1] (safe under the
-  // kernel's read-before-write order)
+  // kernel's read-before-write order).  The x pass writes g_0, the common
+  // factor h of g_1 and g_2 (into g_1's array) and rhobar; the y pass turns
+  // h into ky h (g_1) and, as a second transform, h into g_2's array, whose
+  // kz the z pass applies.
   Ptrs4 so{};
   if (op == SPEC_GRAD3) {
     so = fftk::ptrs(specs, 3);
@@ -87,8 +92,13 @@ int fft_spectral_op(Plan* p, const FftShape& s, SpecOp op, T* const* reals, cplx
   }
   if ((rc = fftk::x_fused_pass<T>(p, s, op, spec_in, so, coef, st))) return rc;
   const int64_t ncell = int64_t(s.n0) * s.n1 * s.n2;
-  rc = y_pass<T>(p, s, so, nout, true, st);
-  if (!rc) rc = fftk::c2r_z_pass<T>(p, s, so, fftk::ptrs(reals, nout), nout, T(2.0) / T(ncell), st);
+  // the y pass over g_0, h (two transforms) and rhobar
+  Ptrs4 sy{};
+  sy.p[0] = so.p[0];
+  sy.p[1] = so.p[1];
+  sy.p[2] = so.p[3];
+  rc = y_pass<T>(p, s, sy, nout - 1, true, st, 1, so.p[2]);
+  if (!rc) rc = fftk::c2r_z_pass<T>(p, s, so, fftk::ptrs(reals, nout), nout, T(2.0) / T(ncell), st, 2);
   return rc;
 }
 

@@ -353,17 +353,20 @@ __device__ __forceinline__ void load_twiddles(C* tws, const C* __restrict__ tw) 
 // ---------------------------------------------------------------------------
 // strided complex pass over `batch` arrays: lines of length M (stride ls),
 // W-wide tiles of adjacent columns out of ncols, repeated over nouter blocks
-// of stride ostride
+// of stride ostride.  Array `dual` (>= 0) is transformed twice: as it is into
+// dual_out (same layout), and times the line's wavenumber in place.
 template <typename T>
 int lines_pass(Plan* p, const Ptrs4& arrs, int batch, bool inv, int M, int64_t ls, int64_t ncols,
-               int64_t ostride, int64_t nouter, hipStream_t st);
+               int64_t ostride, int64_t nouter, hipStream_t st, int dual = -1, void* dual_out = nullptr);
 // z passes between real lines of n2 and half-spectrum lines of n2/2 + 1
 template <typename T>
 int r2c_z_pass(Plan* p, const FftShape& s, const Ptrs4& in, const Ptrs4& out, int batch, const ZFold* zf,
                hipStream_t st);
+// kz_arr (>= 0): that array's spectrum is first multiplied by kz = 2 pi k / n2
+// (zero on the Nyquist bin)
 template <typename T>
 int c2r_z_pass(Plan* p, const FftShape& s, const Ptrs4& in, const Ptrs4& out, int batch, T scale,
-               hipStream_t st);
+               hipStream_t st, int kz_arr = -1);
 // fused forward x pass, spectral multipliers and inverse x passes
 template <typename T>
 int x_fused_pass(Plan* p, const FftShape& s, SpecOp op, const Ptrs4& in, const Ptrs4& out, T coef,

@@ -47,12 +47,16 @@ __device__ __forceinline__ KCol<T> kcol(int64_t col, int n1, int n2, int nh) {
 constexpr int x_ept(bool f32, int logm) { return f32 && logm <= 9 ? 8 : (f32 ? 16 : 8); }
 
 // T_j = i k_j coef / k^2, zero at k = 0 and on the Nyquist plane of j.
-// GRAD3:  out_j = T_j in_0,                                j = 0..2
-// ADJ4:   out_3 = -sum_j T_j in_{1+j},  out_j = T_j in_0,  j = 0..2
+// GRAD3:  out_0 = T_0 in_0,  out_1 = h
+// ADJ4:   out_3 = -sum_j T_j in_{1+j},  out_0 = T_0 in_0,  out_1 = h
+// with h = i coef / k^2 in_0 (zero on the x Nyquist plane), the common factor
+// of the y and z components: the y pass forms T_1 in_0 = ky h and h from it
+// (lines_pass with a second transform), and the z pass multiplies by kz.
+// Writing one array for both saves a spectrum write here and a read there.
 // The tile columns run over the flattened (y, kz) plane of the half
 // spectrum.  ADJ4 first consumes in_1..3 and writes out_3, then consumes
-// in_0 and writes out_0..2, so out_3 may alias in_1..3 and out_0..2 may
-// alias any input.
+// in_0 and writes out_0 and out_1, so out_3 may alias in_1..3 and out_0..1
+// may alias any input.
 template <typename T, int LOGM, int OP>
 __global__ __launch_bounds__(kFT, 4) void k_fft_x_fused(Ptrs4 ins, Ptrs4 outs, int n1, int n2, int nh, T coef,
                                                         const cplx<T>* __restrict__ tw) {
@@ -134,43 +138,31 @@ __global__ __launch_bounds__(kFT, 4) void k_fft_x_fused(Ptrs4 ins, Ptrs4 outs, i
       reg_last_stage<EPT, false, LOGM, LOGW, LOGM, LRMAX, false>(lds, tws, X);
     }
   };
-  // inverse FFT along x of Y (frequency rows, the forward's last layout);
-  // stores it to dst_a, or with yz set, ky times it to dst_a and kz times it
-  // to dst_b
-  auto store_rows = [&](int tid, const auto& u, int lr, void* dst_a, void* dst_b, auto yz) {
+  // inverse FFT along x of Y (frequency rows, the forward's last layout),
+  // stored to dst
+  auto store_rows = [&](int tid, const auto& u, int lr, void* dst) {
     constexpr int NB = sizeof(u) / sizeof(u[0]);
     constexpr int NR = sizeof(u[0]) / sizeof(C);
-    C* da = static_cast<C*>(dst_a) + c0;
-    C* db = static_cast<C*>(dst_b) + c0;
+    C* d = static_cast<C*>(dst) + c0;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int col = colof(tid, b);
       if (c0 + col >= ncols) continue;
-      T ky = T(1), kz = T(1);
-      if constexpr (!std::is_same_v<decltype(yz), std::nullptr_t>) yz(tid, b, ky, kz);
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const int64_t at = int64_t(((tid + b * kFT) >> LOGW) + (r << (LOGM - lr))) * ls + col;
-        if constexpr (std::is_same_v<decltype(yz), std::nullptr_t>) {
-          da[at] = u[b][r];
-        } else {
-          da[at] = cmk<C>(ky * u[b][r].x, ky * u[b][r].y);
-          db[at] = cmk<C>(kz * u[b][r].x, kz * u[b][r].y);
-        }
-      }
+      for (int r = 0; r < NR; ++r) d[int64_t(((tid + b * kFT) >> LOGW) + (r << (LOGM - lr))) * ls + col] = u[b][r];
     }
   };
-  auto inverse_store = [&](C (&Y)[IF::B][IF::R], void* dst_a, void* dst_b, auto yz) {
+  auto inverse_store = [&](C (&Y)[IF::B][IF::R], void* dst) {
     __syncthreads();   // earlier readers of lds are done
     reg_first_stage<EPT, true, LOGM, LOGW, LRMAX, true>(Y, lds);
     const int tid = fresh_tid();
     if constexpr (S == 1) {
-      store_rows(tid, Y, IF::LR, dst_a, dst_b, yz);
+      store_rows(tid, Y, IF::LR, dst);
     } else {
       reg_middle_stages<EPT, true, LOGM, LOGW, LOGM, LRMAX, true, 1>(lds, tws);
       C u[IL::B][IL::R];
       reg_last_stage<EPT, true, LOGM, LOGW, LOGM, LRMAX, true>(lds, tws, u);
-      store_rows(tid, u, IL::LR, dst_a, dst_b, yz);
+      store_rows(tid, u, IL::LR, dst);
     }
   };
   // forward FFT along x of ky in_a + kz in_b (ky, kz of each column)
@@ -244,9 +236,9 @@ __global__ __launch_bounds__(kFT, 4) void k_fft_x_fused(Ptrs4 ins, Ptrs4 outs, i
         // -i g s
         acc[b][r] = cmk<C>(acc[b][r].y * g, -acc[b][r].x * g);
       }
-    inverse_store(acc, outs.p[3], nullptr, nullptr);
+    inverse_store(acc, outs.p[3]);
   }
-  // out_0 = IFFT(i g kx X);  out_1, out_2 = ky, kz times IFFT(i g X)
+  // out_0 = IFFT(i g kx X);  out_1 = IFFT(i g X) (h; ky and kz later)
   C X[FL::B][FL::R];
   forward(ins.p[0], X, lds_busy);
   {
@@ -261,7 +253,7 @@ __global__ __launch_bounds__(kFT, 4) void k_fft_x_fused(Ptrs4 ins, Ptrs4 outs, i
         g *= kxn;
         Y[b][r] = cmk<C>(-X[b][r].y * g, X[b][r].x * g);
       }
-    inverse_store(Y, outs.p[0], nullptr, nullptr);
+    inverse_store(Y, outs.p[0]);
   }
   {
     const int tid = fresh_tid();
@@ -273,7 +265,7 @@ __global__ __launch_bounds__(kFT, 4) void k_fft_x_fused(Ptrs4 ins, Ptrs4 outs, i
         gk(tid, b, r, g, kxn);
         X[b][r] = cmk<C>(-X[b][r].y * g, X[b][r].x * g);
       }
-    inverse_store(X, outs.p[1], outs.p[2], kyz);
+    inverse_store(X, outs.p[1]);
   }
 }
 
@@ -316,7 +308,7 @@ int x_fused_pass(Plan* p, const FftShape& s, SpecOp op, const Ptrs4& in, const P
   const size_t lds = size_t((1 << logM) + (1 << logM) * ((1 << logW) + 1)) * sizeof(cplx<T>);
   const cplx<T>* tw = static_cast<const cplx<T>*>(p->tw);
   const int nin = op == SPEC_GRAD3 ? 1 : 4;
-  const int nout = op == SPEC_GRAD3 ? 3 : 4;
+  const int nout = op == SPEC_GRAD3 ? 2 : 3;
   timing_begin(p, PM_K_FFT_POISSON, st);
   (void)with_log2<2, 10>(logM, [&](auto L) {
     constexpr int LOGM = decltype(L)::value;

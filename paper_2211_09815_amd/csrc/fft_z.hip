@@ -91,9 +91,10 @@ __global__ __launch_bounds__(kFT, 4) void k_fft_r2c_z(Ptrs4 ins, Ptrs4 outs, int
 // complex -> real.  From X[0..M] (imaginary parts of X[0] and X[M] ignored):
 // E = (X[k] + conj X[M-k])/2,  O = (X[k] - conj X[M-k]) conj(w^k)/2,
 // Z = E + i O,  z = IFFT_M(Z) (unnormalised),  x[2n] + i x[2n+1] = scale z[n].
+// Array kz_arr first takes X[k] times kz = 2 pi k / (2M), zero at k = M.
 template <typename T, int LOGM>
 __global__ __launch_bounds__(kFT, 4) void k_fft_c2r_z(Ptrs4 ins, Ptrs4 outs, int64_t nlines, T scale,
-                                                      const cplx<T>* __restrict__ tw) {
+                                                      const cplx<T>* __restrict__ tw, int kz_arr) {
   using C = cplx<T>;
   using R = T;
   constexpr int EPT = Cfg<T>::EPT;
@@ -121,6 +122,18 @@ __global__ __launch_bounds__(kFT, 4) void k_fft_c2r_z(Ptrs4 ins, Ptrs4 outs, int
         const C* line = src + int64_t(l) * (M + 1);
         a[i] = line[k];
         b[i] = line[M - k];
+      }
+    }
+    if (int(blockIdx.y) == kz_arr) {
+      // the z factor of the gradient (the Nyquist bin M, and k = 0, get zero)
+      const T two_pi = T(6.283185307179586476925286766559);
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int k = (tid + i * kFT) & (M - 1);
+        const T ka = two_pi * T(k) / T(2 * M);
+        const T kb = k == 0 ? T(0) : two_pi * T(M - k) / T(2 * M);
+        a[i] = cmk<C>(ka * a[i].x, ka * a[i].y);
+        b[i] = cmk<C>(kb * b[i].x, kb * b[i].y);
       }
     }
     load_twiddles<LOGL>(tws, tw);
@@ -191,7 +204,8 @@ int r2c_z_pass(Plan* p, const FftShape& s, const Ptrs4& in, const Ptrs4& out, in
 }
 
 template <typename T>
-int c2r_z_pass(Plan* p, const FftShape& s, const Ptrs4& in, const Ptrs4& out, int batch, T scale, hipStream_t st) {
+int c2r_z_pass(Plan* p, const FftShape& s, const Ptrs4& in, const Ptrs4& out, int batch, T scale, hipStream_t st,
+               int kz_arr) {
   const int nh = s.n2 / 2 + 1;
   const int logM = ilog2(s.n2 / 2);
   const int64_t nlines = int64_t(s.n0) * s.n1;
@@ -203,7 +217,7 @@ int c2r_z_pass(Plan* p, const FftShape& s, const Ptrs4& in, const Ptrs4& out, in
   (void)with_log2<1, 9>(logM, [&](auto L) {
     constexpr int LOGM = decltype(L)::value;
     allow_lds(p, k_fft_c2r_z<T, LOGM>, lds);
-    hipLaunchKernelGGL((k_fft_c2r_z<T, LOGM>), grid, dim3(kFT), lds, st, in, out, nlines, scale, tw);
+    hipLaunchKernelGGL((k_fft_c2r_z<T, LOGM>), grid, dim3(kFT), lds, st, in, out, nlines, scale, tw, kz_arr);
     return PM_OK;
   });
   // method bytes: the 3-D C2R's half spectrum read and real output written
@@ -215,8 +229,8 @@ int c2r_z_pass(Plan* p, const FftShape& s, const Ptrs4& in, const Ptrs4& out, in
 
 template int r2c_z_pass<float>(Plan*, const FftShape&, const Ptrs4&, const Ptrs4&, int, const ZFold*, hipStream_t);
 template int r2c_z_pass<double>(Plan*, const FftShape&, const Ptrs4&, const Ptrs4&, int, const ZFold*, hipStream_t);
-template int c2r_z_pass<float>(Plan*, const FftShape&, const Ptrs4&, const Ptrs4&, int, float, hipStream_t);
-template int c2r_z_pass<double>(Plan*, const FftShape&, const Ptrs4&, const Ptrs4&, int, double, hipStream_t);
+template int c2r_z_pass<float>(Plan*, const FftShape&, const Ptrs4&, const Ptrs4&, int, float, hipStream_t, int);
+template int c2r_z_pass<double>(Plan*, const FftShape&, const Ptrs4&, const Ptrs4&, int, double, hipStream_t, int);
 
 }  // namespace fftk
 }  // namespace pmx
