@@ -40,6 +40,17 @@ Readings (the paper gives no formulas for these; each is ours):
       drops d t^/d theta in its continuous derivation, where that term
       vanishes on the true trajectory; on the spline it does not vanish
       exactly, so it is kept.
+  L7  The paper's own adjoint sets a particle's adjoint to zero after its
+      crossing (Sec. 3.4), which drops the gravitational coupling of an
+      observed particle to the particles observed after it.  As an option
+      (truncate), the discrete form of that: in reverse step i, every
+      particle observed in an earlier step (0 < step < i) carries no
+      adjoint; it gives no cotangent to the force VJPs of step i and what it
+      receives there is discarded (zeroed after each of the step's two kick
+      VJPs).  This is the exact gradient of the forward map in which, during
+      step i, the particles observed before step i source gravity as
+      constants.  Particles in their own crossing step, and never-observed
+      ones, keep the exact adjoint.
 """
 import numpy as np
 from scipy.integrate import quad
@@ -264,10 +275,12 @@ def observation_cotangents(traj, P, a_grid, om, cell, observer, step, obs_bar):
     return xb, pb, om_b
 
 
-def adjoint_stored_with_observations(traj, coefs, dcoefs, xb, pb, F):
+def adjoint_stored_with_observations(traj, coefs, dcoefs, xb, pb, F, step=None):
     """Reverse accumulation through eq. KDFK along the stored trajectory with
     the partial derivatives dJ/dx_k, dJ/dp_k added at every integer time k
-    (eq. explicit_adj).  Returns (xi_0, pi_0, dJ/dOmega_m from the steps)."""
+    (eq. explicit_adj).  Returns (xi_0, pi_0, dJ/dOmega_m from the steps).
+    With `step` (the crossing step of each particle, 0 = never observed) the
+    adjoint is truncated as in reading L7."""
     n = len(coefs)
     xi = np.array(xb[n], dtype=np.float64)
     pi = np.array(pb[n], dtype=np.float64)
@@ -278,10 +291,14 @@ def adjoint_stored_with_observations(traj, coefs, dcoefs, xb, pb, F):
         x_i, a_i = traj["x"][i], traj["a"][i]
         p_half = traj["p_half"][i - 1]
         x_im1, a_im1 = traj["x"][i - 1], traj["a"][i - 1]
+        # particles observed before step i (reading L7; empty without step)
+        gone = np.zeros(len(xi), dtype=bool) if step is None else (step > 0) & (step < i)
         # p_i = p_{i-1/2} + a(x_i) Kb_i
         g, ob, _ = F.vjp(x_i, pi * Kb)
         th += np.sum(pi * a_i) * dKb + ob
         xi = xi + g
+        xi[gone] = 0.0
+        pi[gone] = 0.0
         # x_i = x_{i-1} + p_{i-1/2} D_i
         th += np.sum(xi * p_half) * dD
         pi = pi + xi * D
@@ -289,16 +306,19 @@ def adjoint_stored_with_observations(traj, coefs, dcoefs, xb, pb, F):
         g, ob, _ = F.vjp(x_im1, pi * Ka)
         th += np.sum(pi * a_im1) * dKa + ob
         xi = xi + g
+        xi[gone] = 0.0
+        pi[gone] = 0.0
         # the observations' partial derivatives at t_{i-1}
         xi = xi + xb[i - 1]
         pi = pi + pb[i - 1]
     return xi, pi, th
 
 
-def value_and_grad(omega, cfg, observer, weights):
+def value_and_grad(omega, cfg, observer, weights, truncate=False):
     """J = linear_objective of the light-cone observation of the run from
-    white noise omega, and (dJ/domega, dJ/dOmega_m, dJ/dsigma8).  Returns
-    (J, g_omega, g_theta, obs, step)."""
+    white noise omega, and (dJ/domega, dJ/dOmega_m, dJ/dsigma8), exact or
+    (truncate) with the adjoint of reading L7.  Returns (J, g_omega,
+    g_theta, obs, step)."""
     from . import simulate
     q = simulate.lattice(cfg)
     s0, p0 = simulate.initial_state(omega, cfg)
@@ -312,7 +332,7 @@ def value_and_grad(omega, cfg, observer, weights):
     obs, step = observe_run(traj, P, a_grid, om, cell, observer)
     J = linear_objective(obs, step, weights)
     xb, pb, om_obs = observation_cotangents(traj, P, a_grid, om, cell, observer, step, weights)
-    xi0, pi0, th = adjoint_stored_with_observations(traj, coefs, dcoefs, xb, pb, F)
+    xi0, pi0, th = adjoint_stored_with_observations(traj, coefs, dcoefs, xb, pb, F, step if truncate else None)
     g_omega = lpt.lpt_vjp(omega, cfg.box, cfg.cosmo, cfg.a_start, cfg.r, xi0, pi0)
     ds, dp = lpt.lpt_jvp_omega_m(omega, cfg.box, cfg.cosmo, cfg.a_start, cfg.r)
     g_om = th + om_obs + np.sum(xi0 * ds) + np.sum(pi0 * dp)

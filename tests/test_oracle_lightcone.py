@@ -4,7 +4,9 @@ explicit_adj).  No GPU."""
 import numpy as np
 import pytest
 
+from oracle import cosmology
 from oracle import cosmology as C
+from oracle import integrate
 from oracle import lightcone as L
 from oracle import simulate
 from paper_2211_09815_amd import inputs
@@ -202,6 +204,98 @@ def test_run_gradient_matches_central_differences():
             vals.append((L.objective_value(omega, cp, X, w) - L.objective_value(omega, cm, X, w)) / (2 * hh))
         assert vals[0] == pytest.approx(vals[1], rel=1e-6)
         assert gt[k] == pytest.approx(vals[1], rel=1e-6)
+
+
+def _objective_sourcing_frozen(omega, cfg, observer, weights, step, ref_x):
+    """J of the forward map in which, during step i, the particles observed
+    before step i (0 < step < i) source gravity from their positions ref_x in
+    the unperturbed run instead of their own: the map whose exact gradient
+    the truncated adjoint of reading L7 is.  NaN if the perturbation moved a
+    crossing to another step."""
+    q = simulate.lattice(cfg)
+    s, p = simulate.initial_state(omega, cfg)
+    om = cfg.cosmo.omega_m
+    a_grid = cfg.a_grid()
+    coefs = cosmology.step_coefficients(a_grid, om)
+    F = integrate.ForceModel(cfg.mesh_shape, cfg.n_particles, om)
+    xs, P = [q + s], [p.copy()]
+    for i, (Ka, D, Kb) in enumerate(coefs, start=1):
+        gone = (step > 0) & (step < i)
+
+        def acc(x, k):
+            xh = x.copy()
+            xh[gone] = ref_x[k][gone]
+            return F(xh)
+
+        p = p + acc(q + s, i - 1) * Ka
+        s = s + p * D
+        p = p + acc(q + s, i) * Kb
+        xs.append(q + s)
+        P.append(p.copy())
+    obs, st = L.observe_run({"x": xs}, P, a_grid, om, cfg.box / cfg.n_mesh, observer)
+    if not np.array_equal(st, step):
+        return float("nan")
+    return L.linear_objective(obs, st, weights)
+
+
+def test_truncated_gradient_is_the_gradient_with_observed_sources_frozen():
+    # reading L7 against central differences of the map it differentiates;
+    # first, that the truncation matters here (particles cross in two steps,
+    # so those of step n - 1 are dropped from the adjoint of step n)
+    cfg, X = lightcone_setup()
+    omega = inputs.white_noise(cfg.n_ptcl, 0)
+    w = inputs.normal((cfg.n_particles, 7), inputs.SEED_COTANGENT)
+    J, g, gt, _, step = L.value_and_grad(omega, cfg, X, w)
+    Jt, g_tr, gt_tr, _, step_t = L.value_and_grad(omega, cfg, X, w, truncate=True)
+    assert Jt == J and np.array_equal(step_t, step)
+    assert np.linalg.norm(g_tr - g) > 1e-4 * np.linalg.norm(g)
+    q = simulate.lattice(cfg)
+    s0, p0 = simulate.initial_state(omega, cfg)
+    coefs = cosmology.step_coefficients(cfg.a_grid(), cfg.cosmo.omega_m)
+    F = integrate.ForceModel(cfg.mesh_shape, cfg.n_particles, cfg.cosmo.omega_m)
+    ref_x = integrate.forward(q, s0, p0, coefs, F, store=True)[3]["x"]
+    Jf = lambda om_, c=cfg: _objective_sourcing_frozen(om_, c, X, w, step, ref_x)   # noqa: E731
+    assert Jf(omega) == pytest.approx(J, rel=1e-14)
+    flat = omega.ravel()
+    idx = inputs.probe_indices(flat.size, 24)
+    fds = []
+    for h in (1e-5, 5e-6):
+        fd = np.zeros(len(idx))
+        for t, i in enumerate(idx):
+            e = np.zeros_like(flat)
+            e[i] = h
+            fd[t] = (Jf((flat + e).reshape(omega.shape)) - Jf((flat - e).reshape(omega.shape))) / (2 * h)
+        fds.append(fd)
+    scale = np.abs(fds[0]).max()
+    smooth = np.abs(fds[0] - fds[1]) < 1e-7 * scale
+    assert smooth.mean() > 0.9
+    gs = g_tr.ravel()[idx][smooth]
+    assert np.linalg.norm(gs - fds[1][smooth]) / np.linalg.norm(gs) < 1e-7
+    # and the exact gradient is not the gradient of this map
+    ge = g.ravel()[idx][smooth]
+    assert np.linalg.norm(ge - fds[1][smooth]) / np.linalg.norm(gs) > 1e-5
+    hh = 1e-6
+    for k, (name, val) in enumerate([("omega_m", 0.3), ("sigma8", 0.8)]):
+        cp = cfg.with_cosmo(cfg.cosmo.replace(**{name: val + hh}))
+        cm = cfg.with_cosmo(cfg.cosmo.replace(**{name: val - hh}))
+        fd = (Jf(omega, cp) - Jf(omega, cm)) / (2 * hh)
+        assert gt_tr[k] == pytest.approx(fd, rel=1e-6)
+
+
+def test_truncation_keeps_the_gradient_of_the_first_observed_step():
+    # weights only on particles of the earliest crossing step: before their
+    # crossing (in reverse time: after it) nothing carries an adjoint, and
+    # from there on no particle has crossed earlier, so nothing is dropped
+    cfg, X = lightcone_setup()
+    omega = inputs.white_noise(cfg.n_ptcl, 0)
+    w = inputs.normal((cfg.n_particles, 7), inputs.SEED_COTANGENT)
+    _, _, _, _, step = L.value_and_grad(omega, cfg, X, w)
+    first = step[step > 0].min()
+    w1 = np.where((step == first)[:, None], w, 0.0)
+    _, g, gt, _, _ = L.value_and_grad(omega, cfg, X, w1)
+    _, g_tr, gt_tr, _, _ = L.value_and_grad(omega, cfg, X, w1, truncate=True)
+    np.testing.assert_array_equal(g_tr, g)
+    np.testing.assert_array_equal(gt_tr, gt)
 
 
 def test_vjp_is_finite_for_a_particle_at_the_observer():
