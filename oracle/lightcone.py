@@ -43,14 +43,14 @@ Readings (the paper gives no formulas for these; each is ours):
   L7  The paper's own adjoint sets a particle's adjoint to zero after its
       crossing (Sec. 3.4), which drops the gravitational coupling of an
       observed particle to the particles observed after it.  As an option
-      (truncate), the discrete form of that: in reverse step i, every
-      particle observed in an earlier step (0 < step < i) carries no
-      adjoint; it gives no cotangent to the force VJPs of step i and what it
-      receives there is discarded (zeroed after each of the step's two kick
-      VJPs).  This is the exact gradient of the forward map in which, during
-      step i, the particles observed before step i source gravity as
-      constants.  Particles in their own crossing step, and never-observed
-      ones, keep the exact adjoint.
+      (truncate), the discrete form of that: the force at integer time t_m
+      (the one evaluation that both half-kicks at t_m use) takes the
+      positions of the particles observed in steps 1..m as constants.  Its
+      VJP then gives those particles nothing: what they would receive is
+      discarded, while their own momentum cotangent still reaches the other
+      particles through it.  The result is the exact gradient of that
+      modified forward map; a particle observed in step s keeps its exact
+      adjoint up to t_s, the end of its crossing step.
 """
 import numpy as np
 from scipy.integrate import quad
@@ -291,23 +291,21 @@ def adjoint_stored_with_observations(traj, coefs, dcoefs, xb, pb, F, step=None):
         x_i, a_i = traj["x"][i], traj["a"][i]
         p_half = traj["p_half"][i - 1]
         x_im1, a_im1 = traj["x"][i - 1], traj["a"][i - 1]
-        # particles observed before step i (reading L7; empty without step)
-        gone = np.zeros(len(xi), dtype=bool) if step is None else (step > 0) & (step < i)
         # p_i = p_{i-1/2} + a(x_i) Kb_i
         g, ob, _ = F.vjp(x_i, pi * Kb)
         th += np.sum(pi * a_i) * dKb + ob
+        if step is not None:
+            g[(step > 0) & (step <= i)] = 0.0         # frozen at t_i (reading L7)
         xi = xi + g
-        xi[gone] = 0.0
-        pi[gone] = 0.0
         # x_i = x_{i-1} + p_{i-1/2} D_i
         th += np.sum(xi * p_half) * dD
         pi = pi + xi * D
         # p_{i-1/2} = p_{i-1} + a(x_{i-1}) Ka_i
         g, ob, _ = F.vjp(x_im1, pi * Ka)
         th += np.sum(pi * a_im1) * dKa + ob
+        if step is not None:
+            g[(step > 0) & (step <= i - 1)] = 0.0     # frozen at t_{i-1}
         xi = xi + g
-        xi[gone] = 0.0
-        pi[gone] = 0.0
         # the observations' partial derivatives at t_{i-1}
         xi = xi + xb[i - 1]
         pi = pi + pb[i - 1]

@@ -207,29 +207,31 @@ def test_run_gradient_matches_central_differences():
 
 
 def _objective_sourcing_frozen(omega, cfg, observer, weights, step, ref_x):
-    """J of the forward map in which, during step i, the particles observed
-    before step i (0 < step < i) source gravity from their positions ref_x in
-    the unperturbed run instead of their own: the map whose exact gradient
-    the truncated adjoint of reading L7 is.  NaN if the perturbation moved a
-    crossing to another step."""
+    """J of the forward map in which the force at t_m takes the particles
+    observed in steps 1..m at their positions ref_x[m] in the unperturbed run
+    instead of their own: the map whose exact gradient the truncated adjoint
+    of reading L7 is.  NaN if the perturbation moved a crossing to another
+    step."""
     q = simulate.lattice(cfg)
     s, p = simulate.initial_state(omega, cfg)
     om = cfg.cosmo.omega_m
     a_grid = cfg.a_grid()
     coefs = cosmology.step_coefficients(a_grid, om)
     F = integrate.ForceModel(cfg.mesh_shape, cfg.n_particles, om)
+
+    def acc(x, m):
+        xh = x.copy()
+        frozen = (step > 0) & (step <= m)
+        xh[frozen] = ref_x[m][frozen]
+        return F(xh)
+
     xs, P = [q + s], [p.copy()]
+    a = acc(q + s, 0)
     for i, (Ka, D, Kb) in enumerate(coefs, start=1):
-        gone = (step > 0) & (step < i)
-
-        def acc(x, k):
-            xh = x.copy()
-            xh[gone] = ref_x[k][gone]
-            return F(xh)
-
-        p = p + acc(q + s, i - 1) * Ka
+        p = p + a * Ka
         s = s + p * D
-        p = p + acc(q + s, i) * Kb
+        a = acc(q + s, i)
+        p = p + a * Kb
         xs.append(q + s)
         P.append(p.copy())
     obs, st = L.observe_run({"x": xs}, P, a_grid, om, cfg.box / cfg.n_mesh, observer)
@@ -240,8 +242,7 @@ def _objective_sourcing_frozen(omega, cfg, observer, weights, step, ref_x):
 
 def test_truncated_gradient_is_the_gradient_with_observed_sources_frozen():
     # reading L7 against central differences of the map it differentiates;
-    # first, that the truncation matters here (particles cross in two steps,
-    # so those of step n - 1 are dropped from the adjoint of step n)
+    # first, that the truncation matters here
     cfg, X = lightcone_setup()
     omega = inputs.white_noise(cfg.n_ptcl, 0)
     w = inputs.normal((cfg.n_particles, 7), inputs.SEED_COTANGENT)
@@ -280,22 +281,6 @@ def test_truncated_gradient_is_the_gradient_with_observed_sources_frozen():
         cm = cfg.with_cosmo(cfg.cosmo.replace(**{name: val - hh}))
         fd = (Jf(omega, cp) - Jf(omega, cm)) / (2 * hh)
         assert gt_tr[k] == pytest.approx(fd, rel=1e-6)
-
-
-def test_truncation_keeps_the_gradient_of_the_first_observed_step():
-    # weights only on particles of the earliest crossing step: before their
-    # crossing (in reverse time: after it) nothing carries an adjoint, and
-    # from there on no particle has crossed earlier, so nothing is dropped
-    cfg, X = lightcone_setup()
-    omega = inputs.white_noise(cfg.n_ptcl, 0)
-    w = inputs.normal((cfg.n_particles, 7), inputs.SEED_COTANGENT)
-    _, _, _, _, step = L.value_and_grad(omega, cfg, X, w)
-    first = step[step > 0].min()
-    w1 = np.where((step == first)[:, None], w, 0.0)
-    _, g, gt, _, _ = L.value_and_grad(omega, cfg, X, w1)
-    _, g_tr, gt_tr, _, _ = L.value_and_grad(omega, cfg, X, w1, truncate=True)
-    np.testing.assert_array_equal(g_tr, g)
-    np.testing.assert_array_equal(gt_tr, gt)
 
 
 def test_vjp_is_finite_for_a_particle_at_the_observer():
