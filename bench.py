@@ -666,6 +666,23 @@ def study_lightcone(args):
     res["gradient_lightcone_kernels"] = {"launches": nl_g, "ms_total": ms_g}
     res["dJ_dtheta"] = th.cpu().tolist()
     res["grad_omega_norm"] = float(torch.linalg.vector_norm(g.double()))
+    # the truncated adjoint of Sec. 3.4 (the observed particles' sourcing
+    # frozen from the end of their crossing step) on the same run: its time
+    # and how far its gradient is from the exact one
+    g_ex, th_ex = g.double().clone(), th.clone()
+    lc.forward(omega, cosmo, ltabs)        # the reverse pass consumed the final state
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g_tr, th_tr = lc.gradient(omega, cosmo, w, ltabs, truncate=True)
+    torch.cuda.synchronize()
+    t_tr = time.perf_counter() - t0
+    res["truncated_gradient"] = {
+        "gradient_ms": 1000 * t_tr,
+        "grad_omega_rel_l2_vs_exact": float(torch.linalg.vector_norm(g_tr.double() - g_ex)
+                                            / torch.linalg.vector_norm(g_ex)),
+        "dJ_dtheta": th_tr.cpu().tolist(),
+        "dJ_dtheta_rel_diff_vs_exact": [abs(a - b) / abs(b) for a, b in zip(th_tr.cpu().tolist(),
+                                                                          th_ex.cpu().tolist())]}
     # the plain pass of the same run for comparison
     target = torch.zeros((nm,) * 3, dtype=torch.float32, device="cuda")
     _timed_pass(sim, omega, cosmo, target, tabs)

@@ -440,11 +440,24 @@ int pm_lightcone_vjp(pm_plan plan, const pm_lc_step* st, const void* s0, const v
  *   theta_bar[0] += dKb sum(p_bar . acc) + Kb (*omega_m_bar),
  * where c and *omega_m_bar are pm_force_vjp's disp_bar and omega_m_bar for
  * the cotangent p_bar at x_k, and acc = a_k.  c, acc and omega_m_bar may be
- * NULL (Kb = 0: p_0, or a kick the caller's own VJP already covers).  xi,
- * pi, x_bar, p_bar, c, acc: [3][N_p] mesh dtype. */
+ * NULL (Kb = 0: p_0, or a kick the caller's own VJP already covers).  p_bar
+ * may be NULL (only xi += x_bar + Kb c; pi may then be NULL too, acc must
+ * be).  xi, pi, x_bar, p_bar, c, acc: [3][N_p] mesh dtype. */
 int pm_adj_bump(pm_plan plan, void* xi, void* pi, const void* x_bar, const void* p_bar,
                 const void* c, double Kb, double dKb, const void* acc,
                 const double* omega_m_bar, double* theta_bar, hipStream_t stream);
+
+/* The truncated adjoint of Sec. 3.4, which sets a particle's adjoint to zero
+ * after its crossing, in the discrete form this library gives it: the force
+ * at integer time t_m takes the particles observed in steps 1..m as constant
+ * sources, so its VJP gives them nothing (their own momentum cotangent
+ * still acts).  A driver applies it to what a force VJP at t_m adds to the
+ * position adjoint: x[c][n] = 0 for c < 3 and every particle with
+ * 0 < obs_step[n] <= last (x: [3][N_p] mesh dtype, in place; obs_step as
+ * pm_lightcone writes it; last < 1 does nothing).  The result is the exact
+ * gradient of that modified forward map, not of the observed run. */
+int pm_lightcone_truncate(pm_plan plan, void* x, const int32_t* obs_step, int32_t last,
+                          hipStream_t stream);
 
 /* The kick and drift operators of eq. KDFK on their own (out may alias the
  * input): p_out = p + acc K (p, p_out state dtype, acc mesh dtype) and

@@ -127,6 +127,7 @@ _PROTOS = {
     "pm_lpt_vjp": (c_int, [c_vp, c_vp, P(PmCosmo), P(PmIcCoef), P(PmAdj), c_vp, c_vp, c_vp]),
     "pm_lightcone_tables": (c_int, [P(PmCosmo), P(c_dbl), c_int, c_dbl, P(PmLcCoef)]),
     "pm_lightcone_reach": (c_int, [c_vp, c_vp, P(c_dbl), c_vp, c_vp]),
+    "pm_lightcone_truncate": (c_int, [c_vp, c_vp, c_vp, c_i32, c_vp]),
     "pm_lightcone": (c_int, [c_vp, P(PmLcStep), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "pm_lightcone_vjp": (c_int, [c_vp, P(PmLcStep), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                                  c_vp, c_vp]),

@@ -372,6 +372,14 @@ class Plan:
         self._c(lib().pm_lightcone_reach(self._h, _ptr(disp), obs, _ptr(out), _stream()))
         return out
 
+    def lightcone_truncate(self, x, obs_step, last):
+        """pm_lightcone_truncate: x[:, n] = 0 (in place) for the particles
+        observed in steps 1..last (the frozen sources of the truncated
+        adjoint)."""
+        self._mesh3(x, "x")
+        self._t(obs_step, torch.int32, self.n_particles, "obs_step")
+        self._c(lib().pm_lightcone_truncate(self._h, _ptr(x), _ptr(obs_step), int(last), _stream()))
+
     def lightcone(self, step, s0, p0, s1, p1, obs, obs_step, count):
         """pm_lightcone: record the particles that cross the light front in
         `step` (a pm_lc_step) into obs [7, N_p] and obs_step [N_p];

@@ -243,10 +243,12 @@ __global__ __launch_bounds__(kThreads) void k_adj_bump(T* __restrict__ xi, T* __
   const int64_t stride = int64_t(gridDim.x) * kThreads;
   double dot = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n3; i += stride) {
-    const T pbi = pb[i];
     xi[i] = xi[i] + (c ? fma(Kb, c[i], xb[i]) : xb[i]);
-    pi[i] = pi[i] + pbi;
-    if (a) dot += double(pbi) * double(a[i]);
+    if (pb) {
+      const T pbi = pb[i];
+      pi[i] = pi[i] + pbi;
+      if (a) dot += double(pbi) * double(a[i]);
+    }
   }
   const double t = block_sum_d(dot);
   if (threadIdx.x == 0) {
@@ -301,6 +303,21 @@ int check_lc_step(Plan* p, const pm_lc_step* st) {
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(st->observer[k])) return set_error(p, PM_EINVAL, "observer position is not finite");
   return PM_OK;
+}
+
+// x[c][n] = 0 for the particles observed in steps 1..last (the frozen
+// sources of the truncated adjoint)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_truncate(T* __restrict__ x, const int32_t* __restrict__ obs_step,
+                                                       int32_t last, int64_t N) {
+  const int64_t stride = int64_t(gridDim.x) * kThreads;
+  for (int64_t n = int64_t(blockIdx.x) * kThreads + threadIdx.x; n < N; n += stride) {
+    const int32_t k = obs_step[n];
+    if (k > 0 && k <= last) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) x[c * N + n] = T(0);
+    }
+  }
 }
 
 // largest |q + s - X| over the particles: per-block maxima in part[b * 4],
@@ -407,6 +424,24 @@ extern "C" int pm_lightcone_reach(pm_plan h, const void* disp, const double* obs
   return PM_OK;
 }
 
+extern "C" int pm_lightcone_truncate(pm_plan h, void* x, const int32_t* obs_step, int32_t last,
+                                     hipStream_t stream) {
+  LC_PLAN(h);
+  if (int rc = lc_ptr(p, x, "x")) return rc;
+  if (int rc = lc_ptr(p, obs_step, "obs_step")) return rc;
+  if (int rc = lc_device(p)) return rc;
+  if (last < 1) return PM_OK;
+  const int blocks = elementwise_blocks(p->nptcl);
+  if (p->cfg.mesh_dtype == PM_F64)
+    hipLaunchKernelGGL(k_truncate<double>, dim3(blocks), dim3(kThreads), 0, stream, static_cast<double*>(x), obs_step,
+                       last, p->nptcl);
+  else
+    hipLaunchKernelGGL(k_truncate<float>, dim3(blocks), dim3(kThreads), 0, stream, static_cast<float*>(x), obs_step,
+                       last, p->nptcl);
+  PM_HIP_CHECK(p, hipGetLastError());
+  return PM_OK;
+}
+
 extern "C" int pm_lightcone_vjp(pm_plan h, const pm_lc_step* st, const void* s0, const void* p0, const void* s1,
                                 const void* p1, const int32_t* obs_step, const void* obs_bar, void* x0_bar,
                                 void* p0_bar, void* x1_bar, void* p1_bar, double* theta_bar, hipStream_t stream) {
@@ -440,10 +475,12 @@ extern "C" int pm_adj_bump(pm_plan h, void* xi, void* pi, const void* x_bar, con
                            double Kb, double dKb, const void* acc, const double* omega_m_bar, double* theta_bar,
                            hipStream_t stream) {
   LC_PLAN(h);
-  const void* ptrs[] = {xi, pi, x_bar, p_bar, theta_bar};
-  const char* names[] = {"xi", "pi", "x_bar", "p_bar", "theta_bar"};
-  for (int k = 0; k < 5; ++k)
+  const void* ptrs[] = {xi, x_bar, theta_bar};
+  const char* names[] = {"xi", "x_bar", "theta_bar"};
+  for (int k = 0; k < 3; ++k)
     if (int rc = lc_ptr(p, ptrs[k], names[k])) return rc;
+  if (p_bar && !pi) return set_error(p, PM_EINVAL, "pi is NULL");
+  if (!p_bar && acc) return set_error(p, PM_EINVAL, "acc needs p_bar");
   if (!std::isfinite(Kb) || !std::isfinite(dKb)) return set_error(p, PM_EINVAL, "Kb and dKb must be finite");
   if (int rc = lc_device(p)) return rc;
   const int64_t n3 = 3 * p->nptcl;
@@ -460,7 +497,7 @@ extern "C" int pm_adj_bump(pm_plan h, void* xi, void* pi, const void* x_bar, con
                        static_cast<const float*>(c), float(Kb), static_cast<const float*>(acc), omega_m_bar, n3,
                        p->partials);
   PM_HIP_CHECK(p, hipGetLastError());
-  const double bump_bytes = double(n3) * mb * (6.0 + (c ? 1.0 : 0.0) + (acc ? 1.0 : 0.0));
+  const double bump_bytes = double(n3) * mb * ((p_bar ? 6.0 : 3.0) + (c ? 1.0 : 0.0) + (acc ? 1.0 : 0.0));
   timing_end(p, PM_K_LIGHTCONE, stream, bump_bytes, bump_bytes);
   const double f[4] = {acc ? dKb : 0.0, omega_m_bar ? Kb : 0.0, 0.0, 0.0};
   if (f[0] == 0.0 && f[1] == 0.0) return PM_OK;

@@ -28,6 +28,12 @@ which no particle crosses, and the steps next to them, skip all of this;
 below the first observed step the rest of the reverse pass is the native loop
 (pm_run_adj_from).  The gradient is the exact gradient of the discrete
 forward map, up to the reversibility of the reconstruction.
+
+With truncate, the gradient is the truncated adjoint of Sec. 3.4 in the
+library's discrete form (pm_lightcone_truncate): every force VJP at t_m gives
+the particles observed in steps 1..m nothing.  Those VJPs are pm_adj_init's
+at t_n, each pm_step_adj(m + 1)'s at x_m and each bump's; the position
+cotangent of the observation at t_n is added after pm_adj_init's.
 """
 import numpy as np
 import torch
@@ -126,10 +132,11 @@ class LightCone:
         self.xb[1].zero_()
         self.pb[1].zero_()
 
-    def gradient(self, omega, cosmo, obs_bar, tables=None):
+    def gradient(self, omega, cosmo, obs_bar, tables=None, truncate=False):
         """dJ/domega and dJ/d(Omega_m, sigma8) for the cotangent obs_bar
         ([7, N_p] mesh dtype) of the observed (x^, p^, a^), after forward()
-        with the same arguments.  Returns (g_omega, theta_bar) on the device."""
+        with the same arguments; truncate: the truncated adjoint (module
+        docstring).  Returns (g_omega, theta_bar) on the device."""
         sim, plan = self.sim, self.sim.plan
         coefs, ic, lc = tables if tables is not None else self.tables(cosmo)
         n = len(coefs)
@@ -159,10 +166,17 @@ class LightCone:
         if init_ahead:
             plan.kick(p, self.a[0], -coefs[n - 1][2], out=self.p_int)    # p_{n-1/2}
             ahead(n, self.p_int)
+        x1b = sim.xi
+        if truncate:
+            self.c.zero_()
+            x1b = self.c      # added after pm_adj_init's VJP, which freezes the observed
         if cnt[n] > 0:
             plan.lightcone_vjp(self._step(lc, cosmo, n), self.x_tmp, self.p_tmp, s, p, self.obs_step, obs_bar,
-                               self.xb[1], self.pb[1], sim.xi, sim.pi, thb)
+                               self.xb[1], self.pb[1], x1b, sim.pi, thb)
         plan.adj_init(st, adj, coefs[n - 1], om, thb)
+        if truncate and first <= n:
+            plan.lightcone_truncate(sim.xi, self.obs_step, n)
+            plan.adj_bump(sim.xi, None, self.c, None, None, 0.0, 0.0, None, None, thb)
         self._swap()
         if init_ahead:
             self.a.reverse()
@@ -173,6 +187,9 @@ class LightCone:
                 break
             plan.step_adj(st, adj, coefs[i - 1], coefs[i - 2] if i > 1 else None, om, thb)
             k = i - 1
+            frozen = truncate and k >= first     # particles observed in steps 1..k
+            if frozen:
+                plan.lightcone_truncate(sim.xi, self.obs_step, k)
             if k == 0:
                 if cnt[1] > 0:
                     plan.adj_bump(sim.xi, sim.pi, self.xb[0], self.pb[0], None, 0.0, 0.0, None, None, thb)
@@ -188,6 +205,8 @@ class LightCone:
             if need(k):
                 self.cb.zero_()
                 plan.force_vjp(s, self.pb[0], om, want_acc=False, out=self.c, omega_m_bar=self.cb)
+                if frozen:
+                    plan.lightcone_truncate(self.c, self.obs_step, k)
                 Kb, dKb = coefs[k - 1][2], coefs[k - 1][5]
                 plan.adj_bump(sim.xi, sim.pi, self.xb[0], self.pb[0], self.c, Kb, dKb, self.a[0], self.cb, thb)
                 self._swap()

@@ -220,7 +220,7 @@ def _lightcone_setup(n=8, nm=16, box=32.0, steps=4, split_step=None):
     return cfg, np.array([nm / 2.0 - chi_k, nm / 2.0, nm / 2.0])
 
 
-def _gpu_run(cfg, X, omega, w, mdt, sdt):
+def _gpu_run(cfg, X, omega, w, mdt, sdt, truncate=False):
     api = _api()
     from paper_2211_09815_amd.lightcone import LightCone
     from paper_2211_09815_amd.simulate import SimConfig, Simulation
@@ -232,7 +232,7 @@ def _gpu_run(cfg, X, omega, w, mdt, sdt):
     counts = lc.forward(om_t, cosmo, tabs)
     obs = host(lc.obs)
     ostep = lc.obs_step.cpu().numpy()
-    g, th = lc.gradient(om_t, cosmo, dev(w, mdt), tabs)
+    g, th = lc.gradient(om_t, cosmo, dev(w, mdt), tabs, truncate=truncate)
     return counts, obs, ostep, host(g), host(th)
 
 
@@ -277,6 +277,63 @@ def test_end_to_end_fp32_mesh_vs_oracle(sdt):
         assert abs(obs_ref[i, 6] - a_b) < 1e-3 * da, (i, obs_ref[i, 6], a_b)
     assert rel_l2(g, g_ref) < 1e-3
     np.testing.assert_allclose(th, th_ref, rtol=1e-3)
+
+
+@pytest.mark.parametrize("n,nm,box,steps,split", [(8, 16, 32.0, 4, None), (16, 16, 64.0, 12, 9)])
+def test_truncated_gradient_fp64_vs_oracle(n, nm, box, steps, split):
+    # the truncated adjoint (Sec. 3.4, reading L7) against the oracle's, and
+    # different from the exact gradient
+    announce("light-cone truncated gradient FP64 %d/%d/%d" % (n, nm, steps))
+    cfg, X = _lightcone_setup(n, nm, box, steps, split)
+    omega = inputs.white_noise(n, 0)
+    w = inputs.normal((cfg.n_particles, 7), inputs.SEED_COTANGENT)
+    _, g_ref, th_ref, _, step_ref = olc.value_and_grad(omega, cfg, X, w, truncate=True)
+    _, _, ostep, g, th = _gpu_run(cfg, X, omega, np.ascontiguousarray(w.T), torch.float64, torch.float64, True)
+    np.testing.assert_array_equal(ostep, step_ref)
+    assert rel_l2(g, g_ref) < 1e-8
+    np.testing.assert_allclose(th, th_ref, rtol=1e-8)
+    _, _, _, g_ex, _ = _gpu_run(cfg, X, omega, np.ascontiguousarray(w.T), torch.float64, torch.float64)
+    assert rel_l2(g, g_ex) > 1e-4
+
+
+@pytest.mark.parametrize("sdt", [torch.float64, torch.float32])
+def test_truncated_gradient_fp32_mesh_vs_oracle(sdt):
+    announce("light-cone truncated gradient FP32 mesh, %s state" % sdt)
+    cfg, X = _lightcone_setup(16, 16, 64.0, 12, 9)
+    omega = inputs.white_noise(16, 0)
+    w = inputs.normal((cfg.n_particles, 7), inputs.SEED_COTANGENT).astype(np.float32).astype(np.float64)
+    _, g_ref, th_ref, _, step_ref = olc.value_and_grad(omega, cfg, X, w, truncate=True)
+    _, _, ostep, g, th = _gpu_run(cfg, X, omega.astype(np.float32), np.ascontiguousarray(w.T), torch.float32, sdt,
+                                  True)
+    assert (ostep == step_ref).mean() > 0.999
+    assert rel_l2(g, g_ref) < 1e-3
+    np.testing.assert_allclose(th, th_ref, rtol=1e-3)
+
+
+@pytest.mark.parametrize("mdt", [torch.float64, torch.float32])
+def test_truncate_and_bump_without_p_bar(mdt):
+    api = _api()
+    announce("light-cone truncate, bump without p_bar %s" % mdt)
+    plan = api.Plan(16, 8, mesh_dtype=mdt, state_dtype=torch.float64)
+    N = plan.n_particles
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal((3, N))
+    ostep = rng.integers(0, 6, N).astype(np.int32)
+    tx = dev(x, mdt)
+    ts = torch.as_tensor(ostep, device="cuda")
+    plan.lightcone_truncate(tx, ts, 3)
+    want = np.where(((ostep > 0) & (ostep <= 3))[None, :], 0.0, host(dev(x, mdt)))
+    np.testing.assert_array_equal(host(tx), want)
+    plan.lightcone_truncate(tx, ts, 0)                     # last < 1: nothing
+    np.testing.assert_array_equal(host(tx), want)
+    xi, xb, c, pi = (dev(rng.standard_normal((3, N)), mdt) for _ in range(4))
+    xi0, pi0 = host(xi), host(pi)
+    thb = torch.tensor([1.0, 2.0], dtype=torch.float64, device="cuda")
+    plan.adj_bump(xi, None, xb, None, c, 0.25, 0.5, None, None, thb)
+    tol = 1e-15 if mdt == torch.float64 else 3e-7
+    assert rel_l2(host(xi), xi0 + host(xb) + 0.25 * host(c)) < tol
+    np.testing.assert_array_equal(host(pi), pi0)
+    assert host(thb).tolist() == [1.0, 2.0]
 
 
 def test_lightcone_reach_vs_numpy():
