@@ -141,9 +141,11 @@ def test_force_vs_oracle(mesh, ptcl, scale, mdt, sdt):
     assert np.abs(a.sum(0)).max() < (1e-4 if mdt == torch.float32 else 1e-10) * np.abs(a).sum()
 
 
-@pytest.mark.parametrize("mesh,ptcl,scale", FORCE_CASES[:3])
+@pytest.mark.parametrize("mesh,ptcl,scale", FORCE_CASES)
 @pytest.mark.parametrize("mdt", [torch.float32, torch.float64])
 def test_force_vjp_vs_oracle(mesh, ptcl, scale, mdt):
+    # the non-cubic mesh keeps k_y (lines of n1) and k_z (n2) of the shared
+    # gradient factor apart
     announce("force_vjp mesh=%s ptcl=%s %s" % (mesh, ptcl, mdt))
     plan = _plan(mesh, ptcl, mdt, torch.float64)
     r = [mesh[a] / ptcl[a] for a in range(3)]
