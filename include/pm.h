@@ -276,7 +276,7 @@ int pm_run_fwd_ckpt(pm_plan plan, pm_state* st, const pm_step_coef* coefs, int n
  * drift on the stored s_j (the force and its VJP are evaluated there; the
  * theta term (xi . p) dD and pi += xi D are unchanged) and ends with p set to
  * the stored p_{j-1/2}; a checkpoint at n sets p_{n-1/2} after pm_adj_init.
- * xi and pi are integrated as in pm_run_adj.  With a checkpoint at every step
+ * xi and pi are integrated, and pi held, as in pm_run_adj.  With a checkpoint at every step
  * the adjoint runs on the forward trajectory itself.  Errors: PM_EINVAL for
  * unordered or out-of-range steps or NULL buffers (before any launch). */
 int pm_run_adj_ckpt(pm_plan plan, pm_state* st, pm_adj* adj, const pm_step_coef* coefs, int n,
