@@ -99,6 +99,15 @@ typedef struct {
                             /* two cube in 4..1024 and box a positive cube),   */
                             /* so pm_lpt and pm_lpt_vjp allocate nothing; 0:   */
                             /* the first of those calls allocates it           */
+    int32_t lpt_keep;       /* 1: pm_lpt keeps the second-order fields it      */
+                            /* forms (the Hessian of the first-order potential */
+                            /* and the second-order displacement) in the 2LPT  */
+                            /* scratch, and the next pm_lpt_vjp uses them when */
+                            /* it gets the same omega pointer and bytewise the */
+                            /* same cosmology and coefficients, instead of     */
+                            /* forming them again; the caller must not change  */
+                            /* omega's contents in between.  Any pm_lpt_vjp    */
+                            /* consumes them.  0: pm_lpt_vjp always forms them */
 } pm_config;
 
 /* Creates a plan on the current HIP device and allocates its scratch.

@@ -57,7 +57,7 @@ c_sz = ctypes.c_size_t
 class PmConfig(ctypes.Structure):
     _fields_ = [("mesh", c_i32 * 3), ("ptcl", c_i32 * 3), ("box", c_dbl * 3),
                 ("lattice_offset", c_dbl), ("mesh_dtype", c_i32), ("state_dtype", c_i32),
-                ("deterministic", c_i32), ("lpt_scratch", c_i32)]
+                ("deterministic", c_i32), ("lpt_scratch", c_i32), ("lpt_keep", c_i32)]
 
 
 class PmStepCoef(ctypes.Structure):

@@ -94,10 +94,12 @@ class Plan:
     deterministic=True (default): the fixed-point paint, bitwise
     reproducible; False: floating-point LDS atomics (see pm_config).
     lpt_scratch (default: whenever the lattice and box allow 2LPT): the plan
-    allocates the 2LPT lattice scratch up front, so no later call allocates."""
+    allocates the 2LPT lattice scratch up front, so no later call allocates.
+    lpt_keep (default True): pm_lpt keeps its second-order fields for the
+    next pm_lpt_vjp of the same omega tensor and cosmology (pm_config)."""
 
     def __init__(self, mesh, ptcl, box=(1.0, 1.0, 1.0), lattice_offset=0.0, mesh_dtype=torch.float32,
-                 state_dtype=torch.float64, deterministic=True, lpt_scratch=None):
+                 state_dtype=torch.float64, deterministic=True, lpt_scratch=None, lpt_keep=True):
         mesh = tuple(int(m) for m in (mesh if np.iterable(mesh) else (mesh,) * 3))
         ptcl = tuple(int(m) for m in (ptcl if np.iterable(ptcl) else (ptcl,) * 3))
         box = tuple(float(b) for b in (box if np.iterable(box) else (box,) * 3))
@@ -107,7 +109,7 @@ class Plan:
                            and box == (box[0],) * 3)
         self.cfg = PmConfig((ctypes.c_int32 * 3)(*mesh), (ctypes.c_int32 * 3)(*ptcl), (ctypes.c_double * 3)(*box),
                             float(lattice_offset), _code(mesh_dtype), _code(state_dtype), int(bool(deterministic)),
-                            int(bool(lpt_scratch)))
+                            int(bool(lpt_scratch)), int(bool(lpt_keep)))
         self.mesh = mesh
         self.ptcl = ptcl
         self.box = box

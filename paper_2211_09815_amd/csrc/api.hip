@@ -70,6 +70,7 @@ int validate_cfg(const pm_config* c, std::string& why) {
   }
   if (c->deterministic != 0 && c->deterministic != 1) { why = "deterministic must be 0 or 1"; return PM_EINVAL; }
   if (c->lpt_scratch != 0 && c->lpt_scratch != 1) { why = "lpt_scratch must be 0 or 1"; return PM_EINVAL; }
+  if (c->lpt_keep != 0 && c->lpt_keep != 1) { why = "lpt_keep must be 0 or 1"; return PM_EINVAL; }
   if (c->lpt_scratch) {
     const int n = c->ptcl[0];
     if (c->ptcl[1] != n || c->ptcl[2] != n || !pow2_in(n, 4, 1024)) {

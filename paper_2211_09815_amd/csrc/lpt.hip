@@ -17,6 +17,7 @@
 //   (1/N) sum_k w_k Re[ dA/dOmega_m(k) W(k) conj(G(k)) ],  G = rfft(delta1bar),
 // with w_k = 1 on the kz = 0 and kz = N/2 planes and 2 elsewhere.
 #include <cmath>
+#include <cstring>
 
 #include "cosmo_eh.h"
 #include "tiles.h"
@@ -304,9 +305,11 @@ int mul(Plan* p, const Lat<T>& L, const Cx<T>* in, Cx<T>* out, int kind, bool am
 
 // forward fields: s1 -> real 0..2, H -> real 3..8, s2 -> real 10..12;
 // W = rfft(omega) stays in spec 0, delta1(k) = A(k) W(k) is formed once in
-// spec 2 (overwritten by the second-order step)
+// spec 2 (overwritten by the second-order step).  The first-order part (W,
+// s1) alone when second_order is false.
 template <typename T>
-int forward_fields(Plan* p, const Lat<T>& L, const T* omega, const AmpP& ap, hipStream_t st) {
+int forward_fields(Plan* p, const Lat<T>& L, const T* omega, const AmpP& ap, hipStream_t st,
+                   bool second_order = true) {
   const FftShape fs{L.n, L.n, L.n};
   const T scale = T(2.0 / double(L.N));
   int rc = fft_r2c_3d<T>(p, fs, omega, L.spec(p, 0), 1, L.N, L.ns, st);
@@ -316,6 +319,7 @@ int forward_fields(Plan* p, const Lat<T>& L, const T* omega, const AmpP& ap, hip
     if ((rc = mul<T>(p, L, L.spec(p, 2), L.spec(p, 1), MUL_D1 + j, false, false, false, ap, st))) return rc;
     if ((rc = fft_c2r_3d<T>(p, fs, L.spec(p, 1), L.real(p, j), 1, L.ns, L.N, scale, st))) return rc;
   }
+  if (!second_order) return PM_OK;
   for (int q = 0; q < 6; ++q) {
     if ((rc = mul<T>(p, L, L.spec(p, 2), L.spec(p, 1), MUL_D2 + q, false, false, false, ap, st))) return rc;
     if ((rc = fft_c2r_3d<T>(p, fs, L.spec(p, 1), L.real(p, 3 + q), 1, L.ns, L.N, scale, st))) return rc;
@@ -346,15 +350,18 @@ int lpt_fwd_typed(Plan* p, const void* omega, const pm_cosmo* c, const pm_ic_coe
   return PM_OK;
 }
 
+// kept: H and s2 of the same omega and cosmology are still in the lattice
+// scratch (cfg.lpt_keep); only W and s1, which share the plan's meshes and
+// spectra, are formed again
 template <typename T>
 int lpt_bwd_typed(Plan* p, const void* omega, const pm_cosmo* c, const pm_ic_coef* ic, const pm_adj* adj,
-                  void* omega_bar, double* theta_bar, hipStream_t st) {
+                  void* omega_bar, double* theta_bar, bool kept, hipStream_t st) {
   Lat<T> L{p->np[0], int64_t(p->np[0]) * p->np[0] * p->np[0], int64_t(p->np[0]) * p->np[0] * (p->np[0] / 2 + 1)};
   const AmpP ap = amp_params(p, c, ic);
   const FftShape fs{L.n, L.n, L.n};
   const T scale = T(2.0 / double(L.N));
   const double r = p->r[0];
-  int rc = forward_fields<T>(p, L, static_cast<const T*>(omega), ap, st);
+  int rc = forward_fields<T>(p, L, static_cast<const T*>(omega), ap, st, !kept);
   if (rc) return rc;
   // lattice fields: s1 0..2, H 3..8, S 9, s2 10..12; after k_bars s1bar is
   // in 13..15 and s2bar replaces s2 in 10..12.
@@ -407,21 +414,34 @@ int lpt_bwd_typed(Plan* p, const void* omega, const pm_cosmo* c, const pm_ic_coe
 }  // namespace
 
 int lpt_forward(Plan* p, const void* omega, const pm_cosmo* c, const pm_ic_coef* ic, pm_state* st, hipStream_t s) {
+  p->lpt_kept = false;
   int rc = check_lattice(p);
   if (rc) return rc;
   if ((rc = ensure_lattice(p))) return rc;
-  if (p->cfg.mesh_dtype == PM_F64) return lpt_fwd_typed<double, double>(p, omega, c, ic, st, s);
-  if (p->cfg.state_dtype == PM_F64) return lpt_fwd_typed<double, float>(p, omega, c, ic, st, s);
-  return lpt_fwd_typed<float, float>(p, omega, c, ic, st, s);
+  if (p->cfg.mesh_dtype == PM_F64) rc = lpt_fwd_typed<double, double>(p, omega, c, ic, st, s);
+  else if (p->cfg.state_dtype == PM_F64) rc = lpt_fwd_typed<double, float>(p, omega, c, ic, st, s);
+  else rc = lpt_fwd_typed<float, float>(p, omega, c, ic, st, s);
+  if (rc == PM_OK && p->cfg.lpt_keep) {
+    p->lpt_kept = true;
+    p->lpt_omega = omega;
+    p->lpt_cosmo = *c;
+    p->lpt_ic = *ic;
+  }
+  return rc;
 }
 
 int lpt_backward(Plan* p, const void* omega, const pm_cosmo* c, const pm_ic_coef* ic, const pm_adj* adj,
                  void* omega_bar, double* theta_bar, hipStream_t s) {
+  // the fields pm_lpt kept serve this omega and cosmology only, and this
+  // call overwrites them either way
+  const bool kept = p->lpt_kept && omega == p->lpt_omega && std::memcmp(c, &p->lpt_cosmo, sizeof(pm_cosmo)) == 0 &&
+                    std::memcmp(ic, &p->lpt_ic, sizeof(pm_ic_coef)) == 0;
+  p->lpt_kept = false;
   int rc = check_lattice(p);
   if (rc) return rc;
   if ((rc = ensure_lattice(p))) return rc;
-  if (p->cfg.mesh_dtype == PM_F64) return lpt_bwd_typed<double>(p, omega, c, ic, adj, omega_bar, theta_bar, s);
-  return lpt_bwd_typed<float>(p, omega, c, ic, adj, omega_bar, theta_bar, s);
+  if (p->cfg.mesh_dtype == PM_F64) return lpt_bwd_typed<double>(p, omega, c, ic, adj, omega_bar, theta_bar, kept, s);
+  return lpt_bwd_typed<float>(p, omega, c, ic, adj, omega_bar, theta_bar, kept, s);
 }
 
 }  // namespace pmx

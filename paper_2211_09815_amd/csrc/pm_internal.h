@@ -98,6 +98,12 @@ struct Plan {
   void* lreal[10] = {};
   void* lspec[2] = {};
   bool lpt_ready = false;
+  // the second-order fields of the last pm_lpt, kept for the next pm_lpt_vjp
+  // of the same omega and cosmology (cfg.lpt_keep)
+  bool lpt_kept = false;
+  const void* lpt_omega = nullptr;
+  pm_cosmo lpt_cosmo{};
+  pm_ic_coef lpt_ic{};
   Timing timing;
   std::string err;
 };

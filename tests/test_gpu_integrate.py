@@ -164,6 +164,56 @@ def test_lpt_vjp_vs_oracle(n, nm, mdt, tol):
     assert th[1] == pytest.approx(np.sum(xb * ds8) + np.sum(pb * dp8), rel=10 * tol)
 
 
+@pytest.mark.parametrize("n,nm", [(16, 32), (16, 16)])
+@pytest.mark.parametrize("mdt", [torch.float64, torch.float32])
+def test_lpt_vjp_with_kept_fields_is_the_full_one(n, nm, mdt):
+    # pm_config.lpt_keep: after pm_lpt of the same omega and cosmology the VJP
+    # forms only the first-order fields again (fewer inverse transforms) and
+    # gives bitwise the same result; another omega buffer, another cosmology
+    # or a second VJP form everything again
+    from paper_2211_09815_amd._lib import PM_K_FFT_C2R_Z
+    announce("lpt_vjp with kept fields %d^3/%d^3 %s" % (n, nm, mdt))
+    api, cfg, omega, plan = _setup(n, nm, 4.0 * n, 1, mdt=mdt)
+    assert plan.cfg.lpt_keep == 1
+    cos = api.Cosmology()
+    _, ic = api.tables(cos, cfg.a_grid())
+    adj = {"xi": dev(soa(inputs.normal((cfg.n_particles, 3), 62)), mdt),
+           "pi": dev(soa(inputs.normal((cfg.n_particles, 3), 63)), mdt)}
+    om = dev(omega, mdt)
+    st = plan.new_state(torch.empty((3, cfg.n_particles), dtype=torch.float64, device="cuda"),
+                        torch.empty((3, cfg.n_particles), dtype=torch.float64, device="cuda"))
+
+    def vjp(o, c, i):
+        tb = torch.zeros(2, dtype=torch.float64, device="cuda")
+        plan.timing_enable([PM_K_FFT_C2R_Z])
+        g = host(plan.lpt_vjp(o, c, i, adj, tb))
+        launches = plan.timing_read(PM_K_FFT_C2R_Z)[1]
+        plan.timing_enable(())
+        return g, host(tb), launches
+
+    g0, t0, full = vjp(om, cos, ic)                      # nothing kept yet
+    plan.lpt(om, cos, ic, st)
+    g1, t1, kept = vjp(om, cos, ic)
+    assert kept < full
+    np.testing.assert_array_equal(g1, g0)
+    np.testing.assert_array_equal(t1, t0)
+    g2, t2, again = vjp(om, cos, ic)                     # consumed
+    assert again == full
+    np.testing.assert_array_equal(g2, g0)
+    plan.lpt(om, cos, ic, st)
+    g3, _, n3 = vjp(om.clone(), cos, ic)                 # another buffer
+    assert n3 == full
+    np.testing.assert_array_equal(g3, g0)
+    cos2 = api.Cosmology(sigma8=0.75)
+    _, ic2 = api.tables(cos2, cfg.a_grid())
+    g4, t4, _ = vjp(om, cos2, ic2)
+    plan.lpt(om, cos, ic, st)
+    g5, t5, n5 = vjp(om, cos2, ic2)                      # another cosmology
+    assert n5 == full
+    np.testing.assert_array_equal(g5, g4)
+    np.testing.assert_array_equal(t5, t4)
+
+
 def _e2e(n, nm, box, steps, a0, mdt, sdt):
     from paper_2211_09815_amd.simulate import SimConfig, Simulation
     api = _api()

@@ -72,9 +72,9 @@ def test_plan_create_rejects_bad_configs_without_launching():
     L = _lib()
     lib = L.lib()
 
-    def cfg(mesh=(8, 8, 8), ptcl=(4, 4, 4), mdt=0, sdt=1, det=0, lpt=0, box=(1, 1, 1)):
+    def cfg(mesh=(8, 8, 8), ptcl=(4, 4, 4), mdt=0, sdt=1, det=0, lpt=0, box=(1, 1, 1), keep=0):
         return L.PmConfig((ctypes.c_int32 * 3)(*mesh), (ctypes.c_int32 * 3)(*ptcl), (ctypes.c_double * 3)(*box),
-                          0.0, mdt, sdt, det, lpt)
+                          0.0, mdt, sdt, det, lpt, keep)
     h = ctypes.c_void_p()
     assert lib.pm_plan_create(ctypes.byref(cfg(mesh=(8, 12, 8))), ctypes.byref(h)) == L.PM_ESHAPE
     assert b"power" in lib.pm_last_error(None)
@@ -88,6 +88,8 @@ def test_plan_create_rejects_bad_configs_without_launching():
     assert lib.pm_plan_create(ctypes.byref(cfg(lpt=1, ptcl=(4, 4, 8))), ctypes.byref(h)) == L.PM_ESHAPE
     assert lib.pm_plan_create(ctypes.byref(cfg(lpt=1, ptcl=(6, 6, 6))), ctypes.byref(h)) == L.PM_ESHAPE
     assert lib.pm_plan_create(ctypes.byref(cfg(lpt=1, box=(1, 2, 1))), ctypes.byref(h)) == L.PM_EINVAL
+    assert lib.pm_plan_create(ctypes.byref(cfg(keep=3)), ctypes.byref(h)) == L.PM_EINVAL
+    assert b"lpt_keep" in lib.pm_last_error(None)
     assert lib.pm_workspace_bytes(ctypes.byref(cfg(mesh=(8, 12, 8)))) == 0
     ws = lib.pm_workspace_bytes(ctypes.byref(cfg()))
     # 4 real meshes + 4 half spectra (FP32) + twiddles + reduction scratch
