@@ -365,7 +365,9 @@ int pm_lpt(pm_plan plan, const void* omega, const pm_cosmo* cosmo, const pm_ic_c
 /* Transpose of pm_lpt: omega_bar = d<xi0, s_0> + <pi0, p_0> / d omega
  * ([N_p] mesh dtype, overwritten); theta_bar[0] += the Omega_m derivative
  * through P(k) and the time factors, theta_bar[1] += the sigma8 derivative.
- * xi0, pi0: adj->xi, adj->pi. */
+ * xi0, pi0: adj->xi, adj->pi.  It forms the forward fields again, or, with
+ * cfg.lpt_keep after a pm_lpt of the same omega pointer, cosmology and
+ * coefficients, only the first-order ones (bitwise the same result). */
 int pm_lpt_vjp(pm_plan plan, const void* omega, const pm_cosmo* cosmo,
                const pm_ic_coef* ic, const pm_adj* adj, void* omega_bar,
                double* theta_bar, hipStream_t stream);
