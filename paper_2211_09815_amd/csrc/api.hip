@@ -318,14 +318,15 @@ size_t pm_workspace_bytes(const pm_config* cfg) {
   size_t total = sizes_of(cfg).total();
   // 2LPT lattice scratch (16 real fields, 3 half spectra; 12 real fields when
   // the lattice has the mesh's shape and shares the plan's meshes and
-  // spectra), allocated by the first pm_lpt / pm_lpt_vjp call on a cubic
-  // lattice
+  // spectra) and the amplitude table (two doubles per |f|^2 <= 3 (n/2)^2),
+  // allocated by the first pm_lpt / pm_lpt_vjp call on a cubic lattice
   const int64_t n = cfg->ptcl[0];
   if (cfg->ptcl[1] == n && cfg->ptcl[2] == n) {
     const size_t rb = cfg->mesh_dtype == PM_F64 ? 8 : 4;
     const bool shared = cfg->mesh[0] == n && cfg->mesh[1] == n && cfg->mesh[2] == n;
     total += shared ? size_t(12) * n * n * n * rb
                     : size_t(16) * n * n * n * rb + size_t(3) * n * n * (n / 2 + 1) * 2 * rb;
+    total += size_t(3 * (n / 2) * (n / 2) + 1) * 2 * sizeof(double);
   }
   return total;
 }
@@ -468,6 +469,7 @@ int pm_plan_destroy(pm_plan h) {
   (void)hipFree(p->kick_al);
   for (void* q : p->lreal) if (q) (void)hipFree(q);
   for (void* q : p->lspec) if (q) (void)hipFree(q);
+  (void)hipFree(p->amp_tab);
   for (auto& f : p->timing.fam)
     for (auto& e : f.ev)
       if (e) (void)hipEventDestroy(e);

@@ -31,6 +31,7 @@ struct AmpP {
   double A, dA;      // P = A k^ns T^2 and dA/dOmega_m
   double box;        // Mpc/h
   int n;
+  const double* tab; // A(k), dA/dOmega_m per m = |f|^2 (k_amp_table)
 };
 
 enum MulKind {
@@ -49,21 +50,36 @@ __device__ __forceinline__ void decode(int idx, int logn, int nh, double inv_nh,
   x = row >> logn;
 }
 
+// A(k) depends on |k| only, and |k|^2 = (2 pi / n)^2 m with the integer
+// m = fx^2 + fy^2 + fz^2 of the lattice mode (m <= 3 (n/2)^2).  The transfer
+// function and its Omega_m derivative are evaluated once per m, not once per
+// mode: one thread per table entry.
+__global__ __launch_bounds__(kThreads) void k_amp_table(AmpP ap, double* __restrict__ tab, int mmax) {
+  const int m = int(blockIdx.x) * kThreads + int(threadIdx.x);
+  if (m > mmax) return;
+  double A = 0.0, dA = 0.0;
+  if (m > 0) {
+    const int n = ap.n;
+    const double dk = 6.283185307179586476925286766559 / n;
+    const double kph = ::sqrt(double(m)) * dk * n / ap.box;
+    const Dual T = eh_nowiggle<Dual>(kph, Dual{ap.om, 1.0}, ap.ob, ap.h, ap.tcmb);
+    const double cell = ap.box / n;
+    const double base = ::sqrt(ap.A * ::pow(kph, ap.ns) / (cell * cell * cell));
+    A = T.v * base;
+    dA = A * (0.5 * ap.dA / ap.A + T.d / T.v);
+  }
+  tab[2 * m] = A;
+  tab[2 * m + 1] = dA;
+}
+
 // amplitude A(k) and its Omega_m derivative at lattice mode (x, y, z)
-__device__ void amp_at(const AmpP& ap, int x, int y, int z, double& A, double& dA) {
+__device__ __forceinline__ void amp_at(const AmpP& ap, int x, int y, int z, double& A, double& dA) {
   const int n = ap.n;
-  const double tp = 6.283185307179586476925286766559;
   const int fx = x < n / 2 ? x : x - n;
   const int fy = y < n / 2 ? y : y - n;
-  const double kx = tp * fx / n, ky = tp * fy / n, kz = tp * z / n;
-  const double k2 = kx * kx + ky * ky + kz * kz;
-  if (k2 == 0.0) { A = 0.0; dA = 0.0; return; }
-  const double kph = ::sqrt(k2) * n / ap.box;
-  const Dual T = eh_nowiggle<Dual>(kph, Dual{ap.om, 1.0}, ap.ob, ap.h, ap.tcmb);
-  const double cell = ap.box / n;
-  const double base = ::sqrt(ap.A * ::pow(kph, ap.ns) / (cell * cell * cell));
-  A = T.v * base;
-  dA = A * (0.5 * ap.dA / ap.A + T.d / T.v);
+  const int m = fx * fx + fy * fy + z * z;
+  A = ap.tab[2 * m];
+  dA = ap.tab[2 * m + 1];
 }
 
 // out = [out +] M(k) [A(k)] in, M conj'ed if CONJ; one thread per mode of
@@ -214,6 +230,9 @@ __global__ __launch_bounds__(kThreads) void k_theta_amp(const Cx<T>* __restrict_
   if (threadIdx.x == 0) partials[blockIdx.x * 4 + 0] = t;
 }
 
+// largest |f|^2 of a mode of the n^3 lattice's half spectrum
+int amp_mmax(int n) { return 3 * (n / 2) * (n / 2); }
+
 int grid_for(int64_t work) {
   const int64_t need = (work + kThreads - 1) / kThreads;
   return int(need < 2048 ? (need < 1 ? 1 : need) : 2048);
@@ -255,6 +274,14 @@ int ensure_lattice(Plan* p) {
     p->lreal[0] = nullptr;
     return set_error(p, PM_ENOMEM, "could not allocate 2LPT lattice spectra");
   }
+  if (hipMalloc(&p->amp_tab, size_t(amp_mmax(int(n)) + 1) * 2 * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(p->lreal[0]);
+    (void)hipFree(p->lspec[0]);
+    p->lreal[0] = p->lspec[0] = nullptr;
+    p->amp_tab = nullptr;
+    return set_error(p, PM_ENOMEM, "could not allocate the 2LPT amplitude table");
+  }
   p->lpt_ready = true;
   return PM_OK;
 }
@@ -279,8 +306,9 @@ struct Lat {
   }
 };
 
-AmpP amp_params(const Plan* p, const pm_cosmo* c, const pm_ic_coef* ic) {
-  AmpP ap;
+// the amplitude parameters of this call, and its table of A(k) and
+// dA/dOmega_m formed on the stream
+int amp_params(Plan* p, const pm_cosmo* c, const pm_ic_coef* ic, hipStream_t st, AmpP& ap) {
   ap.om = c->omega_m;
   ap.ob = c->omega_b;
   ap.h = c->h;
@@ -290,7 +318,11 @@ AmpP amp_params(const Plan* p, const pm_cosmo* c, const pm_ic_coef* ic) {
   ap.dA = ic->dA;
   ap.box = p->cfg.box[0];
   ap.n = p->np[0];
-  return ap;
+  ap.tab = p->amp_tab;
+  const int mmax = amp_mmax(ap.n);
+  hipLaunchKernelGGL(k_amp_table, dim3(unsigned(mmax / kThreads + 1)), dim3(kThreads), 0, st, ap, p->amp_tab, mmax);
+  PM_HIP_CHECK(p, hipGetLastError());
+  return PM_OK;
 }
 
 template <typename T>
@@ -339,9 +371,10 @@ template <typename S, typename T>
 int lpt_fwd_typed(Plan* p, const void* omega, const pm_cosmo* c, const pm_ic_coef* ic, pm_state* stt,
                   hipStream_t st) {
   Lat<T> L{p->np[0], int64_t(p->np[0]) * p->np[0] * p->np[0], int64_t(p->np[0]) * p->np[0] * (p->np[0] / 2 + 1)};
-  const AmpP ap = amp_params(p, c, ic);
-  int rc = forward_fields<T>(p, L, static_cast<const T*>(omega), ap, st);
+  AmpP ap;
+  int rc = amp_params(p, c, ic, st, ap);
   if (rc) return rc;
+  if ((rc = forward_fields<T>(p, L, static_cast<const T*>(omega), ap, st))) return rc;
   const double r = p->r[0];
   hipLaunchKernelGGL((k_combine<S, T>), dim3(grid_for(3 * L.N)), dim3(kThreads), 0, st, L.real(p, 0),
                      L.real(p, 10), static_cast<S*>(stt->s), static_cast<S*>(stt->p), L.N, r, ic->D1, ic->D2, ic->P1,
@@ -357,12 +390,13 @@ template <typename T>
 int lpt_bwd_typed(Plan* p, const void* omega, const pm_cosmo* c, const pm_ic_coef* ic, const pm_adj* adj,
                   void* omega_bar, double* theta_bar, bool kept, hipStream_t st) {
   Lat<T> L{p->np[0], int64_t(p->np[0]) * p->np[0] * p->np[0], int64_t(p->np[0]) * p->np[0] * (p->np[0] / 2 + 1)};
-  const AmpP ap = amp_params(p, c, ic);
+  AmpP ap;
+  int rc = amp_params(p, c, ic, st, ap);
+  if (rc) return rc;
   const FftShape fs{L.n, L.n, L.n};
   const T scale = T(2.0 / double(L.N));
   const double r = p->r[0];
-  int rc = forward_fields<T>(p, L, static_cast<const T*>(omega), ap, st, !kept);
-  if (rc) return rc;
+  if ((rc = forward_fields<T>(p, L, static_cast<const T*>(omega), ap, st, !kept))) return rc;
   // lattice fields: s1 0..2, H 3..8, S 9, s2 10..12; after k_bars s1bar is
   // in 13..15 and s2bar replaces s2 in 10..12.
   {

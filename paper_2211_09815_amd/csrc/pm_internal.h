@@ -97,6 +97,7 @@ struct Plan {
   // lattice scratch for pm_lpt / pm_lpt_vjp (allocated lazily on first use)
   void* lreal[10] = {};
   void* lspec[2] = {};
+  double* amp_tab = nullptr;   // [3 (np/2)^2 + 1][2] A(k), dA/dOmega_m per integer |f|^2
   bool lpt_ready = false;
   // the second-order fields of the last pm_lpt, kept for the next pm_lpt_vjp
   // of the same omega and cosmology (cfg.lpt_keep)
