@@ -586,23 +586,35 @@ __global__ __launch_bounds__(kPaintThreads) void k_paint_tiles(TileGeo g, const 
 // core cells on the lower faces of each tile gather the halo faces of the
 // lower neighbours d in {0,1}^3 \ {0} (wrapped), for every channel.  DEFER:
 // the z face of the tile below (d = (0,0,1), the only contribution to the
-// bottom-plane cells off the x and y faces) is left to the next R2C
+// bottom-plane cells off the x and y faces) is left to the next R2C.  One
+// workgroup takes 2^lpz tiles adjacent in z, so that the rows of their lower
+// x and y faces, 16 cells each, join into whole 128-byte lines.
 template <typename T, int NCH, bool DEFER>
-__global__ __launch_bounds__(kThreads) void k_halo_add(TileGeo g, T* __restrict__ mesh, const T* __restrict__ halo) {
-  const int64_t tile = xcd_tile(blockIdx.x, int64_t(gridDim.x));
-  const int t2 = int(tile % g.ntz);
-  const int64_t t01 = tile / g.ntz;
+__global__ __launch_bounds__(kThreads) void k_halo_add(TileGeo g, T* __restrict__ mesh, const T* __restrict__ halo,
+                                                       int lpz) {
+  const int64_t grp = xcd_tile(blockIdx.x, int64_t(gridDim.x));
+  const int ngz = g.ntz >> lpz;
+  const int t2g = int(grp % ngz);
+  const int64_t t01 = grp / ngz;
   const int t1 = int(t01 % g.nty);
   const int t0 = int(t01 / g.nty);
   const int ez = g.tz + 1, ey = g.ty + 1;
   const int fx = ey * ez, fy = g.tx * ez;
-  const int nA = g.ty * g.tz, nB = (g.tx - 1) * g.tz, nC = (g.tx - 1) * (g.ty - 1);
-  const int nb = nA + nB + (DEFER ? 0 : nC);
+  const int lw = g.ltz + lpz;   // log2 of a face row across the group
+  const int nA = g.ty << lw, nB = (g.tx - 1) << lw, nC = (g.tx - 1) * (g.ty - 1);
+  const int nb = nA + nB + (DEFER ? 0 : nC << lpz);
   for (int i = threadIdx.x; i < nb; i += kThreads) {
-    int lx, ly, lz;
-    if (i < nA) { lx = 0; ly = i / g.tz; lz = i % g.tz; }
-    else if (i < nA + nB) { const int k = i - nA; lx = 1 + k / g.tz; ly = 0; lz = k % g.tz; }
-    else { const int k = i - nA - nB; lx = 1 + k / (g.ty - 1); ly = 1 + k % (g.ty - 1); lz = 0; }
+    int lx, ly, lzz;
+    if (i < nA) { lx = 0; ly = i >> lw; lzz = i & ((1 << lw) - 1); }
+    else if (i < nA + nB) { const int k = i - nA; lx = 1 + (k >> lw); ly = 0; lzz = k & ((1 << lw) - 1); }
+    else {
+      const int k = i - nA - nB, sub = k / nC, r = k - sub * nC;
+      lx = 1 + r / (g.ty - 1);
+      ly = 1 + r % (g.ty - 1);
+      lzz = sub << g.ltz;
+    }
+    const int t2 = (t2g << lpz) + (lzz >> g.ltz);
+    const int lz = lzz & (g.tz - 1);
     const int64_t cell = (int64_t(t0 * g.tx + lx) * g.n1 + (t1 * g.ty + ly)) * g.n2 + (t2 * g.tz + lz);
     // every load is issued before any is used: the cell's own values, then
     // the halo entry of each neighbour d (a neighbour that does not touch
@@ -755,6 +767,9 @@ int paint_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
   const int nlow = g.ty * g.tz + (g.tx - 1) * g.tz + (in.defer_z ? 0 : (g.tx - 1) * (g.ty - 1));
   const double lower = double(nlow) / (g.tx * g.ty * g.tz);
   const double hadd_bytes = halo_bytes * (in.defer_z ? double(g.hc - zc) / g.hc : 1.0) + 2.0 * lower * core_bytes;
+  // the halo fold takes tiles in pairs along z where their number is even
+  const int lpz = g.ntz % 2 == 0 ? 1 : 0;
+  const dim3 hg(unsigned(g.ntiles >> lpz));
 #define PM_TILES_W(NCH, UNIT, WPM)                                                                         \
   timing_begin(p, PM_K_PAINT_TILES, st);                                                                   \
   if (fixed)                                                                                               \
@@ -765,8 +780,8 @@ int paint_typed(Plan* p, DriftMode mode, const PaintArgs& in, hipStream_t st) {
                        p->bin_offs, p->bin_list, mesh, halo, wglob, static_cast<const float4*>(p->bin_rec)); \
   timing_end(p, PM_K_PAINT_TILES, st, tile_bytes, tile_method);                                            \
   timing_begin(p, PM_K_HALO, st);                                                                          \
-  if (in.defer_z) hipLaunchKernelGGL((k_halo_add<T, NCH, true>), tg, block, 0, st, g, mesh, halo);         \
-  else hipLaunchKernelGGL((k_halo_add<T, NCH, false>), tg, block, 0, st, g, mesh, halo);                   \
+  if (in.defer_z) hipLaunchKernelGGL((k_halo_add<T, NCH, true>), hg, block, 0, st, g, mesh, halo, lpz);   \
+  else hipLaunchKernelGGL((k_halo_add<T, NCH, false>), hg, block, 0, st, g, mesh, halo, lpz);             \
   timing_end(p, PM_K_HALO, st, hadd_bytes, 0.0)
 #define PM_TILES(NCH, UNIT) PM_TILES_W(NCH, UNIT, false)
   if (in.pi_pm) {
